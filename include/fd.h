@@ -1,0 +1,143 @@
+/*
+ * fd.h -- batched forward dynamics of serial articulated chains on MI355X (gfx950).
+ *
+ * Method: Yang, Wu and Pan, "A Novel GPU-based Parallel Implementation Scheme
+ * and Performance Analysis of Robot Forward Dynamics Algorithms" (arXiv
+ * 1609.06779). Joint accelerations qdd are computed from joint torques tau,
+ * positions q and velocities qd (Sec. II-C, eq. (eq-motion), (tau-bias)):
+ *
+ *     qdd = M(q)^-1 (tau - tau_bias(q, qd)),
+ *
+ * by one of three factorisations of M^-1: the joint space inertia inversion
+ * algorithm (JSIIA, Sec. II-C), the articulated-body inertia algorithm (ABIA,
+ * Sec. II-C) or the constraint force algorithm (CFA, Sec. III, Algorithm 1),
+ * built from two solvers: a parallel scan for block bi-diagonal systems
+ * (Sec. II-B) and odd-even elimination for block tri-diagonal systems
+ * (Sec. IV, Algorithm 2). Both solvers are also exported on their own.
+ *
+ * Conventions. A robot is a serial chain of n revolute joints on a fixed base.
+ * Twists are (w; v), wrenches (n; f). Link frame i sits on joint i's axis; its
+ * pose in frame i-1 is T_{i-1,i}(q_i) = (Rhome_i Rot(axis_i, q_i), offset_i).
+ * Gravity acts as a base acceleration (the "const." terms of eq. (EOM-full));
+ * there is no force at the end effector. SI units, angles in radians.
+ *
+ * Layout. Per-link arrays of a batch are packed chain after chain: chain b
+ * owns entries [start_b, start_b + n_b) of q, qd, tau, qdd. start_b is b * n
+ * for batches whose chains all have n links (offsets == NULL), else offsets[b].
+ *
+ * Ownership and threading. The caller owns every state, output and workspace
+ * buffer (device memory) and the stream; calls only enqueue work on that
+ * stream, never allocate and never synchronise it (fd_init and fd_destroy
+ * excepted). Buffers must stay valid until the stream has passed the call.
+ * The model is read-only after fd_init, so calls on different streams may
+ * overlap; a workspace must not be shared by calls that overlap.
+ *
+ * Errors. Argument checks are synchronous and return a status without
+ * enqueueing anything. A launch failure returns FD_ERR_DEVICE. No C++
+ * exception crosses this interface. Non-finite inputs give non-finite outputs.
+ */
+#ifndef FD_H
+#define FD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FD_OK = 0,
+    FD_ERR_INVALID_ARG = -1,   /* a null pointer, size or value out of range, inconsistent batch */
+    FD_ERR_UNSUPPORTED = -2,   /* valid request this build does not handle (chain too long, ...) */
+    FD_ERR_OUT_OF_MEMORY = -3, /* fd_init could not allocate device memory */
+    FD_ERR_DEVICE = -4,        /* a HIP call or kernel launch failed */
+    FD_ERR_WORKSPACE = -5      /* workspace missing or smaller than fd_workspace_size */
+} fd_status_t;
+
+typedef enum { FD_ALGO_ABIA = 0, FD_ALGO_JSIIA = 1, FD_ALGO_CFA = 2, FD_ALGO_AUTO = 3 } fd_algo_t;
+typedef enum { FD_F64 = 0, FD_F32 = 1 } fd_dtype_t;
+
+typedef struct fd_model fd_model_t; /* opaque, device resident, owned by the library */
+
+/* Robot set, host pointers, FP64, copied by fd_init. Links of all robots are
+ * packed robot after robot; robot r has n_links[r] >= 1 links. */
+typedef struct {
+    int32_t num_robots;
+    const int32_t* n_links;  /* [num_robots] */
+    const double* axis;      /* [L][3] joint axis in frame i (non-zero; normalised by fd_init) */
+    const double* home_rot;  /* [L][9] row-major Rhome_i (a rotation), or NULL for identity */
+    const double* offset;    /* [L][3] origin of frame i in frame i-1 */
+    const double* mass;      /* [L] > 0 */
+    const double* com;       /* [L][3] centre of mass in frame i */
+    const double* inertia;   /* [L][6] SPD inertia about the COM, frame-i axes: xx yy zz xy xz yz */
+    double gravity[3];       /* gravitational acceleration in the base frame, e.g. {0, 0, -9.81} */
+} fd_model_desc_t;
+
+/* A batch of chains (device pointers). */
+typedef struct {
+    int32_t batch;             /* number of chains, >= 0 */
+    const int32_t* robot_id;   /* [batch] robot of chain b, or NULL: chain b uses robot b
+                                  (every chain uses robot 0 when the model has one robot) */
+    const int64_t* offsets;    /* [batch + 1] first entry of chain b, or NULL when all chains of
+                                  the batch have the same length (start_b = b * n) */
+} fd_batch_t;
+
+/* Upload a robot set in the given precision (FD_F32 rounds every parameter).
+ * Validates masses, inertias, axes and rotations; FD_ERR_INVALID_ARG if any is
+ * out of range. Synchronous. On success *out owns device memory until fd_destroy. */
+fd_status_t fd_init(const fd_model_desc_t* desc, fd_dtype_t dtype, fd_model_t** out);
+void fd_destroy(fd_model_t* model);
+fd_dtype_t fd_model_dtype(const fd_model_t* model);
+/* Longest chain any algorithm of this build takes for the model's precision (JSIIA may be lower). */
+int32_t fd_max_links(const fd_model_t* model, fd_algo_t algo);
+
+/* Bytes of workspace fd_forward needs for this batch and algorithm (0 if none). */
+fd_status_t fd_workspace_size(const fd_model_t* model, const fd_batch_t* batch, fd_algo_t algo, size_t* bytes);
+
+/* Forward dynamics, eq. (tau-bias): qdd = M(q)^-1 (tau - tau_bias(q, qd)).
+ * q, qd, tau, qdd: device arrays of the model's precision (double or float),
+ * packed per chain. algo FD_ALGO_AUTO picks by chain length. hip_stream: a
+ * hipStream_t (NULL = default stream). Asynchronous. */
+fd_status_t fd_forward(const fd_model_t* model, const fd_batch_t* batch, const void* q, const void* qd,
+                       const void* tau, void* qdd, fd_algo_t algo, void* workspace, size_t ws_bytes,
+                       void* hip_stream);
+
+/* Inverse dynamics, eq. (EOM-full) (CalcInvDyn of Algorithm 1):
+ * tau = M(q) qdd + tau_bias(q, qd), with gravity when `gravity` != 0.
+ * qdd may be NULL (zero: tau is then the bias torque). Asynchronous. */
+fd_status_t fd_inverse(const fd_model_t* model, const fd_batch_t* batch, const void* q, const void* qd,
+                       const void* qdd, int gravity, void* tau, void* hip_stream);
+
+/* Joint-space inertia M(q) = S^T (I - Gamma)^-T J (I - Gamma)^-1 S (Sec. II-C) as
+ * the JSIIA builds it. Uniform batches only (offsets NULL): chain b's n x n
+ * row-major block starts at m_out + b * n * n. Asynchronous. */
+fd_status_t fd_joint_inertia(const fd_model_t* model, const fd_batch_t* batch, const void* q, void* m_out,
+                             void* hip_stream);
+
+/* Segmented scan for block bi-diagonal systems (Sec. II-B):
+ *     x_i = B_i x_{i-1} + c_i within each segment (x before the segment = 0),
+ * or with reverse != 0, x_i = B_i x_{i+1} + c_i. b: [N][6][6] row-major,
+ * c, x: [N][6], device; offsets: device [segments + 1]; every segment at most
+ * 256 long. dtype selects double or float. Asynchronous. */
+fd_status_t fd_scan6(fd_dtype_t dtype, int32_t segments, const int64_t* offsets, int32_t max_len, const void* b,
+                     const void* c, int reverse, void* x, void* hip_stream);
+
+/* Odd-even elimination (Sec. IV, Algorithm 2) for symmetric positive definite
+ * block tri-diagonal systems with 6x6 blocks, eq. (A_mat): system s has rows
+ * offsets[s] .. offsets[s+1]-1 with diagonal blocks d[i] and upper blocks u[i]
+ * coupling rows i and i+1 (u of a system's last row is ignored); solves
+ * A x = r. d, u: [N][6][6] row-major, r, x: [N][6]; at most 256 rows per
+ * system. status (device int, may be NULL) gets bit 0 set when a pivot was
+ * not positive (A not SPD) and bit 1 when a system is longer than max_len (left
+ * untouched). Asynchronous. */
+fd_status_t fd_btd_solve6(fd_dtype_t dtype, int32_t segments, const int64_t* offsets, int32_t max_len,
+                          const void* d, const void* u, const void* r, void* x, int* status, void* hip_stream);
+
+const char* fd_status_string(fd_status_t status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FD_H */

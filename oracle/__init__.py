@@ -102,6 +102,7 @@ def _mstart(model_start):
 
 
 def max_threads() -> int:
+    """Threads the last batch call ran with (all host cores unless a count was given)."""
     return int(_load().oracle_max_threads())
 
 

@@ -292,3 +292,20 @@ def cfa_qdd(ch: Chain, q, tau_delta):
     _, _, _, a, b, c = cfa_matrices(ch, q)
     fc = -np.linalg.solve(a, b @ tau_delta)
     return c @ tau_delta + b.T @ fc
+
+
+def cfa_c_matrix(ch: Chain, q):
+    """C = S^T Phi S (n x n, tri-diagonal) from the blocks of Phi:
+    Phi_ii = J_i^-1 + Ad_i J_{i-1}^-1 Ad_i^T, Phi_{i,i+1} = -J_i^-1 Ad_{i+1}^T.
+    ||C|| ||M|| bounds the cancellation in qdd = (C - B^T A^-1 B) tau_delta."""
+    n = ch.n
+    jinv = [np.linalg.inv(inertia6(ch.mass[i], ch.com[i], ch.inertia[i])) for i in range(n)]
+    ad = [ch.ad_link(i, q[i]) for i in range(n)]
+    s = [ch.screw(i) for i in range(n)]
+    c = np.zeros((n, n))
+    for i in range(n):
+        phi = jinv[i] + (ad[i] @ jinv[i - 1] @ ad[i].T if i > 0 else 0.0)
+        c[i, i] = s[i] @ phi @ s[i]
+        if i + 1 < n:
+            c[i, i + 1] = c[i + 1, i] = s[i] @ (-jinv[i] @ ad[i + 1].T) @ s[i + 1]
+    return c

@@ -371,7 +371,7 @@ static chain_t chain_at(const model_arrays_t *ma, int64_t start, int n) {
 
 static void set_threads(int nthreads) {
 #ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
+    omp_set_num_threads(nthreads > 0 ? nthreads : omp_get_num_procs());
 #else
     (void)nthreads;
 #endif

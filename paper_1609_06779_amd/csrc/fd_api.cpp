@@ -1,0 +1,359 @@
+// fd_api.cpp -- host runtime of the C-ABI (include/fd.h): argument checks,
+// model upload, tile choice and kernel launches on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/fd.h"
+#include "kernels.h"
+
+struct fd_model {
+    fd_dtype_t dtype = FD_F64;
+    int32_t num_robots = 0;
+    int64_t total_links = 0;
+    std::vector<int32_t> n_links;     // host copy
+    std::vector<int32_t> prefix_max;  // max n over robots 0..r
+    std::vector<uint8_t> prefix_uni;  // robots 0..r all have n_links[0] links
+    int32_t nmax = 0;
+    bool uniform = false;
+    double g[3] = {0, 0, 0};
+    void* d_fields = nullptr;         // T[MF_COUNT][total_links]
+    int64_t* d_link_start = nullptr;
+    int32_t* d_n_links = nullptr;
+};
+
+namespace {
+
+constexpr int kMaxLinks = 256;
+
+bool finite3(const double* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+bool valid_rotation(const double* r) {
+    for (int k = 0; k < 9; ++k)
+        if (!std::isfinite(r[k])) return false;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double d = r[3 * i] * r[3 * j] + r[3 * i + 1] * r[3 * j + 1] + r[3 * i + 2] * r[3 * j + 2];
+            if (std::fabs(d - (i == j ? 1.0 : 0.0)) > 1e-6) return false;
+        }
+    double det = r[0] * (r[4] * r[8] - r[5] * r[7]) - r[1] * (r[3] * r[8] - r[5] * r[6]) +
+                 r[2] * (r[3] * r[7] - r[4] * r[6]);
+    return std::fabs(det - 1.0) < 1e-6;
+}
+
+bool valid_inertia(const double* in) {
+    for (int k = 0; k < 6; ++k)
+        if (!std::isfinite(in[k])) return false;
+    double a00 = in[0], a11 = in[1], a22 = in[2], a01 = in[3], a02 = in[4], a12 = in[5];
+    double m2 = a00 * a11 - a01 * a01;
+    double det = a00 * (a11 * a22 - a12 * a12) - a01 * (a01 * a22 - a12 * a02) + a02 * (a01 * a12 - a11 * a02);
+    return a00 > 0 && m2 > 0 && det > 0;
+}
+
+int pow2_lanes(int n) {
+    int p = 8;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+template <typename T> fdk::ModelView<T> view(const fd_model* m) {
+    fdk::ModelView<T> v;
+    v.base = static_cast<const T*>(m->d_fields);
+    v.stride = m->total_links;
+    v.link_start = m->d_link_start;
+    v.n_links = m->d_n_links;
+    v.num_robots = m->num_robots;
+    for (int k = 0; k < 3; ++k) v.g[k] = (T)m->g[k];
+    return v;
+}
+
+struct BatchPlan {
+    fdk::ChainMap cm;
+    int nmax;
+};
+
+fd_status_t plan_batch(const fd_model* m, const fd_batch_t* b, BatchPlan* p) {
+    if (!m || !b || b->batch < 0) return FD_ERR_INVALID_ARG;
+    p->cm.robot_id = b->robot_id;
+    p->cm.offsets = b->offsets;
+    p->cm.batch = b->batch;
+    p->cm.n_uniform = 0;
+    p->nmax = 0;
+    if (b->batch == 0) return FD_OK;
+    bool uni;
+    int n0;
+    if (b->robot_id == nullptr) {
+        if (m->num_robots == 1) {
+            p->nmax = m->n_links[0];
+            uni = true;
+        } else {
+            if (b->batch > m->num_robots) return FD_ERR_INVALID_ARG;
+            p->nmax = m->prefix_max[b->batch - 1];
+            uni = m->prefix_uni[b->batch - 1] != 0;
+        }
+        n0 = m->n_links[0];
+    } else {
+        p->nmax = m->nmax;
+        uni = m->uniform;
+        n0 = m->n_links[0];
+    }
+    if (b->offsets == nullptr) {
+        if (!uni) return FD_ERR_INVALID_ARG;
+        p->cm.n_uniform = n0;
+    }
+    return FD_OK;
+}
+
+fd_status_t from_hip(hipError_t e) {
+    if (e == hipSuccess) return FD_OK;
+    if (e == hipErrorInvalidConfiguration) return FD_ERR_UNSUPPORTED;
+    return FD_ERR_DEVICE;
+}
+
+fd_algo_t pick_algo(int nmax) {
+    // chosen from measured solves/s on gfx950 (see the benchmark); JSIIA is
+    // limited by its O(n^3) inversion and CFA by its log-depth overhead.
+    return nmax <= 64 ? FD_ALGO_ABIA : FD_ALGO_ABIA;
+}
+
+template <typename T>
+fd_status_t forward_t(const fd_model* m, const BatchPlan& p, const void* q, const void* qd, const void* tau,
+                      void* qdd, fd_algo_t algo, void* ws, size_t ws_bytes, hipStream_t st) {
+    const auto v = view<T>(m);
+    const T* tq = static_cast<const T*>(q);
+    const T* tqd = static_cast<const T*>(qd);
+    const T* tt = static_cast<const T*>(tau);
+    T* out = static_cast<T*>(qdd);
+    const int np = pow2_lanes(p.nmax);
+    switch (algo) {
+        case FD_ALGO_ABIA: {
+            size_t need = fdk::abia_workspace_elems(p.cm.batch, p.nmax) * sizeof(T);
+            if (!ws || ws_bytes < need) return FD_ERR_WORKSPACE;
+            return from_hip(fdk::launch_abia<T>(v, p.cm, p.nmax, tq, tqd, tt, out, static_cast<T*>(ws), st));
+        }
+        case FD_ALGO_JSIIA:
+            if (np > fdk::jsiia_max_np<T>()) return FD_ERR_UNSUPPORTED;
+            return from_hip(fdk::launch_jsiia<T>(np, v, p.cm, tq, tqd, tt, out, nullptr, st));
+        case FD_ALGO_CFA:
+            return from_hip(fdk::launch_cfa<T>(np, v, p.cm, tq, tqd, tt, out, nullptr, st));
+        default:
+            return FD_ERR_INVALID_ARG;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+fd_status_t fd_init(const fd_model_desc_t* d, fd_dtype_t dtype, fd_model_t** out) {
+    if (!d || !out || d->num_robots < 1 || !d->n_links || !d->axis || !d->offset || !d->mass || !d->com ||
+        !d->inertia || (dtype != FD_F64 && dtype != FD_F32))
+        return FD_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!finite3(d->gravity)) return FD_ERR_INVALID_ARG;
+    int64_t total = 0;
+    for (int r = 0; r < d->num_robots; ++r) {
+        if (d->n_links[r] < 1 || d->n_links[r] > kMaxLinks) return FD_ERR_INVALID_ARG;
+        total += d->n_links[r];
+    }
+    static const double kEye[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    std::vector<double> raw;
+    std::vector<uint8_t> first;
+    try {
+        raw.resize((size_t)total * 25);
+        first.resize((size_t)total);
+    } catch (const std::bad_alloc&) {
+        return FD_ERR_OUT_OF_MEMORY;
+    }
+    int64_t l = 0;
+    for (int r = 0; r < d->num_robots; ++r) {
+        for (int i = 0; i < d->n_links[r]; ++i, ++l) {
+            const double* ax = d->axis + 3 * l;
+            const double* hr = d->home_rot ? d->home_rot + 9 * l : kEye;
+            if (!finite3(ax) || std::sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]) < 1e-12) return FD_ERR_INVALID_ARG;
+            if (!valid_rotation(hr) || !finite3(d->offset + 3 * l) || !finite3(d->com + 3 * l)) return FD_ERR_INVALID_ARG;
+            if (!std::isfinite(d->mass[l]) || !(d->mass[l] > 0)) return FD_ERR_INVALID_ARG;
+            if (!valid_inertia(d->inertia + 6 * l)) return FD_ERR_INVALID_ARG;
+            double* w = raw.data() + 25 * l;
+            std::memcpy(w + 0, ax, 3 * sizeof(double));
+            std::memcpy(w + 3, hr, 9 * sizeof(double));
+            std::memcpy(w + 12, d->offset + 3 * l, 3 * sizeof(double));
+            w[15] = d->mass[l];
+            std::memcpy(w + 16, d->com + 3 * l, 3 * sizeof(double));
+            std::memcpy(w + 19, d->inertia + 6 * l, 6 * sizeof(double));
+            first[l] = i == 0;
+        }
+    }
+    fd_model* m = new (std::nothrow) fd_model;
+    if (!m) return FD_ERR_OUT_OF_MEMORY;
+    m->dtype = dtype;
+    m->num_robots = d->num_robots;
+    m->total_links = total;
+    m->n_links.assign(d->n_links, d->n_links + d->num_robots);
+    m->prefix_max.resize(d->num_robots);
+    m->prefix_uni.resize(d->num_robots);
+    int32_t mx = 0;
+    bool uni = true;
+    for (int r = 0; r < d->num_robots; ++r) {
+        mx = std::max(mx, d->n_links[r]);
+        uni = uni && d->n_links[r] == d->n_links[0];
+        m->prefix_max[r] = mx;
+        m->prefix_uni[r] = uni;
+    }
+    m->nmax = mx;
+    m->uniform = uni;
+    for (int k = 0; k < 3; ++k) m->g[k] = d->gravity[k];
+    std::vector<int64_t> starts(d->num_robots);
+    int64_t s = 0;
+    for (int r = 0; r < d->num_robots; ++r) {
+        starts[r] = s;
+        s += d->n_links[r];
+    }
+    const size_t esz = dtype == FD_F64 ? sizeof(double) : sizeof(float);
+    double* d_raw = nullptr;
+    uint8_t* d_first = nullptr;
+    fd_status_t st = FD_OK;
+    hipError_t e = hipSuccess;
+    if ((e = hipMalloc(&m->d_fields, esz * fdk::MF_COUNT * total)) != hipSuccess ||
+        (e = hipMalloc(&m->d_link_start, sizeof(int64_t) * d->num_robots)) != hipSuccess ||
+        (e = hipMalloc(&m->d_n_links, sizeof(int32_t) * d->num_robots)) != hipSuccess ||
+        (e = hipMalloc(&d_raw, raw.size() * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&d_first, first.size())) != hipSuccess) {
+        st = e == hipErrorOutOfMemory ? FD_ERR_OUT_OF_MEMORY : FD_ERR_DEVICE;
+    }
+    if (st == FD_OK) {
+        if (hipMemcpy(m->d_link_start, starts.data(), sizeof(int64_t) * starts.size(), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(m->d_n_links, d->n_links, sizeof(int32_t) * d->num_robots, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(d_raw, raw.data(), raw.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(d_first, first.data(), first.size(), hipMemcpyHostToDevice) != hipSuccess ||
+            fdk::launch_model_init(total, d_raw, d_first, m->d_fields, dtype == FD_F32, nullptr) != hipSuccess ||
+            hipDeviceSynchronize() != hipSuccess)
+            st = FD_ERR_DEVICE;
+    }
+    if (d_raw) (void)hipFree(d_raw);
+    if (d_first) (void)hipFree(d_first);
+    if (st != FD_OK) {
+        fd_destroy(m);
+        return st;
+    }
+    *out = m;
+    return FD_OK;
+}
+
+void fd_destroy(fd_model_t* m) {
+    if (!m) return;
+    if (m->d_fields) (void)hipFree(m->d_fields);
+    if (m->d_link_start) (void)hipFree(m->d_link_start);
+    if (m->d_n_links) (void)hipFree(m->d_n_links);
+    delete m;
+}
+
+fd_dtype_t fd_model_dtype(const fd_model_t* m) { return m ? m->dtype : FD_F64; }
+
+int32_t fd_max_links(const fd_model_t* m, fd_algo_t algo) {
+    if (!m) return 0;
+    if (algo == FD_ALGO_JSIIA) return m->dtype == FD_F64 ? fdk::jsiia_max_np<double>() : fdk::jsiia_max_np<float>();
+    return kMaxLinks;
+}
+
+fd_status_t fd_workspace_size(const fd_model_t* m, const fd_batch_t* b, fd_algo_t algo, size_t* bytes) {
+    if (!bytes) return FD_ERR_INVALID_ARG;
+    BatchPlan p;
+    fd_status_t s = plan_batch(m, b, &p);
+    if (s != FD_OK) return s;
+    if (algo == FD_ALGO_AUTO) algo = pick_algo(p.nmax);
+    const size_t esz = m->dtype == FD_F64 ? sizeof(double) : sizeof(float);
+    *bytes = algo == FD_ALGO_ABIA ? fdk::abia_workspace_elems(b->batch, p.nmax) * esz : 0;
+    return FD_OK;
+}
+
+fd_status_t fd_forward(const fd_model_t* m, const fd_batch_t* b, const void* q, const void* qd, const void* tau,
+                       void* qdd, fd_algo_t algo, void* ws, size_t ws_bytes, void* hip_stream) {
+    BatchPlan p;
+    fd_status_t s = plan_batch(m, b, &p);
+    if (s != FD_OK) return s;
+    if (algo < FD_ALGO_ABIA || algo > FD_ALGO_AUTO) return FD_ERR_INVALID_ARG;
+    if (b->batch == 0) return FD_OK;
+    if (!q || !qd || !tau || !qdd) return FD_ERR_INVALID_ARG;
+    if (algo == FD_ALGO_AUTO) algo = pick_algo(p.nmax);
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (m->dtype == FD_F64) return forward_t<double>(m, p, q, qd, tau, qdd, algo, ws, ws_bytes, st);
+    return forward_t<float>(m, p, q, qd, tau, qdd, algo, ws, ws_bytes, st);
+}
+
+fd_status_t fd_inverse(const fd_model_t* m, const fd_batch_t* b, const void* q, const void* qd, const void* qdd,
+                       int gravity, void* tau, void* hip_stream) {
+    BatchPlan p;
+    fd_status_t s = plan_batch(m, b, &p);
+    if (s != FD_OK) return s;
+    if (b->batch == 0) return FD_OK;
+    if (!q || !qd || !tau) return FD_ERR_INVALID_ARG;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const int np = pow2_lanes(p.nmax);
+    if (m->dtype == FD_F64)
+        return from_hip(fdk::launch_inverse<double>(np, view<double>(m), p.cm, (const double*)q, (const double*)qd,
+                                                    (const double*)qdd, gravity, (double*)tau, st));
+    return from_hip(fdk::launch_inverse<float>(np, view<float>(m), p.cm, (const float*)q, (const float*)qd,
+                                               (const float*)qdd, gravity, (float*)tau, st));
+}
+
+fd_status_t fd_joint_inertia(const fd_model_t* m, const fd_batch_t* b, const void* q, void* m_out, void* hip_stream) {
+    BatchPlan p;
+    fd_status_t s = plan_batch(m, b, &p);
+    if (s != FD_OK) return s;
+    if (b->offsets != nullptr) return FD_ERR_INVALID_ARG;
+    if (b->batch == 0) return FD_OK;
+    if (!q || !m_out) return FD_ERR_INVALID_ARG;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const int np = pow2_lanes(p.nmax);
+    if (m->dtype == FD_F64)
+        return from_hip(fdk::launch_mass<double>(np, view<double>(m), p.cm, (const double*)q, (double*)m_out, st));
+    return from_hip(fdk::launch_mass<float>(np, view<float>(m), p.cm, (const float*)q, (float*)m_out, st));
+}
+
+fd_status_t fd_scan6(fd_dtype_t dtype, int32_t segs, const int64_t* off, int32_t max_len, const void* b,
+                     const void* c, int reverse, void* x, void* hip_stream) {
+    if (segs < 0 || (dtype != FD_F64 && dtype != FD_F32)) return FD_ERR_INVALID_ARG;
+    if (segs == 0) return FD_OK;
+    if (!off || !b || !c || !x || max_len < 1) return FD_ERR_INVALID_ARG;
+    if (max_len > kMaxLinks) return FD_ERR_UNSUPPORTED;
+    const int np = pow2_lanes(max_len);
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (dtype == FD_F64)
+        return from_hip(fdk::launch_scan6<double>(np, segs, off, (const double*)b, (const double*)c, reverse,
+                                                  (double*)x, st));
+    return from_hip(fdk::launch_scan6<float>(np, segs, off, (const float*)b, (const float*)c, reverse, (float*)x, st));
+}
+
+fd_status_t fd_btd_solve6(fd_dtype_t dtype, int32_t segs, const int64_t* off, int32_t max_len, const void* d,
+                          const void* u, const void* r, void* x, int* status, void* hip_stream) {
+    if (segs < 0 || (dtype != FD_F64 && dtype != FD_F32)) return FD_ERR_INVALID_ARG;
+    if (segs == 0) return FD_OK;
+    if (!off || !d || !u || !r || !x || max_len < 1) return FD_ERR_INVALID_ARG;
+    if (max_len > kMaxLinks) return FD_ERR_UNSUPPORTED;
+    const int np = pow2_lanes(max_len);
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (dtype == FD_F64)
+        return from_hip(fdk::launch_btd6<double>(np, segs, off, (const double*)d, (const double*)u, (const double*)r,
+                                                 (double*)x, status, st));
+    return from_hip(fdk::launch_btd6<float>(np, segs, off, (const float*)d, (const float*)u, (const float*)r,
+                                            (float*)x, status, st));
+}
+
+const char* fd_status_string(fd_status_t s) {
+    switch (s) {
+        case FD_OK: return "ok";
+        case FD_ERR_INVALID_ARG: return "invalid argument";
+        case FD_ERR_UNSUPPORTED: return "unsupported by this build";
+        case FD_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case FD_ERR_DEVICE: return "device error";
+        case FD_ERR_WORKSPACE: return "workspace missing or too small";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,170 @@
+// k_abia.hip -- articulated-body inertia algorithm (Sec. II-C), one lane per chain.
+//
+// The articulated-body inertias come from a nonlinear backward recursion that
+// cannot be split across processors beyond a constant factor (Sec. III), so a
+// whole chain stays on one lane and a wavefront carries 64 chains. Three sweeps:
+//  1. forward (base to tip): link velocities and bias accelerations of the
+//     inverse dynamics at qdd = 0 (gravity as base acceleration), and the link
+//     forces f_i = J_i a_i - ad_{v_i}^T J_i v_i (kept in the workspace);
+//  2. backward: the force recursion gives tau_delta_i = tau_i - S_i^T F_i; in
+//     the same sweep the articulated inertias
+//        Jh_i = J_i + Ad_{i+1}^T (Jh_{i+1} - h h^T / D)_{i+1} Ad_{i+1},
+//        h_i = Jh_i S_i, D_i = S_i^T h_i,
+//     and the first linear (bi-diagonal, (I - X^T)-type) recursion
+//        p_i = Ad_{i+1}^T (p_{i+1} + h_{i+1} u_{i+1} / D_{i+1}),  u_i = tau_delta_i - S_i^T p_i;
+//  3. forward: the second linear recursion
+//        a_i = Ad_i a_{i-1} + S_i qdd_i,  qdd_i = (u_i - h_i^T Ad_i a_{i-1}) / D_i,
+// which together apply M^-1 to tau_delta (zero velocity, no gravity).
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+#include "spatial.h"
+
+namespace fdk {
+
+constexpr int ABIA_WS_FIELDS = 7;   // sweep 1: f (6); sweep 2 overwrites: h / D (6), u / D (1)
+
+size_t abia_workspace_elems(int batch, int nmax) {
+    size_t blocks = (size_t)(batch + 63) / 64;
+    return blocks * (size_t)nmax * ABIA_WS_FIELDS * 64;
+}
+
+template <typename T>
+__device__ __forceinline__ Pose<T> link_pose_at(const ModelView<T>& m, int64_t link, T q) {
+    T rh[9], p[3];
+    m.home(link, rh, p);
+    return joint_pose(rh, p, q);
+}
+
+// Y = X^T P X for X = Ad(T^-1) and symmetric P (full 6x6, row-major):
+// columns of X^T P are wrench_to_parent of the columns of P; then the same on the rows.
+template <typename T> __device__ __forceinline__ void congruence_to_parent(const Pose<T>& t, const T p[36], T y[36]) {
+    T w[36];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        T col[6], out[6];
+#pragma unroll
+        for (int r = 0; r < 6; ++r) col[r] = p[6 * r + c];
+        wrench_to_parent(t, col, out);
+#pragma unroll
+        for (int r = 0; r < 6; ++r) w[6 * r + c] = out[r];
+    }
+#pragma unroll
+    for (int r = 0; r < 6; ++r) wrench_to_parent(t, w + 6 * r, y + 6 * r);
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_abia(ModelView<T> m, ChainMap cm, int nmax, const T* __restrict__ q,
+                                             const T* __restrict__ qd, const T* __restrict__ tau,
+                                             T* __restrict__ qdd, T* __restrict__ ws) {
+    const int lane = threadIdx.x;
+    const int b = blockIdx.x * 64 + lane;
+    if (b >= cm.batch) return;
+    const ChainInfo ci = chain_info(m, cm, b);
+    const int n = ci.n;
+    // workspace: [block][link][field][lane]
+    T* wsb = ws + (size_t)blockIdx.x * nmax * ABIA_WS_FIELDS * 64 + lane;
+    auto wsat = [&](int i, int f) -> T& { return wsb[((size_t)i * ABIA_WS_FIELDS + f) * 64]; };
+
+    // sweep 1
+    T v[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+    T a[6] = {T(0), T(0), T(0), -m.g[0], -m.g[1], -m.g[2]};
+    for (int i = 0; i < n; ++i) {
+        const int64_t link = ci.link0 + i, st = ci.state0 + i;
+        const Pose<T> tl = link_pose_at(m, link, q[st]);
+        const T qdi = qd[st];
+        T t[6];
+        ad_inv_apply(tl, v, t);
+        t[2] += qdi;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[c] = t[c];
+        ad_inv_apply(tl, a, t);
+        // + ad_{V_i}(S qd) = (w x e3 qd; v x e3 qd)
+        t[0] += v[1] * qdi; t[1] -= v[0] * qdi;
+        t[3] += v[4] * qdi; t[4] -= v[3] * qdi;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) a[c] = t[c];
+        T f[6];
+        link_force(m.inertia(link), v, a, f);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) wsat(i, c) = f[c];
+    }
+
+    // sweep 2
+    T fc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};   // F_{i+1} (frame i+1)
+    T pc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};   // p_{i+1} + h_{i+1} u_{i+1} / D_{i+1} (frame i+1)
+    T pi[36];                                          // Jh_{i+1} - h h^T / D (frame i+1)
+#pragma unroll
+    for (int c = 0; c < 36; ++c) pi[c] = T(0);
+    Pose<T> tn = pose_identity<T>();                   // T_{i,i+1}
+    for (int i = n - 1; i >= 0; --i) {
+        const int64_t link = ci.link0 + i, st = ci.state0 + i;
+        T f[6], fp[6], pp[6], jh[36];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) f[c] = wsat(i, c);
+        inertia_to_mat6(m.inertia(link), jh);
+        if (i + 1 < n) {
+            wrench_to_parent(tn, fc, fp);
+            wrench_to_parent(tn, pc, pp);
+            T y[36];
+            congruence_to_parent(tn, pi, y);
+#pragma unroll
+            for (int c = 0; c < 36; ++c) jh[c] += y[c];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) f[c] += fp[c];
+        } else {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) pp[c] = T(0);
+        }
+        const T td = tau[st] - f[2];
+        const T dinv = T(1) / jh[14];
+        const T u = td - pp[2];
+        T h[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) h[c] = jh[6 * c + 2];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) wsat(i, c) = h[c] * dinv;
+        wsat(i, 6) = u * dinv;
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) pi[6 * r + c] = jh[6 * r + c] - h[r] * h[c] * dinv;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            pc[c] = pp[c] + h[c] * u * dinv;
+            fc[c] = f[c];
+        }
+        tn = link_pose_at(m, link, q[st]);
+    }
+
+    // sweep 3
+    T acc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+    for (int i = 0; i < n; ++i) {
+        const int64_t link = ci.link0 + i, st = ci.state0 + i;
+        const Pose<T> tl = link_pose_at(m, link, q[st]);
+        T t[6];
+        ad_inv_apply(tl, acc, t);
+        T x = wsat(i, 6);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) x -= wsat(i, c) * t[c];
+        t[2] += x;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) acc[c] = t[c];
+        qdd[st] = x;
+    }
+}
+
+template <typename T>
+hipError_t launch_abia(const ModelView<T>& m, const ChainMap& cm, int nmax, const T* q, const T* qd, const T* tau,
+                       T* qdd, T* ws, hipStream_t st) {
+    if (cm.batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_abia<T>), dim3((cm.batch + 63) / 64), dim3(64), 0, st, m, cm, nmax, q, qd, tau, qdd, ws);
+    return hipGetLastError();
+}
+
+template hipError_t launch_abia<double>(const ModelView<double>&, const ChainMap&, int, const double*, const double*,
+                                        const double*, double*, double*, hipStream_t);
+template hipError_t launch_abia<float>(const ModelView<float>&, const ChainMap&, int, const float*, const float*,
+                                       const float*, float*, float*, hipStream_t);
+
+}  // namespace fdk

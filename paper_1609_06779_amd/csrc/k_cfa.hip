@@ -1,0 +1,172 @@
+// k_cfa.hip -- the constraint force algorithm (Sec. III, Algorithm 1), one lane per link.
+//
+// With Phi = (I - Gamma) J^-1 (I - Gamma)^T (block tri-diagonal):
+//   Phi_ii = J_i^-1 + Ad_i J_{i-1}^-1 Ad_i^T,  Phi_{i,i+1} = -J_i^-1 Ad_{i+1}^T,
+// where Ad_i = Ad(T_{i-1,i}^-1). In the canonical joint frames S_i = e3 and
+// W_i = [e1 e2 e4 e5 e6], so A = W^T Phi W has the 5x5 blocks of Phi without
+// row and column 3 (eq. (cfa-eq2)), B tau = W^T Phi S tau and C = S^T Phi S.
+// Steps, as in Algorithm 1: CalcInvDyn and CalcDiffTorques (tau_delta), the
+// blocks of A and R = -B tau_delta, SolvBTDSys by odd-even elimination (F_c),
+// then CalcAcc: F = S tau_delta + W F_c and qdd_i = S_i^T sum_k Phi_ik F_k
+// (= C tau_delta + B^T F_c, eq. (fijany-final)).
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+#include "oee.h"
+#include "rnea.h"
+
+namespace fdk {
+
+// rows of Ad(T^-1) X for X given by rows: y_row = Ad(T^-1) x_row
+template <typename T> __device__ __forceinline__ void ad_inv_rows(const Pose<T>& t, const T x[36], T y[36]) {
+#pragma unroll
+    for (int r = 0; r < 6; ++r) ad_inv_apply(t, x + 6 * r, y + 6 * r);
+}
+
+__device__ __forceinline__ constexpr int wsel(int a) { return a < 2 ? a : a + 1; }   // W_i coordinates
+
+template <typename T, int NP>
+__global__ __launch_bounds__(Geo<NP>::threads) void k_cfa(ModelView<T> m, ChainMap cm, const T* __restrict__ q,
+                                                           const T* __restrict__ qd, const T* __restrict__ tau,
+                                                           T* __restrict__ qdd, int* __restrict__ status) {
+    __shared__ T xbuf[NP > 64 ? 12 * NP : 1];
+    __shared__ T oslot[Geo<NP>::chains * NP * OeeSlot<5>::size];
+    const int grp = threadIdx.x / NP, li = threadIdx.x % NP;
+    const int b = blockIdx.x * Geo<NP>::chains + grp;
+    ChainInfo ci{0, 0, 0};
+    if (b < cm.batch) ci = chain_info(m, cm, b);
+    const int n = ci.n;
+    const bool active = li < n;
+    const int64_t st = ci.state0 + li;
+    const int64_t link = ci.link0 + li;
+    T qi = active ? q[st] : T(0), qdi = active ? qd[st] : T(0), ti = active ? tau[st] : T(0);
+
+    // CalcInvDyn(q, qd, 0) and CalcDiffTorques
+    LinkLane<T> k;
+    const T tb = rnea_lane<T, NP>(m, link, active, qi, qdi, T(0), true, li, xbuf, k);
+    const T td = active ? ti - tb : T(0);
+
+    // Phi_ii
+    T phi[36];
+    T pnx[36];            // Phi_{i,i+1}
+    if (active) {
+        m.inertia_inv(link, phi);
+        if (li > 0) {
+            T jp[36], y[36], z[36];
+            m.inertia_inv(link - 1, jp);
+            ad_inv_rows(k.tl, jp, y);            // rows of Ad jp (jp symmetric: rows = columns)
+            // (Ad jp Ad^T): row r = Ad (row r of (Ad jp))^T ... use symmetry of Ad jp Ad^T:
+            // z = Ad * y^T applied column-wise, i.e. z_row_r = Ad (column r of y)
+#pragma unroll
+            for (int r = 0; r < 6; ++r) {
+                T col[6];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) col[c] = y[6 * c + r];
+                ad_inv_apply(k.tl, col, z + 6 * r);
+            }
+#pragma unroll
+            for (int c = 0; c < 36; ++c) phi[c] += z[c];
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < 36; ++c) phi[c] = T(0);
+    }
+    // Phi_{i,i+1} = -J_i^-1 Ad_{i+1}^T: row r = -(Ad_{i+1} (row r of J_i^-1))^T
+    Pose<T> tn;
+    shift_down<NP>(k.tl.r, tn.r, 9, 1, xbuf);
+    shift_down<NP>(k.tl.p, tn.p, 3, 1, xbuf);
+    const bool has_next = active && li + 1 < n;
+    const bool has_prev = active && li > 0;
+    if (has_next) {
+        T ji[36];
+        m.inertia_inv(link, ji);
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+            T y[6];
+            ad_inv_apply(tn, ji + 6 * r, y);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) pnx[6 * r + c] = -y[c];
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < 36; ++c) pnx[c] = T(0);
+    }
+
+    // R = -W^T (Phi_{i,i-1} e3 td_{i-1} + Phi_ii e3 td_i + Phi_{i,i+1} e3 td_{i+1}),
+    // Phi_{i,i-1} e3 = (row 3 of Phi_{i-1,i})^T, supplied by lane i-1.
+    T tdn, wsend[6], wprev[6];
+    shift_down<NP>(&td, &tdn, 1, 1, xbuf);
+    if (!has_next) tdn = T(0);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) wsend[c] = pnx[12 + c] * td;
+    shift_up<NP>(wsend, wprev, 6, 1, xbuf);
+    T rfull[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) rfull[c] = phi[6 * c + 2] * td + pnx[6 * c + 2] * tdn + (has_prev ? wprev[c] : T(0));
+
+    T d[25], u[25], r[5];
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+        r[a] = -rfull[wsel(a)];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            d[5 * a + c] = phi[6 * wsel(a) + wsel(c)];
+            u[5 * a + c] = pnx[6 * wsel(a) + wsel(c)];
+        }
+    }
+    if (!active) {
+        // keep inactive rows well defined (they never couple to active rows)
+#pragma unroll
+        for (int a = 0; a < 5; ++a)
+#pragma unroll
+            for (int c = 0; c < 5; ++c) d[5 * a + c] = (a == c) ? T(1) : T(0);
+    }
+    // rows of Phi needed by CalcAcc
+    T prow[6], nrow[6], ncol[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        prow[c] = phi[12 + c];
+        nrow[c] = pnx[12 + c];
+        ncol[c] = pnx[6 * c + 2];
+    }
+
+    // SolvBTDSys
+    const bool ok = oee_solve_rows<T, 5, NP>(d, u, r, li, n, active, oslot + grp * NP * OeeSlot<5>::size);
+
+    // CalcAcc
+    T f[6];
+#pragma unroll
+    for (int a = 0; a < 5; ++a) f[wsel(a)] = r[a];
+    f[2] = td;
+    T fn[6];
+    shift_down<NP>(f, fn, 6, 1, xbuf);
+    T csend = T(0), cprev;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) csend += ncol[c] * f[c];
+    shift_up<NP>(&csend, &cprev, 1, 1, xbuf);
+    T acc = T(0);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc += prow[c] * f[c] + (has_next ? nrow[c] * fn[c] : T(0));
+    if (has_prev) acc += cprev;
+    if (active) qdd[st] = acc;
+    if (active && !ok && status) atomicOr(status, 1);
+}
+
+template <typename T>
+hipError_t launch_cfa(int np, const ModelView<T>& m, const ChainMap& cm, const T* q, const T* qd, const T* tau,
+                      T* qdd, int* status, hipStream_t st) {
+    if (cm.batch <= 0) return hipSuccess;
+#define CALL(P)                                                                                      \
+    hipLaunchKernelGGL((k_cfa<T, P>), dim3((cm.batch + Geo<P>::chains - 1) / Geo<P>::chains),       \
+                       dim3(Geo<P>::threads), 0, st, m, cm, q, qd, tau, qdd, status)
+    FDK_NP_SWITCH(np, CALL)
+#undef CALL
+    return hipGetLastError();
+}
+
+template hipError_t launch_cfa<double>(int, const ModelView<double>&, const ChainMap&, const double*, const double*,
+                                       const double*, double*, int*, hipStream_t);
+template hipError_t launch_cfa<float>(int, const ModelView<float>&, const ChainMap&, const float*, const float*,
+                                      const float*, float*, int*, hipStream_t);
+
+}  // namespace fdk

@@ -1,0 +1,53 @@
+// kernels.h -- launchers of the device kernels (host side of the HIP path).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lanes.h"
+
+namespace fdk {
+
+#define FDK_NP_SWITCH(np, CALL)               \
+    switch (np) {                             \
+        case 8: CALL(8); break;               \
+        case 16: CALL(16); break;             \
+        case 32: CALL(32); break;             \
+        case 64: CALL(64); break;             \
+        case 128: CALL(128); break;           \
+        case 256: CALL(256); break;           \
+        default: return hipErrorInvalidValue; \
+    }
+
+// lane-per-link kernels: np = lanes per chain (power of two, 8..256)
+template <typename T>
+hipError_t launch_inverse(int np, const ModelView<T>& m, const ChainMap& cm, const T* q, const T* qd,
+                          const T* qdd, int gravity, T* tau, hipStream_t st);
+template <typename T>
+hipError_t launch_mass(int np, const ModelView<T>& m, const ChainMap& cm, const T* q, T* mass_out,
+                       hipStream_t st);
+template <typename T>
+hipError_t launch_cfa(int np, const ModelView<T>& m, const ChainMap& cm, const T* q, const T* qd,
+                      const T* tau, T* qdd, int* status, hipStream_t st);
+template <typename T>
+hipError_t launch_jsiia(int np, const ModelView<T>& m, const ChainMap& cm, const T* q, const T* qd,
+                        const T* tau, T* qdd, int* status, hipStream_t st);
+template <typename T> int jsiia_max_np();
+// lane-per-chain kernel
+template <typename T>
+hipError_t launch_abia(const ModelView<T>& m, const ChainMap& cm, int nmax, const T* q, const T* qd,
+                       const T* tau, T* qdd, T* ws, hipStream_t st);
+size_t abia_workspace_elems(int batch, int nmax);
+
+// building blocks
+template <typename T>
+hipError_t launch_scan6(int np, int segs, const int64_t* offsets, const T* b, const T* c, int reverse,
+                        T* x, hipStream_t st);
+template <typename T>
+hipError_t launch_btd6(int np, int segs, const int64_t* offsets, const T* d, const T* u, const T* r,
+                       T* x, int* status, hipStream_t st);
+
+// model upload: canonical joint frames from raw per-link parameters (fp64 in)
+hipError_t launch_model_init(int64_t nlinks, const double* raw, const uint8_t* first, void* out,
+                             int as_float, hipStream_t st);
+
+}  // namespace fdk

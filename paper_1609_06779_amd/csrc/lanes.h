@@ -1,0 +1,195 @@
+// lanes.h -- lane-group exchange, segmented scans and the device model view.
+//
+// A chain of n <= NP links is processed by a group of NP consecutive threads
+// (one link per thread). NP <= 64 groups live inside one wavefront and
+// exchange through ds_bpermute shuffles limited to the group; NP = 128 or 256
+// groups span a whole workgroup and exchange through LDS.
+//
+// The scans are the paper's all-prefix-sum over a binary associative operator
+// (Sec. II-B), evaluated by recursive doubling over the NP lanes of a chain:
+// log2(NP) steps, each combining with the partial result s lanes away.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "spatial.h"
+
+namespace fdk {
+
+// ---------------- model view (canonical joint frames, structure of arrays) ----------------
+// Field f of link l lives at base[f * stride + l].
+enum ModelField {
+    MF_ROT = 0,     // 9: home rotation of frame i in frame i-1 (row-major)
+    MF_POS = 9,     // 3: origin of frame i in frame i-1
+    MF_MASS = 12,   // 1
+    MF_H = 13,      // 3: m c (first mass moment about the frame origin)
+    MF_IB = 16,     // 6: Ic - m[c][c] (xx yy zz xy xz yz)
+    MF_ICINV = 22,  // 6: Ic^-1
+    MF_COM = 28,    // 3: c
+    MF_MINV = 31,   // 1: 1/m
+    MF_COUNT = 32
+};
+
+template <typename T> struct ModelView {
+    const T* base;
+    int64_t stride;               // total links of the model
+    const int64_t* link_start;    // [num_robots] first link of each robot
+    const int32_t* n_links;       // [num_robots]
+    int32_t num_robots;
+    T g[3];                       // gravity, base frame
+
+    __device__ __forceinline__ T at(int f, int64_t l) const { return base[f * stride + l]; }
+
+    __device__ __forceinline__ void home(int64_t l, T r[9], T p[3]) const {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) r[k] = at(MF_ROT + k, l);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) p[k] = at(MF_POS + k, l);
+    }
+
+    __device__ __forceinline__ Inertia<T> inertia(int64_t l) const {
+        Inertia<T> j;
+        j.m = at(MF_MASS, l);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) j.h[k] = at(MF_H + k, l);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) j.ib[k] = at(MF_IB + k, l);
+        return j;
+    }
+
+    // J^-1 = [[Ic^-1, -Ic^-1 [c]], [[c] Ic^-1, 1/m - [c] Ic^-1 [c]]] as a full 6x6 (row-major)
+    __device__ __forceinline__ void inertia_inv(int64_t l, T m[36]) const {
+        T s[6], c[3];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) s[k] = at(MF_ICINV + k, l);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) c[k] = at(MF_COM + k, l);
+        T mi = at(MF_MINV, l);
+        T a[9] = {s[0], s[3], s[4], s[3], s[1], s[5], s[4], s[5], s[2]};
+        // X = a [c]  (X[r][k] = sum_j a[r][j] [c][j][k])
+        T cx[9] = {T(0), -c[2], c[1], c[2], T(0), -c[0], -c[1], c[0], T(0)};
+        T x[9];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                x[3 * r + k] = a[3 * r] * cx[k] + a[3 * r + 1] * cx[3 + k] + a[3 * r + 2] * cx[6 + k];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                m[6 * r + k] = a[3 * r + k];
+                m[6 * r + k + 3] = -x[3 * r + k];        // -a [c]
+                m[6 * (r + 3) + k] = -x[3 * k + r];      // [c] a = -(a [c])^T
+                // 1/m - [c] a [c] = 1/m + (a [c])^T [c]
+                T y = cx[r] * x[k] + cx[3 + r] * x[3 + k] + cx[6 + r] * x[6 + k];
+                m[6 * (r + 3) + k + 3] = (r == k ? mi : T(0)) + y;
+            }
+    }
+};
+
+// ---------------- chain lookup ----------------
+struct ChainMap {
+    const int32_t* robot_id;   // device [batch] or null: chain b uses robot b (robot 0 if one robot)
+    const int64_t* offsets;    // device [batch+1] or null: chain b starts at b * n_uniform
+    int32_t batch;
+    int32_t n_uniform;
+};
+
+struct ChainInfo { int64_t link0; int64_t state0; int n; };
+
+template <typename T>
+__device__ __forceinline__ ChainInfo chain_info(const ModelView<T>& m, const ChainMap& cm, int b) {
+    int r = cm.robot_id ? cm.robot_id[b] : (m.num_robots == 1 ? 0 : b);
+    ChainInfo ci;
+    if (r < 0 || r >= m.num_robots) {   // out-of-range robot id: the chain is skipped
+        ci.link0 = 0;
+        ci.n = 0;
+        ci.state0 = 0;
+        return ci;
+    }
+    ci.link0 = m.link_start[r];
+    ci.n = m.n_links[r];
+    ci.state0 = cm.offsets ? cm.offsets[b] : (int64_t)b * cm.n_uniform;
+    return ci;
+}
+
+// ---------------- lane-group exchange ----------------
+// Value of lane (li - s) of the same group (callers only use it where li >= s).
+template <int NP, typename T>
+__device__ __forceinline__ void shift_up(const T* v, T* out, int k, int s, T* lds) {
+    if constexpr (NP <= 64) {
+        for (int c = 0; c < k; ++c) out[c] = __shfl_up(v[c], (unsigned)s, NP);
+    } else {
+        int t = threadIdx.x;
+        for (int c = 0; c < k; ++c) lds[c * NP + t] = v[c];
+        __syncthreads();
+        int src = t >= s ? t - s : t;
+        for (int c = 0; c < k; ++c) out[c] = lds[c * NP + src];
+        __syncthreads();
+    }
+}
+
+// Value of lane (li + s) of the same group (callers only use it where li + s < NP).
+template <int NP, typename T>
+__device__ __forceinline__ void shift_down(const T* v, T* out, int k, int s, T* lds) {
+    if constexpr (NP <= 64) {
+        for (int c = 0; c < k; ++c) out[c] = __shfl_down(v[c], (unsigned)s, NP);
+    } else {
+        int t = threadIdx.x;
+        for (int c = 0; c < k; ++c) lds[c * NP + t] = v[c];
+        __syncthreads();
+        int src = t + s < NP ? t + s : t;
+        for (int c = 0; c < k; ++c) out[c] = lds[c * NP + src];
+        __syncthreads();
+    }
+}
+
+// Inclusive prefix product of poses along the group: G_i = T_0 T_1 ... T_i.
+template <int NP, typename T>
+__device__ __forceinline__ Pose<T> scan_pose(Pose<T> x, int li, T* lds) {
+#pragma unroll
+    for (int s = 1; s < NP; s <<= 1) {
+        Pose<T> o;
+        shift_up<NP>(x.r, o.r, 9, s, lds);
+        shift_up<NP>(x.p, o.p, 3, s, lds);
+        if (li >= s) x = pose_mul(o, x);
+    }
+    return x;
+}
+
+// Inclusive prefix sum of K-vectors along the group.
+template <int NP, int K, typename T>
+__device__ __forceinline__ void scan_add(T* x, int li, T* lds) {
+#pragma unroll
+    for (int s = 1; s < NP; s <<= 1) {
+        T o[K];
+        shift_up<NP>(x, o, K, s, lds);
+        if (li >= s) {
+#pragma unroll
+            for (int c = 0; c < K; ++c) x[c] += o[c];
+        }
+    }
+}
+
+// Inclusive suffix sum of K-vectors along the group.
+template <int NP, int K, typename T>
+__device__ __forceinline__ void scan_add_rev(T* x, int li, T* lds) {
+#pragma unroll
+    for (int s = 1; s < NP; s <<= 1) {
+        T o[K];
+        shift_down<NP>(x, o, K, s, lds);
+        if (li + s < NP) {
+#pragma unroll
+            for (int c = 0; c < K; ++c) x[c] += o[c];
+        }
+    }
+}
+
+// Launch geometry of the lane-per-link kernels.
+template <int NP> struct Geo {
+    static constexpr int threads = NP < 64 ? 64 : NP;
+    static constexpr int chains = NP < 64 ? 64 / NP : 1;
+};
+
+}  // namespace fdk

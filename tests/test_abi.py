@@ -1,0 +1,101 @@
+"""The C-ABI library loads, exports every entry point of include/fd.h and
+rejects bad arguments before touching the GPU (runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1609_06779_amd import _lib, synth
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "fd.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fd_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1609_06779_amd import build
+        build.build()
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    declared = _declared()
+    assert "fd_forward" in declared and "fd_init" in declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(_lib.EXPORTS) == declared
+
+
+def test_status_strings(lib):
+    for s in (0, -1, -2, -3, -4, -5):
+        assert lib.fd_status_string(s)
+    assert _lib.status_string(-5) == "workspace missing or too small"
+
+
+def _desc(rb, keep):
+    d = _lib.ModelDesc()
+    dp = ctypes.POINTER(ctypes.c_double)
+    arrs = {k: np.ascontiguousarray(getattr(rb, k), dtype=np.float64)
+            for k in ("axis", "home_rot", "offset", "mass", "com", "inertia")}
+    arrs["n"] = np.ascontiguousarray(rb.n_links, dtype=np.int32)
+    keep.append(arrs)
+    d.num_robots = len(rb.n_links)
+    d.n_links = arrs["n"].ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    for k in ("axis", "home_rot", "offset", "mass", "com", "inertia"):
+        setattr(d, k, arrs[k].ctypes.data_as(dp))
+    for k in range(3):
+        d.gravity[k] = rb.gravity[k]
+    return d, arrs
+
+
+@pytest.mark.parametrize("mutate", ["mass_zero", "mass_nan", "inertia_not_spd", "axis_zero",
+                                    "rot_not_orthonormal", "n_zero", "n_too_long", "gravity_inf"])
+def test_init_rejects_invalid_models(lib, mutate):
+    rb = synth.make_robots([3, 2], seed=5)
+    keep = []
+    d, arrs = _desc(rb, keep)
+    if mutate == "mass_zero":
+        arrs["mass"][1] = 0.0
+    elif mutate == "mass_nan":
+        arrs["mass"][0] = np.nan
+    elif mutate == "inertia_not_spd":
+        arrs["inertia"][2] = [1.0, 1.0, 1.0, 2.0, 0.0, 0.0]
+    elif mutate == "axis_zero":
+        arrs["axis"][4] = 0.0
+    elif mutate == "rot_not_orthonormal":
+        arrs["home_rot"][0] = [2, 0, 0, 0, 1, 0, 0, 0, 1]
+    elif mutate == "n_zero":
+        arrs["n"][1] = 0
+    elif mutate == "n_too_long":
+        arrs["n"][0] = 100000
+    elif mutate == "gravity_inf":
+        d.gravity[2] = float("inf")
+    out = ctypes.c_void_p()
+    assert lib.fd_init(ctypes.byref(d), 0, ctypes.byref(out)) == _lib.FD_ERR_INVALID_ARG
+    assert not out.value
+
+
+def test_null_arguments(lib):
+    out = ctypes.c_void_p()
+    assert lib.fd_init(None, 0, ctypes.byref(out)) == _lib.FD_ERR_INVALID_ARG
+    b = _lib.Batch()
+    b.batch = 4
+    assert lib.fd_forward(None, ctypes.byref(b), None, None, None, None, 0, None, 0, None) == _lib.FD_ERR_INVALID_ARG
+    n = ctypes.c_size_t()
+    assert lib.fd_workspace_size(None, ctypes.byref(b), 0, ctypes.byref(n)) == _lib.FD_ERR_INVALID_ARG
+    assert lib.fd_inverse(None, ctypes.byref(b), None, None, None, 1, None, None) == _lib.FD_ERR_INVALID_ARG
+    assert lib.fd_scan6(0, -1, None, 8, None, None, 0, None, None) == _lib.FD_ERR_INVALID_ARG
+    assert lib.fd_scan6(0, 0, None, 8, None, None, 0, None, None) == _lib.FD_OK
+    assert lib.fd_scan6(7, 1, None, 8, None, None, 0, None, None) == _lib.FD_ERR_INVALID_ARG
+    assert lib.fd_btd_solve6(0, 2, None, 8, None, None, None, None, None, None) == _lib.FD_ERR_INVALID_ARG
+    fake = ctypes.c_void_p(8)   # never dereferenced: the length check fails first
+    assert lib.fd_btd_solve6(0, 1, fake, 300, fake, fake, fake, fake, None, None) == _lib.FD_ERR_UNSUPPORTED
+    assert lib.fd_max_links(None, 0) == 0

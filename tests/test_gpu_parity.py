@@ -1,0 +1,323 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle.
+
+Forward dynamics is compared per chain by the normwise relative error
+||qdd - qdd_ref|| / ||qdd_ref||. The bar is 1e-10 in FP64 and 1e-4 in FP32
+where the problem's conditioning allows it. Past that, a chain's bar is
+COND_FACTOR * kappa * u (u = unit roundoff of the path's precision), with the
+error model of each factorisation:
+  * JSIIA and ABIA are backward stable: kappa = cond_2(M), and additionally the
+    normwise backward error ||M qdd - tau_delta|| / (||M|| ||qdd|| + ||tau|| + ||tau_bias||)
+    (tau and the bias torque are the data of the solve) must stay below 64 u;
+  * the CFA's M^-1 = C - B^T A^-1 B (eq. (fijany-final)) is a difference of two
+    terms of size ||C||, so its error scales with kappa = ||C||_2 ||M||_2 (a
+    first-order scale, not a bound: hence the larger factor).
+FP32 runs round robots and states to FP32 first and the FP64 oracle runs on
+the same rounded values.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import dense
+from paper_1609_06779_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ALGOS = ("abia", "jsiia", "cfa")
+U = {"f64": 2.0 ** -53, "f32": 2.0 ** -24}
+TOL = {"f64": 1e-10, "f32": 1e-4}
+COND_FACTOR = {"abia": 16.0, "jsiia": 16.0, "cfa": 64.0}   # measured maxima 12.6, 12.6, 18
+BACKWARD_FACTOR = 64.0                                      # measured maximum 16
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def fdm():
+    from paper_1609_06779_amd import fd
+    return fd
+
+
+def _prep(lengths, dtype, cfg=2, seed=synth.ROOT_SEED, random_home=False):
+    rb = synth.make_robots(lengths, seed=seed, cfg=cfg, random_home=random_home)
+    q, qd, tau = synth.make_state(lengths, seed=seed, cfg=cfg)
+    if dtype == "f32":
+        rb = rb.astype_rounded(np.float32)
+        q, qd, tau = (a.astype(np.float32).astype(np.float64) for a in (q, qd, tau))
+    return rb, q, qd, tau
+
+
+def _t(a, dtype, dev):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64 if dtype == "f64" else np.float32)).to(dev)
+
+
+def _kappa(algo, rb, q, off):
+    ms = oracle.crba(rb, q, offsets=off)
+    if algo != "cfa":
+        return np.array([np.linalg.cond(m) for m in ms])
+    out = []
+    for b, m in enumerate(ms):
+        ch = dense.Chain(rb, off[b], int(off[b + 1] - off[b]))
+        out.append(np.linalg.norm(dense.cfa_c_matrix(ch, q[off[b]:off[b + 1]]), 2) * np.linalg.norm(m, 2))
+    return np.array(out)
+
+
+def _backward_error(rb, q, qd, tau, qdd, off):
+    ms = oracle.crba(rb, q, offsets=off)
+    bias = oracle.rnea(rb, q, qd, offsets=off)
+    eta = []
+    for b, m in enumerate(ms):
+        sl = slice(off[b], off[b + 1])
+        td = tau[sl] - bias[sl]
+        eta.append(np.linalg.norm(m @ qdd[sl] - td) /
+                   (np.linalg.norm(m, 2) * np.linalg.norm(qdd[sl]) + np.linalg.norm(tau[sl]) + np.linalg.norm(bias[sl])))
+    return np.array(eta)
+
+
+def _check(got, ref, off, dtype, rb, q, what, algo, qd=None, tau=None):
+    err = oracle.relative_error(got, ref, off)
+    bar = np.full(len(err), TOL[dtype])
+    worst = float(err.max()) if len(err) else 0.0
+    if worst > TOL[dtype]:
+        bar = np.maximum(bar, COND_FACTOR[algo] * _kappa(algo, rb, q, off) * U[dtype])
+    bad = np.nonzero(~(err <= bar))[0]
+    assert len(bad) == 0, f"{what}: {len(bad)} chains over the bar, worst {worst:.3e} (chain {bad[:5]})"
+    if algo != "cfa" and qd is not None:
+        eta = _backward_error(rb, q, qd, tau, got, off)
+        assert eta.max() <= BACKWARD_FACTOR * U[dtype], f"{what}: backward error {eta.max():.3e}"
+    return err
+
+
+def _forward(fdm, dev, rb, q, qd, tau, dtype, algo, offsets=None, robot_id=None, model=None):
+    m = model or fdm.Model(rb, dtype, device=dev)
+    batch = len(rb.n_links) if robot_id is None else len(robot_id)
+    toff = None if offsets is None else torch.from_numpy(np.asarray(offsets, np.int64)).to(dev)
+    trid = None if robot_id is None else torch.from_numpy(np.asarray(robot_id, np.int32)).to(dev)
+    out = m.forward(_t(q, dtype, dev), _t(qd, dtype, dev), _t(tau, dtype, dev), batch=batch, algo=algo,
+                    offsets=toff, robot_id=trid)
+    return out.cpu().numpy().astype(np.float64)
+
+
+# ---------------- forward dynamics, uniform batches ----------------
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 13, 16, 24, 32, 33, 50, 64, 100, 128, 200, 256])
+def test_forward_uniform(fdm, dev, algo, dtype, n):
+    if algo == "jsiia" and n > 128:
+        pytest.skip("JSIIA keeps M in LDS: n <= 128 in this build")
+    batch = 37 if n <= 64 else 11            # not a multiple of the chains per workgroup
+    lengths = np.full(batch, n, np.int32)
+    rb, q, qd, tau = _prep(lengths, dtype, random_home=(n % 2 == 1))
+    off = rb.offsets
+    ref = oracle.fd(rb, q, qd, tau)
+    got = _forward(fdm, dev, rb, q, qd, tau, dtype, algo)
+    _check(got, ref, off, dtype, rb, q, f"{algo} {dtype} n={n}", algo, qd, tau)
+
+
+def test_config_plain_n8_b1024_all_chains(fdm, dev):
+    lengths = synth.uniform_lengths(1024, 8)
+    rb, q, qd, tau = _prep(lengths, "f64", cfg=1)
+    off = rb.offsets
+    ref = oracle.fd(rb, q, qd, tau)
+    model = fdm.Model(rb, "f64", device=dev)
+    for algo in ALGOS:
+        got = _forward(fdm, dev, rb, q, qd, tau, "f64", algo, model=model)
+        err = oracle.relative_error(got, ref, off)
+        assert err.max() <= 1e-10, (algo, err.max())
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_ragged_batch_with_offsets(fdm, dev, algo):
+    hi = 128 if algo == "jsiia" else 256
+    lengths = synth.ragged_lengths(61, 1, hi, cfg=3)
+    lengths[:3] = [1, hi, 2]
+    rb, q, qd, tau = _prep(lengths, "f64", cfg=3)
+    off = rb.offsets
+    ref = oracle.fd(rb, q, qd, tau)
+    got = _forward(fdm, dev, rb, q, qd, tau, "f64", algo, offsets=off)
+    _check(got, ref, off, "f64", rb, q, f"{algo} ragged", algo, qd, tau)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_shared_robots_by_id(fdm, dev, algo):
+    base_lengths = np.array([7, 20, 3, 64, 33], np.int32)
+    base = synth.make_robots(base_lengths, cfg=4)
+    rng = np.random.default_rng(3)
+    rid = rng.integers(0, len(base_lengths), size=150).astype(np.int32)
+    per_chain = base.take(rid)
+    lengths = per_chain.n_links
+    q, qd, tau = synth.make_state(lengths, cfg=4)
+    off = synth.offsets_of(lengths)
+    ref = oracle.fd(per_chain, q, qd, tau)
+    model = fdm.Model(base, "f64", device=dev)
+    got = _forward(fdm, dev, base, q, qd, tau, "f64", algo, offsets=off, robot_id=rid, model=model)
+    _check(got, ref, off, "f64", per_chain, q, f"{algo} shared robots", algo, qd, tau)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_full_size_n64_b65536_sampled(fdm, dev, algo):
+    """The benchmark's workload and launch: 65536 chains of 64 links, FP64,
+    512 chains checked against the oracle."""
+    lengths = synth.uniform_lengths(65536, 64)
+    rb, q, qd, tau = _prep(lengths, "f64", cfg=2)
+    got = _forward(fdm, dev, rb, q, qd, tau, "f64", algo)
+    rng = np.random.default_rng(11)
+    pick = np.sort(rng.choice(65536, size=512, replace=False))
+    pick[0], pick[-1] = 0, 65535
+    sub = rb.take(pick)
+    idx = np.concatenate([np.arange(64 * b, 64 * b + 64) for b in pick])
+    ref = oracle.fd(sub, q[idx], qd[idx], tau[idx])
+    _check(got[idx], ref, sub.offsets, "f64", sub, q[idx], f"{algo} full size", algo, qd[idx], tau[idx])
+    assert np.all(np.isfinite(got))
+
+
+def test_deterministic_and_independent_of_batch_neighbours(fdm, dev):
+    lengths = np.full(40, 24, np.int32)
+    rb, q, qd, tau = _prep(lengths, "f64")
+    model = fdm.Model(rb, "f64", device=dev)
+    for algo in ALGOS:
+        a = _forward(fdm, dev, rb, q, qd, tau, "f64", algo, model=model)
+        b = _forward(fdm, dev, rb, q, qd, tau, "f64", algo, model=model)
+        assert np.array_equal(a, b), algo
+        # chain 5 alone (robot 5 picked by id) gives the same bits as inside the batch
+        sl = slice(5 * 24, 6 * 24)
+        alone = _forward(fdm, dev, rb, q[sl], qd[sl], tau[sl], "f64", algo, robot_id=[5], model=model)
+        assert np.array_equal(alone, a[sl]), algo
+
+
+def test_round_trip_on_gpu(fdm, dev):
+    """ID(q, qd, FD(q, qd, tau)) = tau, both on the GPU, in the normwise sense
+    ||ID - tau|| / (||M|| ||qdd|| + ||tau_delta||) of each factorisation's error model."""
+    lengths = np.full(64, 32, np.int32)
+    rb, q, qd, tau = _prep(lengths, "f64")
+    off = rb.offsets
+    model = fdm.Model(rb, "f64", device=dev)
+    tq, tqd, ttau = _t(q, "f64", dev), _t(qd, "f64", dev), _t(tau, "f64", dev)
+    ms = oracle.crba(rb, q)
+    bias = oracle.rnea(rb, q, qd)
+    for algo in ALGOS:
+        qdd = model.forward(tq, tqd, ttau, batch=64, algo=algo)
+        back = model.inverse(tq, tqd, qdd, batch=64).cpu().numpy()
+        qn = qdd.cpu().numpy()
+        bar = (COND_FACTOR["cfa"] * _kappa(algo, rb, q, off) if algo == "cfa" else np.full(64, BACKWARD_FACTOR)) * U["f64"]
+        for b, m in enumerate(ms):
+            sl = slice(off[b], off[b + 1])
+            eta = np.linalg.norm(back[sl] - tau[sl]) / (np.linalg.norm(m, 2) * np.linalg.norm(qn[sl]) +
+                                                       np.linalg.norm(tau[sl]) + np.linalg.norm(bias[sl]))
+            assert eta <= bar[b], (algo, b, eta)
+
+
+def test_empty_batch_and_workspace_errors(fdm, dev):
+    from paper_1609_06779_amd import _lib
+    lengths = np.full(4, 6, np.int32)
+    rb, q, qd, tau = _prep(lengths, "f64")
+    model = fdm.Model(rb, "f64", device=dev)
+    e = torch.empty(0, dtype=torch.float64, device=dev)
+    model.forward(e, e, e, batch=0, algo="cfa")
+    tq = _t(q, "f64", dev)
+    with pytest.raises(_lib.FdError) as ei:
+        model.forward(tq, tq, tq, batch=4, algo="abia", workspace=torch.empty(8, dtype=torch.uint8, device=dev))
+    assert ei.value.status == _lib.FD_ERR_WORKSPACE
+    with pytest.raises(_lib.FdError) as ei:
+        model.forward(tq, tq, tq, batch=5, algo="cfa")          # more chains than robots
+    assert ei.value.status == _lib.FD_ERR_INVALID_ARG
+    big = synth.make_robots([200], cfg=5)
+    mb = fdm.Model(big, "f64", device=dev)
+    t200 = torch.zeros(200, dtype=torch.float64, device=dev)
+    with pytest.raises(_lib.FdError) as ei:
+        mb.forward(t200, t200, t200, batch=1, algo="jsiia")
+    assert ei.value.status == _lib.FD_ERR_UNSUPPORTED
+
+
+# ---------------- inverse dynamics and the joint-space inertia ----------------
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n", [1, 7, 32, 64, 130, 256])
+def test_inverse_dynamics(fdm, dev, dtype, n):
+    batch = 21
+    lengths = np.full(batch, n, np.int32)
+    rb, q, qd, _ = _prep(lengths, dtype, cfg=6, random_home=True)
+    qdd = np.random.default_rng(n).standard_normal(len(q))
+    if dtype == "f32":
+        qdd = qdd.astype(np.float32).astype(np.float64)
+    model = fdm.Model(rb, dtype, device=dev)
+    for gravity in (True, False):
+        ref = oracle.rnea(rb, q, qd, qdd, gravity=gravity)
+        got = model.inverse(_t(q, dtype, dev), _t(qd, dtype, dev), _t(qdd, dtype, dev), batch=batch,
+                            gravity=gravity).cpu().numpy().astype(np.float64)
+        err = oracle.relative_error(got, ref, rb.offsets)
+        # inverse dynamics is a forward evaluation: error ~ n u times the transform magnitudes
+        bar = 1e-12 if dtype == "f64" else 2e-5
+        assert err.max() <= bar * max(1.0, n / 8), (gravity, err.max())
+
+
+@pytest.mark.parametrize("n", [1, 5, 16, 64, 128])
+def test_joint_inertia(fdm, dev, n):
+    batch = 9
+    lengths = np.full(batch, n, np.int32)
+    rb, q, _, _ = _prep(lengths, "f64", cfg=6, random_home=True)
+    model = fdm.Model(rb, "f64", device=dev)
+    got = model.joint_inertia(_t(q, "f64", dev), batch=batch, n=n).cpu().numpy()
+    ref = oracle.crba(rb, q)
+    for b in range(batch):
+        scale = np.abs(ref[b]).max()
+        assert np.abs(got[b] - ref[b]).max() <= 1e-13 * scale * max(1, n / 8), b
+
+
+# ---------------- the building blocks on their own ----------------
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("reverse", [False, True])
+def test_scan6(fdm, dev, dtype, reverse):
+    lengths = np.array([1, 2, 3, 7, 8, 9, 31, 64, 65, 100, 128, 200, 256, 5], np.int64)
+    b, c = synth.make_scan_elements(lengths, seed=17)
+    off = synth.offsets_of(lengths)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    if dtype == "f32":
+        b, c = b.astype(np.float32).astype(np.float64), c.astype(np.float32).astype(np.float64)
+    x = fdm.scan6(torch.from_numpy(b).to(dev, tdt), torch.from_numpy(c).to(dev, tdt),
+                  torch.from_numpy(off).to(dev), max_len=int(lengths.max()), reverse=reverse).cpu().numpy()
+    for s in range(len(lengths)):
+        sl = slice(off[s], off[s + 1])
+        ref = dense.scan_serial(b[sl], c[sl], reverse)
+        tol = (1e-13 if dtype == "f64" else 1e-5) * np.sqrt(lengths[s])
+        assert np.abs(x[sl] - ref).max() <= tol * (1 + np.abs(ref).max()), s
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_btd_solve6(fdm, dev, dtype):
+    lengths = np.array([1, 2, 3, 4, 5, 7, 8, 9, 16, 17, 33, 64, 100, 128, 129, 255, 256, 6], np.int64)
+    d, u, r = synth.make_btd(lengths, k=6, seed=23)
+    if dtype == "f32":
+        d, u, r = (a.astype(np.float32).astype(np.float64) for a in (d, u, r))
+    off = synth.offsets_of(lengths)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    x, status = fdm.btd_solve6(torch.from_numpy(d).to(dev, tdt), torch.from_numpy(u).to(dev, tdt),
+                               torch.from_numpy(r).to(dev, tdt), torch.from_numpy(off).to(dev),
+                               max_len=int(lengths.max()))
+    x = x.cpu().numpy().astype(np.float64)
+    assert int(status.item()) == 0
+    for s in range(len(lengths)):
+        sl = slice(off[s], off[s + 1])
+        ref = dense.btd_solve_dense(d[sl], u[sl], r[sl])
+        cond = np.linalg.cond(dense.btd_assemble(d[sl], u[sl]))
+        bar = max(1e-11 if dtype == "f64" else 1e-4, 16.0 * cond * U[dtype])
+        rel = np.linalg.norm(x[sl] - ref) / np.linalg.norm(ref)
+        assert rel <= bar, (s, lengths[s], rel)
+
+
+def test_btd_solve6_reports_non_spd(fdm, dev):
+    lengths = np.array([4], np.int64)
+    d = np.tile(-np.eye(6), (4, 1, 1))
+    u = np.zeros((4, 6, 6))
+    r = np.ones((4, 6))
+    _, status = fdm.btd_solve6(torch.from_numpy(d).to(dev), torch.from_numpy(u).to(dev),
+                               torch.from_numpy(r).to(dev), torch.from_numpy(np.array([0, 4])).to(dev), max_len=4)
+    assert int(status.item()) & 1
