@@ -22,6 +22,7 @@ struct fd_model {
     bool uniform = false;
     double g[3] = {0, 0, 0};
     void* d_fields = nullptr;         // T[MF_COUNT][total_links]
+    void* d_il = nullptr;             // T[MF_IL_COUNT][nmax][num_robots]
     int64_t* d_link_start = nullptr;
     int32_t* d_n_links = nullptr;
 };
@@ -68,6 +69,8 @@ template <typename T> fdk::ModelView<T> view(const fd_model* m) {
     v.n_links = m->d_n_links;
     v.num_robots = m->num_robots;
     for (int k = 0; k < 3; ++k) v.g[k] = (T)m->g[k];
+    v.il = static_cast<const T*>(m->d_il);
+    v.il_fstride = (int64_t)m->nmax * m->num_robots;
     return v;
 }
 
@@ -208,11 +211,18 @@ fd_status_t fd_init(const fd_model_desc_t* d, fd_dtype_t dtype, fd_model_t** out
     m->uniform = uni;
     for (int k = 0; k < 3; ++k) m->g[k] = d->gravity[k];
     std::vector<int64_t> starts(d->num_robots);
+    std::vector<int32_t> robot_of(total), index_of(total);
     int64_t s = 0;
     for (int r = 0; r < d->num_robots; ++r) {
         starts[r] = s;
+        for (int i = 0; i < d->n_links[r]; ++i) {
+            robot_of[s + i] = r;
+            index_of[s + i] = i;
+        }
         s += d->n_links[r];
     }
+    const int64_t il_elems = (int64_t)fdk::MF_IL_COUNT * mx * d->num_robots;
+    int32_t* d_ri = nullptr;
     const size_t esz = dtype == FD_F64 ? sizeof(double) : sizeof(float);
     double* d_raw = nullptr;
     uint8_t* d_first = nullptr;
@@ -222,7 +232,9 @@ fd_status_t fd_init(const fd_model_desc_t* d, fd_dtype_t dtype, fd_model_t** out
         (e = hipMalloc(&m->d_link_start, sizeof(int64_t) * d->num_robots)) != hipSuccess ||
         (e = hipMalloc(&m->d_n_links, sizeof(int32_t) * d->num_robots)) != hipSuccess ||
         (e = hipMalloc(&d_raw, raw.size() * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc(&d_first, first.size())) != hipSuccess) {
+        (e = hipMalloc(&d_first, first.size())) != hipSuccess ||
+        (e = hipMalloc(&m->d_il, esz * il_elems)) != hipSuccess ||
+        (e = hipMalloc(&d_ri, sizeof(int32_t) * 2 * total)) != hipSuccess) {
         st = e == hipErrorOutOfMemory ? FD_ERR_OUT_OF_MEMORY : FD_ERR_DEVICE;
     }
     if (st == FD_OK) {
@@ -230,12 +242,18 @@ fd_status_t fd_init(const fd_model_desc_t* d, fd_dtype_t dtype, fd_model_t** out
             hipMemcpy(m->d_n_links, d->n_links, sizeof(int32_t) * d->num_robots, hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(d_raw, raw.data(), raw.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(d_first, first.data(), first.size(), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(d_ri, robot_of.data(), sizeof(int32_t) * total, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(d_ri + total, index_of.data(), sizeof(int32_t) * total, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemset(m->d_il, 0, esz * il_elems) != hipSuccess ||
             fdk::launch_model_init(total, d_raw, d_first, m->d_fields, dtype == FD_F32, nullptr) != hipSuccess ||
+            fdk::launch_model_interleave(total, d_ri, d_ri + total, d->num_robots, (int64_t)mx * d->num_robots,
+                                         m->d_fields, m->d_il, dtype == FD_F32, nullptr) != hipSuccess ||
             hipDeviceSynchronize() != hipSuccess)
             st = FD_ERR_DEVICE;
     }
     if (d_raw) (void)hipFree(d_raw);
     if (d_first) (void)hipFree(d_first);
+    if (d_ri) (void)hipFree(d_ri);
     if (st != FD_OK) {
         fd_destroy(m);
         return st;
@@ -247,6 +265,7 @@ fd_status_t fd_init(const fd_model_desc_t* d, fd_dtype_t dtype, fd_model_t** out
 void fd_destroy(fd_model_t* m) {
     if (!m) return;
     if (m->d_fields) (void)hipFree(m->d_fields);
+    if (m->d_il) (void)hipFree(m->d_il);
     if (m->d_link_start) (void)hipFree(m->d_link_start);
     if (m->d_n_links) (void)hipFree(m->d_n_links);
     delete m;

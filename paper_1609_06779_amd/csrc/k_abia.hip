@@ -29,10 +29,12 @@ size_t abia_workspace_elems(int batch, int nmax) {
     return blocks * (size_t)nmax * ABIA_WS_FIELDS * 64;
 }
 
+// Model reads go through the robot-interleaved copy: lanes hold consecutive
+// chains, so field f of link i is one contiguous read across the wavefront.
 template <typename T>
-__device__ __forceinline__ Pose<T> link_pose_at(const ModelView<T>& m, int64_t link, T q) {
+__device__ __forceinline__ Pose<T> link_pose_at(const ModelView<T>& m, int i, int r, T q) {
     T rh[9], p[3];
-    m.home(link, rh, p);
+    m.home_il(i, r, rh, p);
     return joint_pose(rh, p, q);
 }
 
@@ -70,8 +72,8 @@ __global__ __launch_bounds__(64) void k_abia(ModelView<T> m, ChainMap cm, int nm
     T v[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
     T a[6] = {T(0), T(0), T(0), -m.g[0], -m.g[1], -m.g[2]};
     for (int i = 0; i < n; ++i) {
-        const int64_t link = ci.link0 + i, st = ci.state0 + i;
-        const Pose<T> tl = link_pose_at(m, link, q[st]);
+        const int64_t st = ci.state0 + i;
+        const Pose<T> tl = link_pose_at(m, i, ci.robot, q[st]);
         const T qdi = qd[st];
         T t[6];
         ad_inv_apply(tl, v, t);
@@ -85,7 +87,7 @@ __global__ __launch_bounds__(64) void k_abia(ModelView<T> m, ChainMap cm, int nm
 #pragma unroll
         for (int c = 0; c < 6; ++c) a[c] = t[c];
         T f[6];
-        link_force(m.inertia(link), v, a, f);
+        link_force(m.inertia_il(i, ci.robot), v, a, f);
 #pragma unroll
         for (int c = 0; c < 6; ++c) wsat(i, c) = f[c];
     }
@@ -98,11 +100,11 @@ __global__ __launch_bounds__(64) void k_abia(ModelView<T> m, ChainMap cm, int nm
     for (int c = 0; c < 36; ++c) pi[c] = T(0);
     Pose<T> tn = pose_identity<T>();                   // T_{i,i+1}
     for (int i = n - 1; i >= 0; --i) {
-        const int64_t link = ci.link0 + i, st = ci.state0 + i;
+        const int64_t st = ci.state0 + i;
         T f[6], fp[6], pp[6], jh[36];
 #pragma unroll
         for (int c = 0; c < 6; ++c) f[c] = wsat(i, c);
-        inertia_to_mat6(m.inertia(link), jh);
+        inertia_to_mat6(m.inertia_il(i, ci.robot), jh);
         if (i + 1 < n) {
             wrench_to_parent(tn, fc, fp);
             wrench_to_parent(tn, pc, pp);
@@ -134,14 +136,14 @@ __global__ __launch_bounds__(64) void k_abia(ModelView<T> m, ChainMap cm, int nm
             pc[c] = pp[c] + h[c] * u * dinv;
             fc[c] = f[c];
         }
-        tn = link_pose_at(m, link, q[st]);
+        tn = link_pose_at(m, i, ci.robot, q[st]);
     }
 
     // sweep 3
     T acc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
     for (int i = 0; i < n; ++i) {
-        const int64_t link = ci.link0 + i, st = ci.state0 + i;
-        const Pose<T> tl = link_pose_at(m, link, q[st]);
+        const int64_t st = ci.state0 + i;
+        const Pose<T> tl = link_pose_at(m, i, ci.robot, q[st]);
         T t[6];
         ad_inv_apply(tl, acc, t);
         T x = wsat(i, 6);

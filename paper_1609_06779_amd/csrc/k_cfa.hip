@@ -33,7 +33,7 @@ __global__ __launch_bounds__(Geo<NP>::threads) void k_cfa(ModelView<T> m, ChainM
     __shared__ T oslot[Geo<NP>::chains * NP * OeeSlot<5>::size];
     const int grp = threadIdx.x / NP, li = threadIdx.x % NP;
     const int b = blockIdx.x * Geo<NP>::chains + grp;
-    ChainInfo ci{0, 0, 0};
+    ChainInfo ci{0, 0, 0, 0};
     if (b < cm.batch) ci = chain_info(m, cm, b);
     const int n = ci.n;
     const bool active = li < n;

@@ -49,5 +49,7 @@ hipError_t launch_btd6(int np, int segs, const int64_t* offsets, const T* d, con
 // model upload: canonical joint frames from raw per-link parameters (fp64 in)
 hipError_t launch_model_init(int64_t nlinks, const double* raw, const uint8_t* first, void* out,
                              int as_float, hipStream_t st);
+hipError_t launch_model_interleave(int64_t nlinks, const int32_t* robot, const int32_t* index, int32_t num_robots,
+                                   int64_t fstride, const void* soa, void* il, int as_float, hipStream_t st);
 
 }  // namespace fdk

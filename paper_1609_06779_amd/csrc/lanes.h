@@ -27,7 +27,8 @@ enum ModelField {
     MF_ICINV = 22,  // 6: Ic^-1
     MF_COM = 28,    // 3: c
     MF_MINV = 31,   // 1: 1/m
-    MF_COUNT = 32
+    MF_COUNT = 32,
+    MF_IL_COUNT = 22   // fields MF_ROT .. MF_IB also kept robot-interleaved
 };
 
 template <typename T> struct ModelView {
@@ -37,8 +38,32 @@ template <typename T> struct ModelView {
     const int32_t* n_links;       // [num_robots]
     int32_t num_robots;
     T g[3];                       // gravity, base frame
+    // Robot-interleaved copy of the first MF_IL_COUNT fields: field f of link i
+    // of robot r at il[f * il_fstride + i * num_robots + r] (il_fstride =
+    // longest robot x num_robots), so that lanes holding consecutive robots
+    // read consecutive addresses.
+    const T* il;
+    int64_t il_fstride;
 
     __device__ __forceinline__ T at(int f, int64_t l) const { return base[f * stride + l]; }
+    __device__ __forceinline__ T at_il(int f, int i, int r) const {
+        return il[f * il_fstride + (int64_t)i * num_robots + r];
+    }
+    __device__ __forceinline__ void home_il(int i, int r, T rh[9], T p[3]) const {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) rh[k] = at_il(MF_ROT + k, i, r);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) p[k] = at_il(MF_POS + k, i, r);
+    }
+    __device__ __forceinline__ Inertia<T> inertia_il(int i, int r) const {
+        Inertia<T> j;
+        j.m = at_il(MF_MASS, i, r);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) j.h[k] = at_il(MF_H + k, i, r);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) j.ib[k] = at_il(MF_IB + k, i, r);
+        return j;
+    }
 
     __device__ __forceinline__ void home(int64_t l, T r[9], T p[3]) const {
 #pragma unroll
@@ -96,7 +121,7 @@ struct ChainMap {
     int32_t n_uniform;
 };
 
-struct ChainInfo { int64_t link0; int64_t state0; int n; };
+struct ChainInfo { int64_t link0; int64_t state0; int n; int robot; };
 
 template <typename T>
 __device__ __forceinline__ ChainInfo chain_info(const ModelView<T>& m, const ChainMap& cm, int b) {
@@ -106,8 +131,10 @@ __device__ __forceinline__ ChainInfo chain_info(const ModelView<T>& m, const Cha
         ci.link0 = 0;
         ci.n = 0;
         ci.state0 = 0;
+        ci.robot = 0;
         return ci;
     }
+    ci.robot = r;
     ci.link0 = m.link_start[r];
     ci.n = m.n_links[r];
     ci.state0 = cm.offsets ? cm.offsets[b] : (int64_t)b * cm.n_uniform;
