@@ -134,6 +134,14 @@ fd_status_t fd_scan6(fd_dtype_t dtype, int32_t segments, const int64_t* offsets,
 fd_status_t fd_btd_solve6(fd_dtype_t dtype, int32_t segments, const int64_t* offsets, int32_t max_len,
                           const void* d, const void* u, const void* r, void* x, int* status, void* hip_stream);
 
+/* Choice table for FD_ALGO_AUTO, per precision: table[n * 21 + k] (n = 1..256,
+ * k = 0..20) is the algorithm (FD_ALGO_ABIA/JSIIA/CFA) for batches whose
+ * longest chain has n links and whose size rounds to 2^k chains; produced by
+ * the autotuner from measured launch times. Host pointer, 257 * 21 bytes,
+ * copied. NULL restores the built-in choice. Not safe to call while another
+ * thread is inside fd_forward. FD_ERR_INVALID_ARG for a bad dtype or entry. */
+fd_status_t fd_set_auto_table(fd_dtype_t dtype, const int8_t* table);
+
 const char* fd_status_string(fd_status_t status);
 
 #ifdef __cplusplus

@@ -23,7 +23,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "fd_oracle.c")
+_SRCS = [os.path.join(_HERE, f) for f in ("fd_oracle.c", "fd_oracle_cx.c", "fd_core.inc", "fd_chain.h")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -33,10 +33,11 @@ _i64 = ctypes.POINTER(ctypes.c_int64)
 
 def build(force: bool = False) -> str:
     """Compile the oracle shared library with gcc (plain -O2, no FMA contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    stale = not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f) for f in _SRCS)
+    if force or stale:
         tmp = _LIB + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
-               "-std=c11", "-Wall", "-o", tmp, _SRC, "-lm"]
+               "-std=c11", "-Wall", "-Wno-unused-function", "-o", tmp, _SRCS[0], _SRCS[1], "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -57,6 +58,10 @@ def _load():
         lib.oracle_adjoint.argtypes = [_d, _d, ctypes.c_int, _d]
         lib.oracle_spatial_inertia.argtypes = [ctypes.c_double, _d, _d, _d]
         lib.oracle_max_threads.restype = ctypes.c_int
+        lib.oracle_fd_jvp_batch.argtypes = [ctypes.c_int, _i64, _i64] + model + [_d] * 8 + [ctypes.c_int]
+        lib.oracle_fd_jvp_batch.restype = ctypes.c_int
+        lib.oracle_rnea_jvp_batch.argtypes = [ctypes.c_int, _i64, _i64] + model + [_d] * 6 + [ctypes.c_int, _d, ctypes.c_int]
+        lib.oracle_rnea_jvp_batch.restype = ctypes.c_int
         for f in (lib.oracle_rnea_batch, lib.oracle_crba_batch, lib.oracle_fd_batch,
                   lib.oracle_fk_batch, lib.oracle_energy_batch):
             f.restype = ctypes.c_int
@@ -173,6 +178,32 @@ def energy(robots, q, qd, offsets=None, threads: int = 0):
     pe = np.empty(b)
     lib.oracle_energy_batch(b, _p(off, np.int64), None, *m.args(), _p(q), _p(qd), _p(ke), _p(pe), int(threads))
     return ke, pe
+
+
+def fd_jvp(robots, q, qd, tau, dq, dqd, dtau, offsets=None, threads: int = 0):
+    """(qdd, d qdd) with d qdd the derivative of forward dynamics along (dq, dqd, dtau),
+    exact to rounding (complex step through the same arithmetic as ``fd``)."""
+    lib = _load()
+    off = _offsets(robots, offsets)
+    m = _Model(robots)
+    arrs = [_c(a) for a in (q, qd, tau, dq, dqd, dtau)]
+    qdd = np.empty_like(arrs[0])
+    dqdd = np.empty_like(arrs[0])
+    lib.oracle_fd_jvp_batch(len(off) - 1, _p(off, np.int64), None, *m.args(), *[_p(a) for a in arrs], _p(qdd),
+                            _p(dqdd), int(threads))
+    return qdd, dqdd
+
+
+def rnea_jvp(robots, q, qd, qdd, dq, dqd, dqdd, gravity: bool = True, offsets=None, threads: int = 0):
+    """Derivative of tau = ID(q, qd, qdd) along (dq, dqd, dqdd) (complex step)."""
+    lib = _load()
+    off = _offsets(robots, offsets)
+    m = _Model(robots)
+    arrs = [_c(a) for a in (q, qd, qdd, dq, dqd, dqdd)]
+    out = np.empty_like(arrs[0])
+    lib.oracle_rnea_jvp_batch(len(off) - 1, _p(off, np.int64), None, *m.args(), *[_p(a) for a in arrs],
+                              int(bool(gravity)), _p(out), int(threads))
+    return out
 
 
 def link_rotation(axis, home_rot, q):

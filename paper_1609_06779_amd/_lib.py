@@ -13,7 +13,7 @@ DTYPES = {"f64": 0, "f32": 1}
 
 # C-ABI entry points declared in include/fd.h
 EXPORTS = ("fd_init", "fd_destroy", "fd_model_dtype", "fd_max_links", "fd_workspace_size", "fd_forward",
-           "fd_inverse", "fd_joint_inertia", "fd_scan6", "fd_btd_solve6", "fd_status_string")
+           "fd_inverse", "fd_joint_inertia", "fd_scan6", "fd_btd_solve6", "fd_set_auto_table", "fd_status_string")
 
 
 class ModelDesc(ctypes.Structure):
@@ -76,6 +76,8 @@ def load() -> ctypes.CDLL:
     lib.fd_scan6.restype = ctypes.c_int
     lib.fd_btd_solve6.argtypes = [ctypes.c_int, i32, vp, i32, vp, vp, vp, vp, vp, vp]
     lib.fd_btd_solve6.restype = ctypes.c_int
+    lib.fd_set_auto_table.argtypes = [ctypes.c_int, vp]
+    lib.fd_set_auto_table.restype = ctypes.c_int
     lib.fd_status_string.argtypes = [ctypes.c_int]
     lib.fd_status_string.restype = ctypes.c_char_p
     _lib = lib

@@ -117,10 +117,22 @@ fd_status_t from_hip(hipError_t e) {
     return FD_ERR_DEVICE;
 }
 
-fd_algo_t pick_algo(int nmax) {
-    // chosen from measured solves/s on gfx950 (see the benchmark); JSIIA is
-    // limited by its O(n^3) inversion and CFA by its log-depth overhead.
-    return nmax <= 64 ? FD_ALGO_ABIA : FD_ALGO_ABIA;
+// AUTO choice tables (per precision), [n][log2 batch]; empty = built-in rule.
+std::vector<int8_t> g_auto[2];
+
+int log2_bucket(int batch) {
+    int k = 0;
+    while (k < 20 && (1 << (k + 1)) <= batch) ++k;
+    // round to nearest power of two
+    if (k < 20 && batch - (1 << k) > (1 << (k + 1)) - batch) ++k;
+    return k;
+}
+
+fd_algo_t pick_algo(fd_dtype_t dtype, int nmax, int batch) {
+    const std::vector<int8_t>& t = g_auto[dtype == FD_F64 ? 0 : 1];
+    if (!t.empty() && nmax >= 1 && nmax <= kMaxLinks) return (fd_algo_t)t[nmax * 21 + log2_bucket(batch)];
+    // built-in rule: one lane per chain wins once the batch fills the GPU
+    return FD_ALGO_ABIA;
 }
 
 template <typename T>
@@ -284,7 +296,7 @@ fd_status_t fd_workspace_size(const fd_model_t* m, const fd_batch_t* b, fd_algo_
     BatchPlan p;
     fd_status_t s = plan_batch(m, b, &p);
     if (s != FD_OK) return s;
-    if (algo == FD_ALGO_AUTO) algo = pick_algo(p.nmax);
+    if (algo == FD_ALGO_AUTO) algo = pick_algo(m->dtype, p.nmax, b->batch);
     const size_t esz = m->dtype == FD_F64 ? sizeof(double) : sizeof(float);
     *bytes = algo == FD_ALGO_ABIA ? fdk::abia_workspace_elems(b->batch, p.nmax) * esz : 0;
     return FD_OK;
@@ -298,7 +310,7 @@ fd_status_t fd_forward(const fd_model_t* m, const fd_batch_t* b, const void* q, 
     if (algo < FD_ALGO_ABIA || algo > FD_ALGO_AUTO) return FD_ERR_INVALID_ARG;
     if (b->batch == 0) return FD_OK;
     if (!q || !qd || !tau || !qdd) return FD_ERR_INVALID_ARG;
-    if (algo == FD_ALGO_AUTO) algo = pick_algo(p.nmax);
+    if (algo == FD_ALGO_AUTO) algo = pick_algo(m->dtype, p.nmax, b->batch);
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     if (m->dtype == FD_F64) return forward_t<double>(m, p, q, qd, tau, qdd, algo, ws, ws_bytes, st);
     return forward_t<float>(m, p, q, qd, tau, qdd, algo, ws, ws_bytes, st);
@@ -361,6 +373,25 @@ fd_status_t fd_btd_solve6(fd_dtype_t dtype, int32_t segs, const int64_t* off, in
                                                  (double*)x, status, st));
     return from_hip(fdk::launch_btd6<float>(np, segs, off, (const float*)d, (const float*)u, (const float*)r,
                                             (float*)x, status, st));
+}
+
+fd_status_t fd_set_auto_table(fd_dtype_t dtype, const int8_t* table) {
+    if (dtype != FD_F64 && dtype != FD_F32) return FD_ERR_INVALID_ARG;
+    std::vector<int8_t>& t = g_auto[dtype == FD_F64 ? 0 : 1];
+    if (!table) {
+        t.clear();
+        return FD_OK;
+    }
+    std::vector<int8_t> next(table, table + 257 * 21);
+    const int jmax = dtype == FD_F64 ? fdk::jsiia_max_np<double>() : fdk::jsiia_max_np<float>();
+    for (int n = 1; n <= kMaxLinks; ++n)
+        for (int k = 0; k < 21; ++k) {
+            int a = next[n * 21 + k];
+            if (a < FD_ALGO_ABIA || a > FD_ALGO_CFA) return FD_ERR_INVALID_ARG;
+            if (a == FD_ALGO_JSIIA && pow2_lanes(n) > jmax) return FD_ERR_INVALID_ARG;
+        }
+    t.swap(next);
+    return FD_OK;
 }
 
 const char* fd_status_string(fd_status_t s) {

@@ -1,0 +1,157 @@
+"""Autotuner for the forward-dynamics launch choices.
+
+Times every algorithm on uniform batches over a grid of chain lengths and
+batch sizes (HIP events on the launch stream, inputs resident in HBM) and
+writes a JSON table: for each (precision, chain length, batch size) the
+fastest algorithm. ``fd_forward(..., algo=AUTO)`` follows the table once it is
+loaded with ``load_table`` (the binding calls it on first use when the cache
+file exists). The same sweep reproduces the paper's two experiments: the time
+of one call against the number of links and against the number of robots
+(Sec. V).
+
+    python -m paper_1609_06779_amd.tune --out paper_1609_06779_amd/tuning_gfx950.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_TABLE = os.path.join(HERE, "tuning_gfx950.json")
+ALGOS = ("abia", "jsiia", "cfa")
+N_GRID = (4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256)
+BATCH_GRID = (1, 16, 256, 4096, 65536)
+
+
+def time_forward(model, tq, tqd, ttau, batch, algo, reps=20, warmup=3):
+    """Mean milliseconds of one fd_forward launch over ``reps`` back-to-back launches."""
+    import torch
+
+    out = torch.empty_like(tq)
+    ws = model.workspace(batch, algo)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        model.forward(tq, tqd, ttau, batch=batch, algo=algo, out=out, workspace=ws, stream=stream)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(reps):
+        model.forward(tq, tqd, ttau, batch=batch, algo=algo, out=out, workspace=ws, stream=stream)
+    end.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / reps
+
+
+def sweep(ns=N_GRID, batches=BATCH_GRID, algos=ALGOS, dtype="f64", max_links_total=1 << 23, log=None):
+    """Rows of {n, batch, algo, dtype, ms, solves_per_s} for every grid point that fits."""
+    import torch
+
+    from . import fd, synth
+
+    dev = torch.device("cuda:0")
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    rows = []
+    for n in ns:
+        bmax = max(b for b in batches if b * n <= max_links_total)
+        lengths = synth.uniform_lengths(bmax, n)
+        rb = synth.make_robots(lengths, cfg=2)
+        q, qd, tau = synth.make_state(lengths, cfg=2)
+        if dtype == "f32":
+            rb = rb.astype_rounded(np.float32)
+        model = fd.Model(rb, dtype, device=dev)
+        tq, tqd, ttau = (torch.from_numpy(a).to(dev, tdt) for a in (q, qd, tau))
+        for batch in batches:
+            if batch > bmax:
+                continue
+            for algo in algos:
+                if n > model.max_links(algo):
+                    continue
+                ms = time_forward(model, tq[: batch * n], tqd[: batch * n], ttau[: batch * n], batch, algo,
+                                  reps=50 if batch <= 256 else 10)
+                row = {"n": n, "batch": batch, "algo": algo, "dtype": dtype, "ms": ms,
+                       "solves_per_s": batch / (ms * 1e-3)}
+                rows.append(row)
+                if log:
+                    print(json.dumps(row), file=log, flush=True)
+        model.close()
+        del model, tq, tqd, ttau
+        torch.cuda.empty_cache()
+    return rows
+
+
+def best_table(rows):
+    """{dtype: {"n": [...], "batch": [...], "algo": [[...]]}}: fastest algorithm per grid point."""
+    out = {}
+    for dtype in sorted({r["dtype"] for r in rows}):
+        sub = [r for r in rows if r["dtype"] == dtype]
+        ns = sorted({r["n"] for r in sub})
+        bs = sorted({r["batch"] for r in sub})
+        grid = []
+        for n in ns:
+            line = []
+            for b in bs:
+                cand = [r for r in sub if r["n"] == n and r["batch"] == b]
+                line.append(min(cand, key=lambda r: r["ms"])["algo"] if cand else None)
+            grid.append(line)
+        out[dtype] = {"n": ns, "batch": bs, "algo": grid}
+    return out
+
+
+def table_array(entry):
+    """Dense [257][21] int8 array: best algorithm for chain length n and batch 2^k
+    (nearest measured grid point, lengths rounded up, batches in log scale)."""
+    ns = entry["n"]
+    bs = entry["batch"]
+    codes = {"abia": 0, "jsiia": 1, "cfa": 2, None: 0}
+    arr = np.zeros((257, 21), dtype=np.int8)
+    for n in range(1, 257):
+        i = next((k for k, v in enumerate(ns) if v >= n), len(ns) - 1)
+        for k in range(21):
+            b = 2 ** k
+            j = int(np.argmin([abs(math.log2(x) - math.log2(b)) for x in bs]))
+            arr[n, k] = codes[entry["algo"][i][j]]
+    return arr
+
+
+def load_table(path=DEFAULT_TABLE):
+    """Hand the tuned table to the library (per precision). Returns False if there is none."""
+    if not os.path.exists(path):
+        return False
+    import ctypes
+
+    from . import _lib
+
+    data = json.load(open(path))
+    lib = _lib.load()
+    for dtype, entry in data.get("best", {}).items():
+        arr = np.ascontiguousarray(table_array(entry))
+        _lib.check(lib.fd_set_auto_table(_lib.DTYPES[dtype], arr.ctypes.data_as(ctypes.c_void_p)),
+                   "fd_set_auto_table")
+    return True
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=DEFAULT_TABLE)
+    ap.add_argument("--dtypes", default="f64,f32")
+    ap.add_argument("--ns", default=",".join(map(str, N_GRID)))
+    ap.add_argument("--batches", default=",".join(map(str, BATCH_GRID)))
+    args = ap.parse_args()
+    import torch
+
+    rows = []
+    for dtype in args.dtypes.split(","):
+        rows += sweep(tuple(int(x) for x in args.ns.split(",")), tuple(int(x) for x in args.batches.split(",")),
+                      dtype=dtype, log=sys.stderr)
+    data = {"arch": torch.cuda.get_device_properties(0).gcnArchName, "rows": rows, "best": best_table(rows)}
+    with open(args.out, "w") as f:
+        json.dump(data, f, indent=1)
+    print(json.dumps(data["best"]))
+
+
+if __name__ == "__main__":
+    main()

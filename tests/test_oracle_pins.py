@@ -368,3 +368,42 @@ def test_scan_serial_is_the_bidiagonal_solve():
         big[dd * i:dd * i + dd, dd * (i - 1):dd * i] = -b[i]
     x = np.linalg.solve(big, c.reshape(-1)).reshape(n, dd)
     np.testing.assert_allclose(dense.scan_serial(b, c), x, rtol=1e-12, atol=1e-12)
+
+
+# ---------------- derivatives (complex step) ----------------
+
+def test_fd_jvp_matches_central_differences():
+    lengths = [1, 4, 9]
+    rb = synth.make_robots(lengths, seed=401, random_home=True)
+    q, qd, tau = synth.make_state(lengths, seed=401)
+    rng = np.random.default_rng(401)
+    v = [rng.standard_normal(len(q)) for _ in range(3)]
+    qdd, dqdd = oracle.fd_jvp(rb, q, qd, tau, *v)
+    np.testing.assert_allclose(qdd, oracle.fd(rb, q, qd, tau), rtol=0, atol=1e-13 * (1 + np.abs(qdd).max()))
+    h = 1e-6
+    fp = oracle.fd(rb, q + h * v[0], qd + h * v[1], tau + h * v[2])
+    fm = oracle.fd(rb, q - h * v[0], qd - h * v[1], tau - h * v[2])
+    np.testing.assert_allclose(dqdd, (fp - fm) / (2 * h), rtol=0, atol=1e-7 * np.abs(dqdd).max())
+
+
+def test_rnea_jvp_along_acceleration_is_the_joint_inertia():
+    lengths = [2, 7]
+    rb = synth.make_robots(lengths, seed=402, random_home=True)
+    q, qd, tau = synth.make_state(lengths, seed=402)
+    qdd = oracle.fd(rb, q, qd, tau)
+    a = np.random.default_rng(402).standard_normal(len(q))
+    z = np.zeros(len(q))
+    dt = oracle.rnea_jvp(rb, q, qd, qdd, z, z, a)
+    off = rb.offsets
+    for b, m in enumerate(oracle.crba(rb, q)):
+        np.testing.assert_allclose(dt[off[b]:off[b + 1]], m @ a[off[b]:off[b + 1]], rtol=1e-12, atol=1e-12)
+
+
+def test_fd_jvp_along_torque_is_the_inverse_inertia():
+    lengths = [5]
+    rb = synth.make_robots(lengths, seed=403)
+    q, qd, tau = synth.make_state(lengths, seed=403)
+    v = np.random.default_rng(403).standard_normal(5)
+    z = np.zeros(5)
+    _, dqdd = oracle.fd_jvp(rb, q, qd, tau, z, z, v)
+    np.testing.assert_allclose(dqdd, np.linalg.solve(oracle.crba(rb, q)[0], v), rtol=1e-12, atol=1e-12)
