@@ -64,6 +64,98 @@ def cpu_baseline(rb, q, qd, tau, chains: int):
                       f"Cholesky, all host threads, {dt:.2f} s wall"}
 
 
+def serving_leg(dtype: str, requests: int = 3000):
+    """Continuous batching over 32 resident robots (n ~ U{7..200}), requests of
+    1..4096 chains (log-uniform), Poisson arrivals at 50% and 80% of the
+    measured saturation rate; latency is arrival to result in host memory."""
+    import torch
+
+    from paper_1609_06779_amd import fd, serve, synth
+
+    dev = torch.device("cuda:0")
+    lengths = synth.ragged_lengths(32, 7, 200, cfg=4)
+    model = fd.Model(synth.make_robots(lengths, cfg=4), dtype, device=dev)
+    ex = serve.GpuExecutor(model, lengths, algo="abia", streams=4)
+    budget = 8 << 30
+
+    def run(qps, count, seed):
+        reqs = serve.make_requests(lengths, count, qps, seed=seed, dtype=dtype, shared=True)
+        sched = serve.Scheduler(ex, budget, max_inflight=8, idle=serve.spin_idle)
+        torch.cuda.synchronize()
+        return sched.run(reqs), reqs
+
+    run(float("inf"), 64, 1)                     # warm up allocator and kernels
+    sat, reqs = run(float("inf"), requests // 2, 2)
+    mean_chains = float(np.mean([r.chains for r in reqs]))
+    out = {"robots": 32, "n_links": "U{7..200}", "chains_per_request": "log-uniform 1..4096",
+           "budget_bytes": budget, "streams": 4, "saturation_solves_per_s": sat.solves_per_s,
+           "saturation_launches": sat.launches}
+    for load in (0.5, 0.8):
+        qps = load * sat.solves_per_s / mean_chains
+        st, _ = run(qps, requests, 3 + int(load * 10))
+        out[f"load_{int(load * 100)}pct"] = {"qps": qps, "p50_ms": st.p50 * 1e3, "p99_ms": st.p99 * 1e3,
+                                             "solves_per_s": st.solves_per_s, "launches": st.launches,
+                                             "max_inflight": st.max_inflight}
+    model.close()
+    return out
+
+
+def ragged_leg(dtype: str, batch: int = 100000, lo: int = 4, hi: int = 256, reps: int = 5):
+    """100000 chains with n ~ U{4..256}, each its own robot: one persistent launch
+    (grid from the autotuner's table) against a plain ragged launch and against
+    one launch per distinct length."""
+    import torch
+
+    from paper_1609_06779_amd import fd, synth, tune
+
+    dev = torch.device("cuda:0")
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    lengths = synth.ragged_lengths(batch, lo, hi, cfg=3)
+    rb = synth.make_robots(lengths, cfg=3)
+    q, qd, tau = synth.make_state(lengths, cfg=3)
+    off = rb.offsets
+    model = fd.Model(rb, dtype, device=dev)
+    tq, tqd, ttau = (torch.from_numpy(a).to(dev, tdt) for a in (q, qd, tau))
+    toff = torch.from_numpy(off).to(dev)
+    out = torch.empty_like(tq)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    grid = tune.ragged_grid(dtype)
+    pws = model.persistent_workspace(batch, grid, offsets=toff)
+    ms_pers = timed(lambda: model.forward_persistent(tq, tqd, ttau, batch=batch, grid=grid, offsets=toff, out=out,
+                                                     workspace=pws, stream=stream))
+    aws = model.workspace(batch, "abia", offsets=toff)
+    ms_plain = timed(lambda: model.forward(tq, tqd, ttau, batch=batch, algo="abia", offsets=toff, out=out,
+                                           workspace=aws, stream=stream))
+    groups = []
+    for n in np.unique(lengths):
+        ids = np.nonzero(lengths == n)[0].astype(np.int32)
+        groups.append((len(ids), torch.from_numpy(ids).to(dev), torch.from_numpy(off[ids]).to(dev),
+                       model.workspace(len(ids), "abia", robot_id=torch.from_numpy(ids).to(dev))))
+
+    def per_length():
+        for cnt, rid, goff, ws in groups:
+            model.forward(tq, tqd, ttau, batch=cnt, algo="abia", robot_id=rid, offsets=goff, out=out, workspace=ws,
+                          stream=stream)
+
+    ms_split = timed(per_length)
+    model.close()
+    return {"workload": f"ragged-b{batch}-n{lo}..{hi}", "links": int(lengths.sum()), "grid": grid,
+            "persistent_ms": ms_pers, "persistent_solves_per_s": batch / (ms_pers * 1e-3),
+            "plain_ragged_ms": ms_plain, "per_length_launches": len(groups), "per_length_ms": ms_split}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +167,8 @@ def main():
     ap.add_argument("--algos", default="abia,jsiia,cfa")
     ap.add_argument("--cpu-chains", type=int, default=65536)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-ragged", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); chains are independent, so a "
@@ -158,6 +252,14 @@ def main():
         "roofline": {"bound": "alu", "kernel": dominant, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None},
     }
+    if not args.no_ragged:
+        print("[bench] ragged leg", file=sys.stderr, flush=True)
+        result["ragged"] = ragged_leg(args.dtype)
+    if not args.no_serve:
+        print("[bench] serving leg", file=sys.stderr, flush=True)
+        result["serving"] = serving_leg(args.dtype)
+        l80 = result["serving"]["load_80pct"]
+        result["p99_latency_ms_at_80pct_load"] = l80["p99_ms"]
     if not args.no_cpu and args.dtype == "f64":
         result["cpu_baseline"] = cpu_baseline(rb, q, qd, tau, min(args.cpu_chains, args.batch))
     print(json.dumps(result), flush=True)

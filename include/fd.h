@@ -103,6 +103,47 @@ fd_status_t fd_forward(const fd_model_t* model, const fd_batch_t* batch, const v
                        const void* tau, void* qdd, fd_algo_t algo, void* workspace, size_t ws_bytes,
                        void* hip_stream);
 
+/* Forward dynamics of a batch, typically ragged, in one persistent launch of the
+ * articulated-body algorithm (Sec. II-C). Small planning kernels first sort the
+ * batch's chains on the device by decreasing length (into the workspace);
+ * then `grid` resident wavefronts take 64-chain tiles of that order from an
+ * atomic counter until none is left, so each tile holds chains of nearly
+ * equal length and the longest go first. grid = 0 picks the number of
+ * wavefronts the GPU holds at once. Results equal fd_forward(...,
+ * FD_ALGO_ABIA, ...) bit for bit. The workspace must hold
+ * fd_persistent_workspace_size bytes for the same grid. Asynchronous. */
+fd_status_t fd_persistent_workspace_size(const fd_model_t* model, const fd_batch_t* batch, int32_t grid,
+                                         size_t* bytes);
+fd_status_t fd_forward_persistent(const fd_model_t* model, const fd_batch_t* batch, const void* q, const void* qd,
+                                  const void* tau, void* qdd, int32_t grid, void* workspace, size_t ws_bytes,
+                                  void* hip_stream);
+
+/* Reverse-mode derivative of fd_forward (a vector-Jacobian product). Given
+ * qdd = FD(q, qd, tau) and a cotangent grad_qdd, writes
+ *     grad_tau = lambda = M(q)^-1 grad_qdd,
+ *     [grad_q; grad_qd] = -(d ID / d(q, qd))^T lambda   at (q, qd, qdd),
+ * the implicit-function theorem applied to ID(q, qd, qdd) = tau (eq. (eq-motion)).
+ * lambda uses the articulated-body factorisation of M^-1 (Sec. II-C). accumulate
+ * != 0 adds to the three gradient arrays instead of overwriting them. All arrays
+ * are device arrays of the model's precision, packed per chain; the workspace
+ * must hold fd_backward_workspace_size bytes. Asynchronous. */
+fd_status_t fd_backward_workspace_size(const fd_model_t* model, const fd_batch_t* batch, size_t* bytes);
+fd_status_t fd_backward(const fd_model_t* model, const fd_batch_t* batch, const void* q, const void* qd,
+                        const void* qdd, const void* grad_qdd, void* grad_q, void* grad_qd, void* grad_tau,
+                        int accumulate, void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* One semi-implicit Euler step of a rollout, elementwise over count entries:
+ * qd_next = qd + dt qdd, q_next = q + dt qd_next. Outputs may alias inputs
+ * entry by entry. Asynchronous. */
+fd_status_t fd_euler_step(fd_dtype_t dtype, int64_t count, double dt, const void* q, const void* qd, const void* qdd,
+                          void* q_next, void* qd_next, void* hip_stream);
+/* Its adjoint: from the cotangents of (q_next, qd_next) writes those of q, qd
+ * and qdd (overwriting): grad_qd = grad_qd_next + dt grad_q_next,
+ * grad_q = grad_q_next, grad_qdd = dt grad_qd. Asynchronous. */
+fd_status_t fd_euler_step_backward(fd_dtype_t dtype, int64_t count, double dt, const void* grad_q_next,
+                                   const void* grad_qd_next, void* grad_q, void* grad_qd, void* grad_qdd,
+                                   void* hip_stream);
+
 /* Inverse dynamics, eq. (EOM-full) (CalcInvDyn of Algorithm 1):
  * tau = M(q) qdd + tau_bias(q, qd), with gravity when `gravity` != 0.
  * qdd may be NULL (zero: tau is then the bias torque). Asynchronous. */

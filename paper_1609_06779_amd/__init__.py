@@ -8,11 +8,11 @@ systems), hand-written in HIP behind the C-ABI of include/fd.h.
 not been built.
 """
 
-__all__ = ["Model", "scan6", "btd_solve6"]
+__all__ = ["Model", "scan6", "btd_solve6", "forward_dynamics", "rollout"]
 
 
 def __getattr__(name):
-    if name in ("Model", "scan6", "btd_solve6"):
+    if name in ("Model", "scan6", "btd_solve6", "forward_dynamics", "rollout"):
         from . import fd
         return getattr(fd, name)
     raise AttributeError(name)

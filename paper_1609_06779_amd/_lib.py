@@ -13,6 +13,8 @@ DTYPES = {"f64": 0, "f32": 1}
 
 # C-ABI entry points declared in include/fd.h
 EXPORTS = ("fd_init", "fd_destroy", "fd_model_dtype", "fd_max_links", "fd_workspace_size", "fd_forward",
+           "fd_persistent_workspace_size", "fd_forward_persistent",
+           "fd_backward_workspace_size", "fd_backward", "fd_euler_step", "fd_euler_step_backward",
            "fd_inverse", "fd_joint_inertia", "fd_scan6", "fd_btd_solve6", "fd_set_auto_table", "fd_status_string")
 
 
@@ -68,6 +70,18 @@ def load() -> ctypes.CDLL:
     lib.fd_workspace_size.restype = ctypes.c_int
     lib.fd_forward.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, vp, vp, ctypes.c_int, vp, sz, vp]
     lib.fd_forward.restype = ctypes.c_int
+    lib.fd_persistent_workspace_size.argtypes = [vp, ctypes.POINTER(Batch), i32, ctypes.POINTER(sz)]
+    lib.fd_persistent_workspace_size.restype = ctypes.c_int
+    lib.fd_forward_persistent.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, vp, vp, i32, vp, sz, vp]
+    lib.fd_forward_persistent.restype = ctypes.c_int
+    lib.fd_backward_workspace_size.argtypes = [vp, ctypes.POINTER(Batch), ctypes.POINTER(sz)]
+    lib.fd_backward_workspace_size.restype = ctypes.c_int
+    lib.fd_backward.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp, sz, vp]
+    lib.fd_backward.restype = ctypes.c_int
+    lib.fd_euler_step.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_double, vp, vp, vp, vp, vp, vp]
+    lib.fd_euler_step.restype = ctypes.c_int
+    lib.fd_euler_step_backward.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_double, vp, vp, vp, vp, vp, vp]
+    lib.fd_euler_step_backward.restype = ctypes.c_int
     lib.fd_inverse.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, vp, ctypes.c_int, vp, vp]
     lib.fd_inverse.restype = ctypes.c_int
     lib.fd_joint_inertia.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, vp]

@@ -316,6 +316,109 @@ fd_status_t fd_forward(const fd_model_t* m, const fd_batch_t* b, const void* q, 
     return forward_t<float>(m, p, q, qd, tau, qdd, algo, ws, ws_bytes, st);
 }
 
+int persistent_grid(fd_dtype_t dtype, int32_t grid) {
+    if (grid > 0) return grid;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    // one 64-thread workgroup per SIMD per wave slot the kernel's registers allow
+    const int per_cu = dtype == FD_F64 ? 4 : 12;
+    return cus * per_cu;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+fd_status_t fd_persistent_workspace_size(const fd_model_t* m, const fd_batch_t* b, int32_t grid, size_t* bytes) {
+    if (!bytes || grid < 0) return FD_ERR_INVALID_ARG;
+    BatchPlan p;
+    fd_status_t s = plan_batch(m, b, &p);
+    if (s != FD_OK) return s;
+    const size_t esz = m->dtype == FD_F64 ? sizeof(double) : sizeof(float);
+    const int g = persistent_grid(m->dtype, grid);
+    *bytes = align256(fdk::persistent_plan_bytes(b->batch)) + fdk::abia_persistent_workspace_elems(g, p.nmax) * esz;
+    return FD_OK;
+}
+
+fd_status_t fd_forward_persistent(const fd_model_t* m, const fd_batch_t* b, const void* q, const void* qd,
+                                  const void* tau, void* qdd, int32_t grid, void* ws, size_t ws_bytes,
+                                  void* hip_stream) {
+    BatchPlan p;
+    fd_status_t s = plan_batch(m, b, &p);
+    if (s != FD_OK) return s;
+    if (grid < 0) return FD_ERR_INVALID_ARG;
+    if (b->batch == 0) return FD_OK;
+    if (!q || !qd || !tau || !qdd) return FD_ERR_INVALID_ARG;
+    const size_t esz = m->dtype == FD_F64 ? sizeof(double) : sizeof(float);
+    const int g = persistent_grid(m->dtype, grid);
+    const size_t plan = align256(fdk::persistent_plan_bytes(b->batch));
+    if (!ws || ws_bytes < plan + fdk::abia_persistent_workspace_elems(g, p.nmax) * esz) return FD_ERR_WORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    int32_t* planp = static_cast<int32_t*>(ws);
+    void* abws = static_cast<char*>(ws) + plan;
+    if (m->dtype == FD_F64)
+        return from_hip(fdk::launch_abia_persistent<double>(view<double>(m), p.cm, p.nmax, g, (const double*)q,
+                                                            (const double*)qd, (const double*)tau, (double*)qdd,
+                                                            (double*)abws, planp, st));
+    return from_hip(fdk::launch_abia_persistent<float>(view<float>(m), p.cm, p.nmax, g, (const float*)q,
+                                                       (const float*)qd, (const float*)tau, (float*)qdd, (float*)abws,
+                                                       planp, st));
+}
+
+fd_status_t fd_backward_workspace_size(const fd_model_t* m, const fd_batch_t* b, size_t* bytes) {
+    if (!bytes) return FD_ERR_INVALID_ARG;
+    BatchPlan p;
+    fd_status_t s = plan_batch(m, b, &p);
+    if (s != FD_OK) return s;
+    const size_t esz = m->dtype == FD_F64 ? sizeof(double) : sizeof(float);
+    *bytes = fdk::vjp_workspace_elems(b->batch, p.nmax) * esz;
+    return FD_OK;
+}
+
+fd_status_t fd_backward(const fd_model_t* m, const fd_batch_t* b, const void* q, const void* qd, const void* qdd,
+                        const void* gqdd, void* gq, void* gqd, void* gtau, int accumulate, void* ws, size_t ws_bytes,
+                        void* hip_stream) {
+    BatchPlan p;
+    fd_status_t s = plan_batch(m, b, &p);
+    if (s != FD_OK) return s;
+    if (b->batch == 0) return FD_OK;
+    if (!q || !qd || !qdd || !gqdd || !gq || !gqd || !gtau) return FD_ERR_INVALID_ARG;
+    const size_t esz = m->dtype == FD_F64 ? sizeof(double) : sizeof(float);
+    if (!ws || ws_bytes < fdk::vjp_workspace_elems(b->batch, p.nmax) * esz) return FD_ERR_WORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (m->dtype == FD_F64)
+        return from_hip(fdk::launch_fd_vjp<double>(view<double>(m), p.cm, p.nmax, (const double*)q, (const double*)qd,
+                                                   (const double*)qdd, (const double*)gqdd, (double*)gq, (double*)gqd,
+                                                   (double*)gtau, accumulate, (double*)ws, st));
+    return from_hip(fdk::launch_fd_vjp<float>(view<float>(m), p.cm, p.nmax, (const float*)q, (const float*)qd,
+                                              (const float*)qdd, (const float*)gqdd, (float*)gq, (float*)gqd,
+                                              (float*)gtau, accumulate, (float*)ws, st));
+}
+
+fd_status_t fd_euler_step(fd_dtype_t dtype, int64_t count, double dt, const void* q, const void* qd, const void* qdd,
+                          void* qn, void* qdn, void* hip_stream) {
+    if ((dtype != FD_F64 && dtype != FD_F32) || count < 0 || !std::isfinite(dt)) return FD_ERR_INVALID_ARG;
+    if (count == 0) return FD_OK;
+    if (!q || !qd || !qdd || !qn || !qdn) return FD_ERR_INVALID_ARG;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (dtype == FD_F64)
+        return from_hip(fdk::launch_euler<double>(count, dt, (const double*)q, (const double*)qd, (const double*)qdd,
+                                                  (double*)qn, (double*)qdn, st));
+    return from_hip(fdk::launch_euler<float>(count, (float)dt, (const float*)q, (const float*)qd, (const float*)qdd,
+                                             (float*)qn, (float*)qdn, st));
+}
+
+fd_status_t fd_euler_step_backward(fd_dtype_t dtype, int64_t count, double dt, const void* gqn, const void* gqdn,
+                                   void* gq, void* gqd, void* gqdd, void* hip_stream) {
+    if ((dtype != FD_F64 && dtype != FD_F32) || count < 0 || !std::isfinite(dt)) return FD_ERR_INVALID_ARG;
+    if (count == 0) return FD_OK;
+    if (!gqn || !gqdn || !gq || !gqd || !gqdd) return FD_ERR_INVALID_ARG;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (dtype == FD_F64)
+        return from_hip(fdk::launch_euler_vjp<double>(count, dt, (const double*)gqn, (const double*)gqdn, (double*)gq,
+                                                      (double*)gqd, (double*)gqdd, st));
+    return from_hip(fdk::launch_euler_vjp<float>(count, (float)dt, (const float*)gqn, (const float*)gqdn, (float*)gq,
+                                                 (float*)gqd, (float*)gqdd, st));
+}
+
 fd_status_t fd_inverse(const fd_model_t* m, const fd_batch_t* b, const void* q, const void* qd, const void* qdd,
                        int gravity, void* tau, void* hip_stream) {
     BatchPlan p;

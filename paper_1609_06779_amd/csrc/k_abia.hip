@@ -55,17 +55,13 @@ template <typename T> __device__ __forceinline__ void congruence_to_parent(const
     for (int r = 0; r < 6; ++r) wrench_to_parent(t, w + 6 * r, y + 6 * r);
 }
 
+// One chain on one lane. wsb: this lane's workspace column, field f of link i
+// at wsb[(i * ABIA_WS_FIELDS + f) * 64].
 template <typename T>
-__global__ __launch_bounds__(64) void k_abia(ModelView<T> m, ChainMap cm, int nmax, const T* __restrict__ q,
-                                             const T* __restrict__ qd, const T* __restrict__ tau,
-                                             T* __restrict__ qdd, T* __restrict__ ws) {
-    const int lane = threadIdx.x;
-    const int b = blockIdx.x * 64 + lane;
-    if (b >= cm.batch) return;
-    const ChainInfo ci = chain_info(m, cm, b);
+__device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInfo& ci, const T* __restrict__ q,
+                                           const T* __restrict__ qd, const T* __restrict__ tau,
+                                           T* __restrict__ qdd, T* __restrict__ wsb) {
     const int n = ci.n;
-    // workspace: [block][link][field][lane]
-    T* wsb = ws + (size_t)blockIdx.x * nmax * ABIA_WS_FIELDS * 64 + lane;
     auto wsat = [&](int i, int f) -> T& { return wsb[((size_t)i * ABIA_WS_FIELDS + f) * 64]; };
 
     // sweep 1
@@ -157,6 +153,109 @@ __global__ __launch_bounds__(64) void k_abia(ModelView<T> m, ChainMap cm, int nm
 }
 
 template <typename T>
+__global__ __launch_bounds__(64) void k_abia(ModelView<T> m, ChainMap cm, int nmax, const T* __restrict__ q,
+                                             const T* __restrict__ qd, const T* __restrict__ tau,
+                                             T* __restrict__ qdd, T* __restrict__ ws) {
+    const int lane = threadIdx.x;
+    const int b = blockIdx.x * 64 + lane;
+    if (b >= cm.batch) return;
+    // workspace: [block][link][field][lane]
+    abia_chain(m, chain_info(m, cm, b), q, qd, tau, qdd, ws + (size_t)blockIdx.x * nmax * ABIA_WS_FIELDS * 64 + lane);
+}
+
+// Persistent form for ragged batches: each wavefront takes 64-chain tiles of
+// `order` (chains sorted by decreasing length) from an atomic counter until
+// the list is exhausted, so lanes of a tile have nearly equal lengths and the
+// longest tiles go first. Every wavefront leaves once a tile index runs past
+// the list, so the grid always drains.
+template <typename T>
+__global__ __launch_bounds__(64) void k_abia_persistent(ModelView<T> m, ChainMap cm, int nmax,
+                                                        const int32_t* __restrict__ order, int32_t* counter,
+                                                        const T* __restrict__ q, const T* __restrict__ qd,
+                                                        const T* __restrict__ tau, T* __restrict__ qdd,
+                                                        T* __restrict__ ws) {
+    __shared__ int tile_s;
+    const int lane = threadIdx.x;
+    T* wsb = ws + (size_t)blockIdx.x * nmax * ABIA_WS_FIELDS * 64 + lane;
+    for (;;) {
+        if (lane == 0) tile_s = atomicAdd(counter, 1);
+        __syncthreads();
+        const int tile = tile_s;
+        __syncthreads();
+        if ((int64_t)tile * 64 >= cm.batch) break;
+        const int k = tile * 64 + lane;
+        if (k < cm.batch) abia_chain(m, chain_info(m, cm, order[k]), q, qd, tau, qdd, wsb);
+    }
+}
+
+// ---- planning kernels: counting sort of the batch by decreasing chain length ----
+// bins / cursor: int32[KMAX_LINKS + 2]; bins[n] counts chains of n links (n = 0:
+// chains with an out-of-range robot id, placed last).
+constexpr int PLAN_BINS = 258;
+
+__global__ void k_plan_zero(int32_t* bins, int32_t* cursor, int32_t* counter) {
+    int t = threadIdx.x;
+    for (int k = t; k < PLAN_BINS; k += blockDim.x) {
+        bins[k] = 0;
+        cursor[k] = 0;
+    }
+    if (t == 0) *counter = 0;
+}
+
+template <typename T>
+__global__ void k_plan_hist(ModelView<T> m, ChainMap cm, int32_t* bins) {
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= cm.batch) return;
+    int n = chain_info(m, cm, b).n;
+    atomicAdd(&bins[n < PLAN_BINS ? n : 0], 1);
+}
+
+// cursor[n] = number of chains longer than n (decreasing order); chains of
+// length 0 go after all others. One block.
+__global__ void k_plan_scan(const int32_t* bins, int32_t* cursor) {
+    if (threadIdx.x != 0) return;
+    int acc = 0;
+    for (int n = PLAN_BINS - 1; n >= 1; --n) {
+        cursor[n] = acc;
+        acc += bins[n];
+    }
+    cursor[0] = acc;
+}
+
+template <typename T>
+__global__ void k_plan_scatter(ModelView<T> m, ChainMap cm, int32_t* cursor, int32_t* order) {
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= cm.batch) return;
+    int n = chain_info(m, cm, b).n;
+    int pos = atomicAdd(&cursor[n < PLAN_BINS ? n : 0], 1);
+    order[pos] = b;
+}
+
+size_t persistent_plan_bytes(int batch) {
+    return sizeof(int32_t) * ((size_t)batch + 2 * PLAN_BINS + 64);
+}
+
+size_t abia_persistent_workspace_elems(int grid, int nmax) { return (size_t)grid * nmax * ABIA_WS_FIELDS * 64; }
+
+template <typename T>
+hipError_t launch_abia_persistent(const ModelView<T>& m, const ChainMap& cm, int nmax, int grid, const T* q,
+                                  const T* qd, const T* tau, T* qdd, T* ws, int32_t* plan, hipStream_t st) {
+    if (cm.batch <= 0) return hipSuccess;
+    int32_t* bins = plan;
+    int32_t* cursor = bins + PLAN_BINS;
+    int32_t* counter = cursor + PLAN_BINS;
+    int32_t* order = counter + 64;
+    const unsigned g = (unsigned)((cm.batch + 255) / 256);
+    hipLaunchKernelGGL(k_plan_zero, dim3(1), dim3(256), 0, st, bins, cursor, counter);
+    hipLaunchKernelGGL((k_plan_hist<T>), dim3(g), dim3(256), 0, st, m, cm, bins);
+    hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(64), 0, st, bins, cursor);
+    hipLaunchKernelGGL((k_plan_scatter<T>), dim3(g), dim3(256), 0, st, m, cm, cursor, order);
+    hipLaunchKernelGGL((k_abia_persistent<T>), dim3(grid), dim3(64), 0, st, m, cm, nmax, order, counter, q, qd,
+                       tau, qdd, ws);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_abia(const ModelView<T>& m, const ChainMap& cm, int nmax, const T* q, const T* qd, const T* tau,
                        T* qdd, T* ws, hipStream_t st) {
     if (cm.batch <= 0) return hipSuccess;
@@ -168,5 +267,10 @@ template hipError_t launch_abia<double>(const ModelView<double>&, const ChainMap
                                         const double*, double*, double*, hipStream_t);
 template hipError_t launch_abia<float>(const ModelView<float>&, const ChainMap&, int, const float*, const float*,
                                        const float*, float*, float*, hipStream_t);
+template hipError_t launch_abia_persistent<double>(const ModelView<double>&, const ChainMap&, int, int, const double*,
+                                                   const double*, const double*, double*, double*, int32_t*,
+                                                   hipStream_t);
+template hipError_t launch_abia_persistent<float>(const ModelView<float>&, const ChainMap&, int, int, const float*,
+                                                  const float*, const float*, float*, float*, int32_t*, hipStream_t);
 
 }  // namespace fdk

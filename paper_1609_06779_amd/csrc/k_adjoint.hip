@@ -1,0 +1,324 @@
+// k_adjoint.hip -- reverse-mode derivative (vector-Jacobian product) of forward
+// dynamics, and the semi-implicit Euler step of a rollout with its adjoint.
+//
+// qdd = FD(q, qd, tau) solves ID(q, qd, qdd) = tau (eq. (eq-motion), (tau-bias)),
+// so for a cotangent g of qdd the implicit-function theorem gives
+//     lambda = M^-1 g,   tau_bar = lambda,
+//     [q_bar; qd_bar] = -(d ID / d(q, qd))^T lambda   at qdd = FD(q, qd, tau).
+// lambda comes from the articulated-body factorisation of M^-1 (Sec. II-C),
+// applied to g with zero velocity and no gravity. (d ID / d(q, qd))^T lambda is
+// the reverse of the inverse-dynamics recursions of eq. (EOM-full): with
+// A_i = Ad(T_{i-1,i}^-1) and S = e3 in the canonical joint frames,
+//   forward  (recomputed): V_i = A_i V_{i-1} + S qd_i,
+//                          a_i = A_i a_{i-1} + S qdd_i + ad_{V_i}(S qd_i),
+//                          f_i = J_i a_i - ad_{V_i}^T J_i V_i,
+//   backward (recomputed): F_i = f_i + A_{i+1}^T F_{i+1},  tau_i = S^T F_i;
+//   adjoint, forward in i: Fb_i = lambda_i S + A_i Fb_{i-1}   (Fb = force adjoint),
+//   adjoint, backward in i:
+//     ab_i = J_i Fb_i + A_{i+1}^T ab_{i+1}
+//     Vb_i = ad_{Fb_i}^T (J_i V_i) - J_i ad_{V_i} Fb_i - ad_{S qd_i}^T ab_i + A_{i+1}^T Vb_{i+1}
+//     (dID/dqd)^T lambda |_i = S . Vb_i + S . ad_{V_i}^T ab_i
+//     (dID/dq)^T lambda |_i  = -Vb_i . ad_S V_i - ab_i . ad_S (a_i - ad_{V_i}(S qd_i))
+//                              - (ad_S A_i Fb_{i-1}) . F_i
+// using d A_i / d q_i = -ad_S A_i. One lane per chain, robot-interleaved model.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+#include "spatial.h"
+
+namespace fdk {
+
+// workspace fields per link (block-interleaved like the ABIA workspace)
+constexpr int VJP_HD = 0;      // h / D (6), then lambda (field 0) and the force-term q_bar (field 1)
+constexpr int VJP_UD = 6;      // u / D
+constexpr int VJP_V = 7;       // V (6)
+constexpr int VJP_A = 13;      // a (6)
+constexpr int VJP_F = 19;      // f -> F -> Fb (6)
+constexpr int VJP_FIELDS = 25;
+
+size_t vjp_workspace_elems(int batch, int nmax) {
+    size_t blocks = (size_t)(batch + 63) / 64;
+    return blocks * (size_t)nmax * VJP_FIELDS * 64;
+}
+
+template <typename T>
+__device__ __forceinline__ Pose<T> pose_il(const ModelView<T>& m, int i, int r, T q) {
+    T rh[9], p[3];
+    m.home_il(i, r, rh, p);
+    return joint_pose(rh, p, q);
+}
+
+// Y = X^T P X for X = Ad(T^-1) and symmetric P
+template <typename T> __device__ __forceinline__ void congruence_up(const Pose<T>& t, const T p[36], T y[36]) {
+    T w[36];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        T col[6], out[6];
+#pragma unroll
+        for (int r = 0; r < 6; ++r) col[r] = p[6 * r + c];
+        wrench_to_parent(t, col, out);
+#pragma unroll
+        for (int r = 0; r < 6; ++r) w[6 * r + c] = out[r];
+    }
+#pragma unroll
+    for (int r = 0; r < 6; ++r) wrench_to_parent(t, w + 6 * r, y + 6 * r);
+}
+
+// ad_S x for S = e3 (rotation about z): (z x x_w; z x x_v)
+template <typename T> __device__ __forceinline__ void ad_z(const T x[6], T y[6]) {
+    y[0] = -x[1]; y[1] = x[0]; y[2] = T(0);
+    y[3] = -x[4]; y[4] = x[3]; y[5] = T(0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int nmax, const T* __restrict__ q,
+                                               const T* __restrict__ qd, const T* __restrict__ qdd,
+                                               const T* __restrict__ gqdd, T* __restrict__ gq,
+                                               T* __restrict__ gqd, T* __restrict__ gtau, int accumulate,
+                                               T* __restrict__ ws) {
+    const int lane = threadIdx.x;
+    const int b = blockIdx.x * 64 + lane;
+    if (b >= cm.batch) return;
+    const ChainInfo ci = chain_info(m, cm, b);
+    const int n = ci.n;
+    const int r = ci.robot;
+    T* wsb = ws + (size_t)blockIdx.x * nmax * VJP_FIELDS * 64 + lane;
+    auto w = [&](int i, int f) -> T& { return wsb[((size_t)i * VJP_FIELDS + f) * 64]; };
+
+    // A: articulated-body inertias and the p recursion with tau_delta := g
+    {
+        T pc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+        T pi[36];
+#pragma unroll
+        for (int c = 0; c < 36; ++c) pi[c] = T(0);
+        Pose<T> tn = pose_identity<T>();
+        for (int i = n - 1; i >= 0; --i) {
+            const int64_t st = ci.state0 + i;
+            T jh[36], pp[6];
+            inertia_to_mat6(m.inertia_il(i, r), jh);
+            if (i + 1 < n) {
+                wrench_to_parent(tn, pc, pp);
+                T y[36];
+                congruence_up(tn, pi, y);
+#pragma unroll
+                for (int c = 0; c < 36; ++c) jh[c] += y[c];
+            } else {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) pp[c] = T(0);
+            }
+            const T dinv = T(1) / jh[14];
+            const T u = gqdd[st] - pp[2];
+            T h[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) h[c] = jh[6 * c + 2];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) w(i, VJP_HD + c) = h[c] * dinv;
+            w(i, VJP_UD) = u * dinv;
+#pragma unroll
+            for (int rr = 0; rr < 6; ++rr)
+#pragma unroll
+                for (int c = 0; c < 6; ++c) pi[6 * rr + c] = jh[6 * rr + c] - h[rr] * h[c] * dinv;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) pc[c] = pp[c] + h[c] * u * dinv;
+            tn = pose_il(m, i, r, q[st]);
+        }
+    }
+    // B: lambda, and the inverse dynamics forward sweep at the given qdd
+    {
+        T acc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+        T v[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+        T a[6] = {T(0), T(0), T(0), -m.g[0], -m.g[1], -m.g[2]};
+        for (int i = 0; i < n; ++i) {
+            const int64_t st = ci.state0 + i;
+            const Pose<T> tl = pose_il(m, i, r, q[st]);
+            T t[6];
+            ad_inv_apply(tl, acc, t);
+            T lam = w(i, VJP_UD);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) lam -= w(i, VJP_HD + c) * t[c];
+            t[2] += lam;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) acc[c] = t[c];
+            w(i, VJP_HD) = lam;
+            gtau[st] = accumulate ? gtau[st] + lam : lam;
+
+            const T qdi = qd[st];
+            ad_inv_apply(tl, v, t);
+            t[2] += qdi;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) v[c] = t[c];
+            ad_inv_apply(tl, a, t);
+            t[2] += qdd[st];
+            t[0] += v[1] * qdi; t[1] -= v[0] * qdi;      // + ad_V (S qd) = (w x z qd; v x z qd)
+            t[3] += v[4] * qdi; t[4] -= v[3] * qdi;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) a[c] = t[c];
+            T f[6];
+            link_force(m.inertia_il(i, r), v, a, f);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                w(i, VJP_V + c) = v[c];
+                w(i, VJP_A + c) = a[c];
+                w(i, VJP_F + c) = f[c];
+            }
+        }
+    }
+    // C: force recursion F_i = f_i + A_{i+1}^T F_{i+1}
+    {
+        T fc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+        Pose<T> tn = pose_identity<T>();
+        for (int i = n - 1; i >= 0; --i) {
+            T f[6], fp[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) f[c] = w(i, VJP_F + c);
+            if (i + 1 < n) {
+                wrench_to_parent(tn, fc, fp);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) f[c] += fp[c];
+            }
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                fc[c] = f[c];
+                w(i, VJP_F + c) = f[c];
+            }
+            tn = pose_il(m, i, r, q[ci.state0 + i]);
+        }
+    }
+    // D: Fb_i = lambda_i S + A_i Fb_{i-1}; force term of q_bar
+    {
+        T fb[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+        for (int i = 0; i < n; ++i) {
+            const Pose<T> tl = pose_il(m, i, r, q[ci.state0 + i]);
+            T t[6], z[6];
+            ad_inv_apply(tl, fb, t);           // A_i Fb_{i-1}
+            T qf = T(0);
+            if (i > 0) {
+                ad_z(t, z);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) qf -= z[c] * w(i, VJP_F + c);
+            }
+            t[2] += w(i, VJP_HD);              // + lambda_i S
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                fb[c] = t[c];
+                w(i, VJP_F + c) = t[c];
+            }
+            w(i, VJP_HD + 1) = qf;
+        }
+    }
+    // E: adjoints of the velocity and acceleration recursions
+    {
+        T ab[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+        T vb[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+        Pose<T> tn = pose_identity<T>();
+        for (int i = n - 1; i >= 0; --i) {
+            const int64_t st = ci.state0 + i;
+            const Inertia<T> j = m.inertia_il(i, r);
+            T fb[6], v[6], a[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                fb[c] = w(i, VJP_F + c);
+                v[c] = w(i, VJP_V + c);
+                a[c] = w(i, VJP_A + c);
+            }
+            T na[6], nv[6];
+            if (i + 1 < n) {
+                wrench_to_parent(tn, ab, na);
+                wrench_to_parent(tn, vb, nv);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) na[c] = nv[c] = T(0);
+            }
+            T jf[6];
+            inertia_apply(j, fb, jf);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) ab[c] = jf[c] + na[c];
+            T jv[6], t1[6], avf[6], t2[6];
+            inertia_apply(j, v, jv);
+            ad_twist_T(fb, jv, t1);
+            ad_twist(v, fb, avf);
+            inertia_apply(j, avf, t2);
+            const T qdi = qd[st];
+            // -ad_{S qd}^T ab = (z qd x ab_w; z qd x ab_v)
+            const T sa[6] = {-qdi * ab[1], qdi * ab[0], T(0), -qdi * ab[4], qdi * ab[3], T(0)};
+#pragma unroll
+            for (int c = 0; c < 6; ++c) vb[c] = t1[c] - t2[c] + sa[c] + nv[c];
+            T avt[6];
+            ad_twist_T(v, ab, avt);
+            const T gqd_id = vb[2] + avt[2];
+            // q terms
+            T zv[6], avs[6], am[6], za[6];
+            ad_z(v, zv);
+            const T sqd[6] = {T(0), T(0), qdi, T(0), T(0), T(0)};
+            ad_twist(v, sqd, avs);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) am[c] = a[c] - avs[c];
+            ad_z(am, za);
+            T gq_id = w(i, VJP_HD + 1);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) gq_id -= vb[c] * zv[c] + ab[c] * za[c];
+            gq[st] = accumulate ? gq[st] - gq_id : -gq_id;
+            gqd[st] = accumulate ? gqd[st] - gqd_id : -gqd_id;
+            tn = pose_il(m, i, r, q[st]);
+        }
+    }
+}
+
+// qd' = qd + dt qdd, q' = q + dt qd' (semi-implicit Euler). Elementwise over count entries.
+template <typename T>
+__global__ void k_euler(int64_t count, T dt, const T* __restrict__ q, const T* __restrict__ qd,
+                        const T* __restrict__ qdd, T* __restrict__ qn, T* __restrict__ qdn) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    const T v = qd[k] + dt * qdd[k];
+    qn[k] = q[k] + dt * v;
+    qdn[k] = v;
+}
+
+// Adjoint of k_euler: from (q'_bar, qd'_bar) to q_bar, qd_bar and qdd_bar (overwritten).
+template <typename T>
+__global__ void k_euler_vjp(int64_t count, T dt, const T* __restrict__ gqn, const T* __restrict__ gqdn,
+                            T* __restrict__ gq, T* __restrict__ gqd, T* __restrict__ gqdd) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    const T gv = gqdn[k] + dt * gqn[k];
+    gq[k] = gqn[k];
+    gqd[k] = gv;
+    gqdd[k] = dt * gv;
+}
+
+template <typename T>
+hipError_t launch_fd_vjp(const ModelView<T>& m, const ChainMap& cm, int nmax, const T* q, const T* qd, const T* qdd,
+                         const T* gqdd, T* gq, T* gqd, T* gtau, int accumulate, T* ws, hipStream_t st) {
+    if (cm.batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_fd_vjp<T>), dim3((cm.batch + 63) / 64), dim3(64), 0, st, m, cm, nmax, q, qd, qdd, gqdd, gq,
+                       gqd, gtau, accumulate, ws);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_euler(int64_t count, T dt, const T* q, const T* qd, const T* qdd, T* qn, T* qdn, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_euler<T>), dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, count, dt, q, qd, qdd,
+                       qn, qdn);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_euler_vjp(int64_t count, T dt, const T* gqn, const T* gqdn, T* gq, T* gqd, T* gqdd,
+                            hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_euler_vjp<T>), dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, count, dt, gqn,
+                       gqdn, gq, gqd, gqdd);
+    return hipGetLastError();
+}
+
+#define FDK_ADJ_INST(T)                                                                                          \
+    template hipError_t launch_fd_vjp<T>(const ModelView<T>&, const ChainMap&, int, const T*, const T*, const T*, \
+                                         const T*, T*, T*, T*, int, T*, hipStream_t);                           \
+    template hipError_t launch_euler<T>(int64_t, T, const T*, const T*, const T*, T*, T*, hipStream_t);          \
+    template hipError_t launch_euler_vjp<T>(int64_t, T, const T*, const T*, T*, T*, T*, hipStream_t);
+FDK_ADJ_INST(double)
+FDK_ADJ_INST(float)
+
+}  // namespace fdk

@@ -37,6 +37,22 @@ template <typename T>
 hipError_t launch_abia(const ModelView<T>& m, const ChainMap& cm, int nmax, const T* q, const T* qd,
                        const T* tau, T* qdd, T* ws, hipStream_t st);
 size_t abia_workspace_elems(int batch, int nmax);
+// ragged batches: one persistent launch over chains sorted by decreasing length
+size_t persistent_plan_bytes(int batch);
+size_t abia_persistent_workspace_elems(int grid, int nmax);
+template <typename T>
+hipError_t launch_abia_persistent(const ModelView<T>& m, const ChainMap& cm, int nmax, int grid, const T* q,
+                                  const T* qd, const T* tau, T* qdd, T* ws, int32_t* plan, hipStream_t st);
+
+// reverse mode and the rollout step
+size_t vjp_workspace_elems(int batch, int nmax);
+template <typename T>
+hipError_t launch_fd_vjp(const ModelView<T>& m, const ChainMap& cm, int nmax, const T* q, const T* qd, const T* qdd,
+                         const T* gqdd, T* gq, T* gqd, T* gtau, int accumulate, T* ws, hipStream_t st);
+template <typename T>
+hipError_t launch_euler(int64_t count, T dt, const T* q, const T* qd, const T* qdd, T* qn, T* qdn, hipStream_t st);
+template <typename T>
+hipError_t launch_euler_vjp(int64_t count, T dt, const T* gqn, const T* gqdn, T* gq, T* gqd, T* gqdd, hipStream_t st);
 
 // building blocks
 template <typename T>

@@ -40,6 +40,18 @@ def _c(a, dtype=np.float64):
     return np.ascontiguousarray(a, dtype=dtype)
 
 
+_TABLE_LOADED = False
+
+
+def _load_tuning():
+    """Hand the tuned AUTO table (measured on gfx950 by tune.py) to the library once."""
+    global _TABLE_LOADED
+    if not _TABLE_LOADED:
+        from . import tune
+        tune.load_table()
+        _TABLE_LOADED = True
+
+
 class Model:
     """A robot set uploaded to the GPU in one precision ('f64' or 'f32').
 
@@ -49,6 +61,7 @@ class Model:
 
     def __init__(self, robots, dtype: str = "f64", device=None):
         lib = _lib.load()
+        _load_tuning()
         if dtype not in _lib.DTYPES:
             raise ValueError(f"dtype must be one of {list(_lib.DTYPES)}")
         self.dtype = dtype
@@ -126,6 +139,72 @@ class Model:
                    "fd_forward")
         return out
 
+    def persistent_workspace(self, batch: int, grid: int = 0, robot_id=None, offsets=None):
+        n = ctypes.c_size_t()
+        b = self._batch(batch, robot_id, offsets)
+        _lib.check(_lib.load().fd_persistent_workspace_size(self._h, ctypes.byref(b), int(grid), ctypes.byref(n)),
+                   "fd_persistent_workspace_size")
+        return torch.empty(max(int(n.value), 1), dtype=torch.uint8, device=self.device)
+
+    def forward_persistent(self, q, qd, tau, batch: int, grid: int = 0, robot_id=None, offsets=None, out=None,
+                           workspace=None, stream=None):
+        """qdd for a (ragged) batch in one persistent launch, chains sorted by length on the device."""
+        dt = self.torch_dtype
+        for name, t in (("q", q), ("qd", qd), ("tau", tau)):
+            _dev_tensor(t, dt, self.device, name)
+        out = torch.empty_like(q) if out is None else _dev_tensor(out, dt, self.device, "out")
+        b = self._batch(batch, robot_id, offsets)
+        if workspace is None:
+            workspace = self.persistent_workspace(batch, grid, robot_id, offsets)
+        _lib.check(_lib.load().fd_forward_persistent(self._h, ctypes.byref(b), _ptr(q), _ptr(qd), _ptr(tau),
+                                                     _ptr(out), int(grid), _ptr(workspace), workspace.numel(),
+                                                     _stream(stream)), "fd_forward_persistent")
+        return out
+
+    def backward_workspace(self, batch: int, robot_id=None, offsets=None):
+        n = ctypes.c_size_t()
+        b = self._batch(batch, robot_id, offsets)
+        _lib.check(_lib.load().fd_backward_workspace_size(self._h, ctypes.byref(b), ctypes.byref(n)),
+                   "fd_backward_workspace_size")
+        return torch.empty(max(int(n.value), 1), dtype=torch.uint8, device=self.device)
+
+    def backward(self, q, qd, qdd, grad_qdd, batch: int, robot_id=None, offsets=None, grad_q=None, grad_qd=None,
+                 grad_tau=None, accumulate: bool = False, workspace=None, stream=None):
+        """Vector-Jacobian product of forward dynamics at (q, qd, qdd = FD(q, qd, tau)):
+        returns (grad_q, grad_qd, grad_tau) for the cotangent grad_qdd."""
+        dt = self.torch_dtype
+        for name, t in (("q", q), ("qd", qd), ("qdd", qdd), ("grad_qdd", grad_qdd)):
+            _dev_tensor(t, dt, self.device, name)
+        grad_q = torch.empty_like(q) if grad_q is None else _dev_tensor(grad_q, dt, self.device, "grad_q")
+        grad_qd = torch.empty_like(q) if grad_qd is None else _dev_tensor(grad_qd, dt, self.device, "grad_qd")
+        grad_tau = torch.empty_like(q) if grad_tau is None else _dev_tensor(grad_tau, dt, self.device, "grad_tau")
+        b = self._batch(batch, robot_id, offsets)
+        if workspace is None:
+            workspace = self.backward_workspace(batch, robot_id, offsets)
+        _lib.check(_lib.load().fd_backward(self._h, ctypes.byref(b), _ptr(q), _ptr(qd), _ptr(qdd), _ptr(grad_qdd),
+                                           _ptr(grad_q), _ptr(grad_qd), _ptr(grad_tau), int(bool(accumulate)),
+                                           _ptr(workspace), workspace.numel(), _stream(stream)), "fd_backward")
+        return grad_q, grad_qd, grad_tau
+
+    def euler_step(self, q, qd, qdd, dt: float, q_next=None, qd_next=None, stream=None):
+        """qd_next = qd + dt qdd, q_next = q + dt qd_next (outputs may be the inputs)."""
+        q_next = torch.empty_like(q) if q_next is None else q_next
+        qd_next = torch.empty_like(q) if qd_next is None else qd_next
+        _lib.check(_lib.load().fd_euler_step(_lib.DTYPES[self.dtype], q.numel(), float(dt), _ptr(q), _ptr(qd),
+                                             _ptr(qdd), _ptr(q_next), _ptr(qd_next), _stream(stream)), "fd_euler_step")
+        return q_next, qd_next
+
+    def euler_step_backward(self, grad_q_next, grad_qd_next, dt: float, grad_q=None, grad_qd=None, grad_qdd=None,
+                            stream=None):
+        grad_q = torch.empty_like(grad_q_next) if grad_q is None else grad_q
+        grad_qd = torch.empty_like(grad_q_next) if grad_qd is None else grad_qd
+        grad_qdd = torch.empty_like(grad_q_next) if grad_qdd is None else grad_qdd
+        _lib.check(_lib.load().fd_euler_step_backward(_lib.DTYPES[self.dtype], grad_q_next.numel(), float(dt),
+                                                      _ptr(grad_q_next), _ptr(grad_qd_next), _ptr(grad_q),
+                                                      _ptr(grad_qd), _ptr(grad_qdd), _stream(stream)),
+                   "fd_euler_step_backward")
+        return grad_q, grad_qd, grad_qdd
+
     def inverse(self, q, qd, qdd, batch: int, gravity: bool = True, robot_id=None, offsets=None, out=None,
                 stream=None):
         """tau = M(q) qdd + tau_bias(q, qd) (qdd None = 0)."""
@@ -184,3 +263,82 @@ def btd_solve6(d, u, r, offsets, max_len: int, out=None, status=None, stream=Non
                                          _ptr(d), _ptr(u), _ptr(r), _ptr(out), _ptr(status), _stream(stream)),
                "fd_btd_solve6")
     return out, status
+
+
+class _ForwardDynamics(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, q, qd, tau, model, batch, algo, robot_id, offsets):
+        qdd = model.forward(q.detach(), qd.detach(), tau.detach(), batch=batch, algo=algo, robot_id=robot_id,
+                            offsets=offsets)
+        ctx.model, ctx.batch, ctx.robot_id, ctx.offsets = model, batch, robot_id, offsets
+        ctx.save_for_backward(q.detach(), qd.detach(), qdd)
+        return qdd
+
+    @staticmethod
+    def backward(ctx, grad_qdd):
+        q, qd, qdd = ctx.saved_tensors
+        gq, gqd, gtau = ctx.model.backward(q, qd, qdd, grad_qdd.contiguous(), batch=ctx.batch,
+                                           robot_id=ctx.robot_id, offsets=ctx.offsets)
+        return gq, gqd, gtau, None, None, None, None, None
+
+
+def forward_dynamics(model: Model, q, qd, tau, batch: int, algo: str = "auto", robot_id=None, offsets=None):
+    """Differentiable qdd = FD(q, qd, tau): gradients come from fd_backward."""
+    return _ForwardDynamics.apply(q, qd, tau, model, batch, algo, robot_id, offsets)
+
+
+class _Rollout(torch.autograd.Function):
+    """T semi-implicit Euler steps of forward dynamics; the backward pass keeps
+    (q, qd) every ``every`` steps and recomputes each segment before reversing it."""
+
+    @staticmethod
+    def forward(ctx, q0, qd0, taus, model, batch, dt, every, algo):
+        n_steps = taus.shape[0]
+        q, qd = q0.detach().clone(), qd0.detach().clone()
+        qdd = torch.empty_like(q)
+        ws = model.workspace(batch, algo)
+        checkpoints = []
+        for t in range(n_steps):
+            if t % every == 0:
+                checkpoints.append((q.clone(), qd.clone()))
+            model.forward(q, qd, taus[t], batch=batch, algo=algo, out=qdd, workspace=ws)
+            model.euler_step(q, qd, qdd, dt, q_next=q, qd_next=qd)
+        ctx.model, ctx.batch, ctx.dt, ctx.every, ctx.algo = model, batch, dt, every, algo
+        ctx.checkpoints = checkpoints
+        ctx.save_for_backward(taus.detach())
+        return q, qd
+
+    @staticmethod
+    def backward(ctx, gq_t, gqd_t):
+        (taus,) = ctx.saved_tensors
+        model, batch, dt, every, algo = ctx.model, ctx.batch, ctx.dt, ctx.every, ctx.algo
+        n_steps = taus.shape[0]
+        gq = gq_t.detach().clone().contiguous()
+        gqd = gqd_t.detach().clone().contiguous()
+        gtaus = torch.zeros_like(taus)
+        gqdd = torch.empty_like(gq)
+        fws = model.workspace(batch, algo)
+        bws = model.backward_workspace(batch)
+        for seg in range(len(ctx.checkpoints) - 1, -1, -1):
+            t0 = seg * every
+            t1 = min(n_steps, t0 + every)
+            q, qd = ctx.checkpoints[seg]
+            states = []
+            q, qd = q.clone(), qd.clone()
+            for t in range(t0, t1):                      # recompute the segment
+                qdd = torch.empty_like(q)
+                model.forward(q, qd, taus[t], batch=batch, algo=algo, out=qdd, workspace=fws)
+                states.append((q, qd, qdd))
+                q, qd = model.euler_step(q, qd, qdd, dt)
+            for t in range(t1 - 1, t0 - 1, -1):          # reverse it
+                qs, qds, qdds = states[t - t0]
+                model.euler_step_backward(gq, gqd, dt, grad_q=gq, grad_qd=gqd, grad_qdd=gqdd)
+                model.backward(qs, qds, qdds, gqdd, batch=batch, grad_q=gq, grad_qd=gqd, grad_tau=gtaus[t],
+                               accumulate=True, workspace=bws)
+        return gq, gqd, gtaus, None, None, None, None, None
+
+
+def rollout(model: Model, q0, qd0, taus, batch: int, dt: float, every: int = 10, algo: str = "auto"):
+    """Differentiable (q_T, qd_T) after T = taus.shape[0] semi-implicit Euler steps of
+    forward dynamics with step dt, checkpointing (q, qd) every ``every`` steps."""
+    return _Rollout.apply(q0, qd0, taus, model, batch, float(dt), int(every), algo)

@@ -117,6 +117,49 @@ def table_array(entry):
     return arr
 
 
+def ragged_grid(dtype: str, path=DEFAULT_TABLE) -> int:
+    """Persistent grid size for ragged batches chosen by ``tune_ragged`` (0 = resident capacity)."""
+    if not os.path.exists(path):
+        return 0
+    return int(json.load(open(path)).get("ragged_grid", {}).get(dtype, 0))
+
+
+def tune_ragged(dtype: str = "f64", batch: int = 100000, lo: int = 4, hi: int = 256, reps: int = 5, log=None):
+    """Time the persistent launch over grid sizes (multiples of the CU count) on a
+    ragged batch like the ragged workload and return {grid: ms}."""
+    import torch
+
+    from . import fd, synth
+
+    dev = torch.device("cuda:0")
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    lengths = synth.ragged_lengths(batch, lo, hi, cfg=3)
+    rb = synth.make_robots(lengths, cfg=3)
+    q, qd, tau = synth.make_state(lengths, cfg=3)
+    model = fd.Model(rb, dtype, device=dev)
+    tq, tqd, ttau = (torch.from_numpy(a).to(dev, tdt) for a in (q, qd, tau))
+    toff = torch.from_numpy(rb.offsets).to(dev)
+    out = torch.empty_like(tq)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    res = {}
+    for per_cu in (1, 2, 3, 4, 6, 8, 12, 16):
+        grid = cus * per_cu
+        ws = model.persistent_workspace(batch, grid, offsets=toff)
+        model.forward_persistent(tq, tqd, ttau, batch=batch, grid=grid, offsets=toff, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            model.forward_persistent(tq, tqd, ttau, batch=batch, grid=grid, offsets=toff, out=out, workspace=ws)
+        b.record()
+        torch.cuda.synchronize()
+        res[grid] = a.elapsed_time(b) / reps
+        if log:
+            print(json.dumps({"ragged_grid": grid, "dtype": dtype, "ms": res[grid]}), file=log, flush=True)
+    model.close()
+    return res
+
+
 def load_table(path=DEFAULT_TABLE):
     """Hand the tuned table to the library (per precision). Returns False if there is none."""
     if not os.path.exists(path):
@@ -140,14 +183,24 @@ def main():
     ap.add_argument("--dtypes", default="f64,f32")
     ap.add_argument("--ns", default=",".join(map(str, N_GRID)))
     ap.add_argument("--batches", default=",".join(map(str, BATCH_GRID)))
+    ap.add_argument("--ragged-only", action="store_true", help="keep the existing sweep, redo the ragged grid")
     args = ap.parse_args()
     import torch
 
-    rows = []
+    if args.ragged_only and os.path.exists(args.out):
+        data = json.load(open(args.out))
+    else:
+        rows = []
+        for dtype in args.dtypes.split(","):
+            rows += sweep(tuple(int(x) for x in args.ns.split(",")), tuple(int(x) for x in args.batches.split(",")),
+                          dtype=dtype, log=sys.stderr)
+        data = {"arch": torch.cuda.get_device_properties(0).gcnArchName, "rows": rows, "best": best_table(rows)}
+    data["ragged_timings"] = {}
+    data["ragged_grid"] = {}
     for dtype in args.dtypes.split(","):
-        rows += sweep(tuple(int(x) for x in args.ns.split(",")), tuple(int(x) for x in args.batches.split(",")),
-                      dtype=dtype, log=sys.stderr)
-    data = {"arch": torch.cuda.get_device_properties(0).gcnArchName, "rows": rows, "best": best_table(rows)}
+        res = tune_ragged(dtype, log=sys.stderr)
+        data["ragged_timings"][dtype] = {str(k): v for k, v in res.items()}
+        data["ragged_grid"][dtype] = int(min(res, key=res.get))
     with open(args.out, "w") as f:
         json.dump(data, f, indent=1)
     print(json.dumps(data["best"]))

@@ -1,0 +1,171 @@
+"""GPU parity of the reverse-mode derivative (fd_backward) and of the
+checkpointed rollout gradient, against the oracle's complex-step JVPs
+(exact to rounding) and central differences of the oracle.
+
+The adjoint identity <VJP(g), v> = <g, JVP(v)> is checked per chain for
+random cotangents g and directions v = (dq, dqd, dtau)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1609_06779_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def fdm():
+    from paper_1609_06779_amd import fd
+    return fd
+
+
+def _t(a, dev, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev, dtype)
+
+
+def _chain_sums(x, off):
+    return np.add.reduceat(x, off[:-1])
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 16, 32, 64, 100])
+def test_vjp_adjoint_identity(fdm, dev, n):
+    batch = 9
+    lengths = np.full(batch, n, np.int32)
+    rb = synth.make_robots(lengths, cfg=5, random_home=True)
+    q, qd, tau = synth.make_state(lengths, cfg=5)
+    off = rb.offsets
+    model = fdm.Model(rb, "f64", device=dev)
+    tq, tqd, ttau = _t(q, dev), _t(qd, dev), _t(tau, dev)
+    qdd = model.forward(tq, tqd, ttau, batch=batch, algo="abia")
+    rng = np.random.default_rng(n)
+    ms = oracle.crba(rb, q)
+    for _ in range(3):
+        g = rng.standard_normal(len(q))
+        gq, gqd, gtau = (x.cpu().numpy() for x in model.backward(tq, tqd, qdd, _t(g, dev), batch=batch))
+        # tau_bar = M^-1 g
+        for b in range(batch):
+            sl = slice(off[b], off[b + 1])
+            ref = np.linalg.solve(ms[b], g[sl])
+            bar = max(1e-10, 16 * np.linalg.cond(ms[b]) * 2.0 ** -53)
+            assert np.linalg.norm(gtau[sl] - ref) <= bar * np.linalg.norm(ref), (b, "tau_bar")
+        dq, dqd, dtau = (rng.standard_normal(len(q)) for _ in range(3))
+        _, dqdd = oracle.fd_jvp(rb, q, qd, tau, dq, dqd, dtau)
+        lhs = _chain_sums(g * dqdd, off)
+        rhs = _chain_sums(gq * dq + gqd * dqd + gtau * dtau, off)
+        scale = _chain_sums(np.abs(g * dqdd), off) + _chain_sums(np.abs(gq * dq) + np.abs(gqd * dqd) +
+                                                                 np.abs(gtau * dtau), off)
+        kappa = np.array([np.linalg.cond(m) for m in ms])
+        bar = np.maximum(1e-11, 16 * kappa * 2.0 ** -53)
+        assert np.all(np.abs(lhs - rhs) <= bar * scale), (np.abs(lhs - rhs) / scale).max()
+
+
+def test_vjp_accumulates_and_matches_autograd_function(fdm, dev):
+    lengths = np.full(6, 12, np.int32)
+    rb = synth.make_robots(lengths, cfg=5)
+    q, qd, tau = synth.make_state(lengths, cfg=5)
+    model = fdm.Model(rb, "f64", device=dev)
+    tq = _t(q, dev).requires_grad_(True)
+    tqd = _t(qd, dev).requires_grad_(True)
+    ttau = _t(tau, dev).requires_grad_(True)
+    qdd = fdm.forward_dynamics(model, tq, tqd, ttau, batch=6, algo="cfa")
+    g = torch.randn_like(qdd)
+    (qdd * g).sum().backward()
+    gq, gqd, gtau = model.backward(tq.detach(), tqd.detach(), qdd.detach(), g, batch=6)
+    assert torch.equal(tq.grad, gq) and torch.equal(tqd.grad, gqd) and torch.equal(ttau.grad, gtau)
+    a, b_, c = (x.clone() for x in (gq, gqd, gtau))
+    model.backward(tq.detach(), tqd.detach(), qdd.detach(), g, batch=6, grad_q=a, grad_qd=b_, grad_tau=c,
+                   accumulate=True)
+    assert torch.allclose(a, 2 * gq, rtol=1e-15, atol=0) and torch.allclose(c, 2 * gtau, rtol=1e-15, atol=0)
+
+
+def _oracle_rollout(rb, q, qd, taus, dt, dq=None, dqd=None, dtaus=None):
+    """(q_T, qd_T) and, with directions, their derivatives (complex-step JVP each step)."""
+    q, qd = q.copy(), qd.copy()
+    tq = None if dq is None else dq.copy()
+    tqd = None if dqd is None else dqd.copy()
+    for t in range(taus.shape[0]):
+        if tq is None:
+            qdd = oracle.fd(rb, q, qd, taus[t])
+        else:
+            qdd, dqdd = oracle.fd_jvp(rb, q, qd, taus[t], tq, tqd, dtaus[t])
+            tqd = tqd + dt * dqdd
+            tq = tq + dt * tqd
+        qd = qd + dt * qdd
+        q = q + dt * qd
+    return q, qd, tq, tqd
+
+
+@pytest.mark.parametrize("algo", ["abia", "cfa"])
+def test_rollout_gradient_matches_oracle(fdm, dev, algo):
+    """100 semi-implicit Euler steps, dt = 1e-3, loss = sum(q_T^2 + qd_T^2), gradient
+    with respect to q_0, qd_0 and every tau_t, checkpoints every 10 steps."""
+    batch, n, steps, dt = 24, 32, 100, 1e-3
+    lengths = np.full(batch, n, np.int32)
+    rb = synth.make_robots(lengths, cfg=5)
+    q0, qd0, _ = synth.make_state(lengths, cfg=5)
+    taus = np.random.default_rng(5).standard_normal((steps, len(q0)))
+    off = rb.offsets
+    model = fdm.Model(rb, "f64", device=dev)
+    tq0 = _t(q0, dev).requires_grad_(True)
+    tqd0 = _t(qd0, dev).requires_grad_(True)
+    ttaus = _t(taus, dev).requires_grad_(True)
+    qt, qdt = fdm.rollout(model, tq0, tqd0, ttaus, batch=batch, dt=dt, every=10, algo=algo)
+    loss = (qt ** 2).sum() + (qdt ** 2).sum()
+    loss.backward()
+    g0, gd0, gt = tq0.grad.cpu().numpy(), tqd0.grad.cpu().numpy(), ttaus.grad.cpu().numpy()
+    rq, rqd, _, _ = _oracle_rollout(rb, q0, qd0, taus, dt)
+    np.testing.assert_allclose(qt.detach().cpu().numpy(), rq, rtol=0, atol=1e-10 * (1 + np.abs(rq).max()))
+    rng = np.random.default_rng(55)
+    for _ in range(2):
+        dq, dqd = rng.standard_normal(len(q0)), rng.standard_normal(len(q0))
+        dtaus = rng.standard_normal(taus.shape)
+        _, _, tq, tqd = _oracle_rollout(rb, q0, qd0, taus, dt, dq, dqd, dtaus)
+        # per chain: dL = 2 q_T . dq_T + 2 qd_T . dqd_T
+        exact = _chain_sums(2 * rq * tq + 2 * rqd * tqd, off)
+        ours = _chain_sums(g0 * dq + gd0 * dqd + (gt * dtaus).sum(axis=0), off)
+        assert np.all(np.abs(ours - exact) <= 1e-10 * (1 + np.abs(exact))), np.abs(ours - exact).max()
+    # central differences on the oracle along one direction, whole batch
+    h = 1e-6
+    dq, dqd = rng.standard_normal(len(q0)), rng.standard_normal(len(q0))
+    dtaus = rng.standard_normal(taus.shape)
+    lp = sum(np.sum(x ** 2) for x in _oracle_rollout(rb, q0 + h * dq, qd0 + h * dqd, taus + h * dtaus, dt)[:2])
+    lm = sum(np.sum(x ** 2) for x in _oracle_rollout(rb, q0 - h * dq, qd0 - h * dqd, taus - h * dtaus, dt)[:2])
+    fd_dir = (lp - lm) / (2 * h)
+    ours = np.sum(g0 * dq) + np.sum(gd0 * dqd) + np.sum(gt * dtaus)
+    assert abs(ours - fd_dir) <= 1e-6 * max(1.0, abs(fd_dir)), (ours, fd_dir)
+
+
+def test_rollout_full_size_sampled(fdm, dev):
+    """16384 chains of 32 links, 100 steps: gradient of sampled chains against the oracle."""
+    batch, n, steps, dt = 16384, 32, 100, 1e-3
+    lengths = np.full(batch, n, np.int32)
+    rb = synth.make_robots(lengths, cfg=5)
+    q0, qd0, _ = synth.make_state(lengths, cfg=5)
+    taus = np.random.default_rng(6).standard_normal((steps, len(q0)))
+    model = fdm.Model(rb, "f64", device=dev)
+    tq0 = _t(q0, dev).requires_grad_(True)
+    tqd0 = _t(qd0, dev).requires_grad_(True)
+    ttaus = _t(taus, dev).requires_grad_(True)
+    qt, qdt = fdm.rollout(model, tq0, tqd0, ttaus, batch=batch, dt=dt, every=10)
+    ((qt ** 2).sum() + (qdt ** 2).sum()).backward()
+    g0, gd0, gt = tq0.grad.cpu().numpy(), tqd0.grad.cpu().numpy(), ttaus.grad.cpu().numpy()
+    assert np.all(np.isfinite(g0)) and np.all(np.isfinite(gt))
+    pick = np.array([0, 777, 8191, 16383])
+    sub = rb.take(pick)
+    idx = np.concatenate([np.arange(n * b, n * b + n) for b in pick])
+    rng = np.random.default_rng(66)
+    dq, dqd = rng.standard_normal(len(idx)), rng.standard_normal(len(idx))
+    dtaus = rng.standard_normal((steps, len(idx)))
+    rq, rqd, tq, tqd = _oracle_rollout(sub, q0[idx], qd0[idx], taus[:, idx], dt, dq, dqd, dtaus)
+    off = sub.offsets
+    exact = _chain_sums(2 * rq * tq + 2 * rqd * tqd, off)
+    ours = _chain_sums(g0[idx] * dq + gd0[idx] * dqd + (gt[:, idx] * dtaus).sum(axis=0), off)
+    assert np.all(np.abs(ours - exact) <= 1e-10 * (1 + np.abs(exact))), np.abs(ours - exact).max()

@@ -1,0 +1,57 @@
+"""Serving on the GPU: every request's result is the same alone and inside the
+continuous-batching mix (bit for bit with one lane per chain), and matches
+the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1609_06779_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def test_served_results_equal_alone_and_oracle(dev):
+    from paper_1609_06779_amd import fd, serve
+
+    lengths = synth.ragged_lengths(32, 7, 200, cfg=4)
+    robots = synth.make_robots(lengths, cfg=4)
+    model = fd.Model(robots, "f64", device=dev)
+    reqs = serve.make_requests(lengths, count=60, qps=20000.0, seed=7, max_chains=512)
+    ex = serve.GpuExecutor(model, lengths, algo="abia", streams=4)
+    sched = serve.Scheduler(ex, budget_bytes=64 << 20, max_inflight=4, idle=serve.spin_idle)
+    stats = sched.run(reqs)
+    assert stats.completed == 60 and stats.rejected == 0 and stats.launches >= 2
+    for r in reqs[::7]:
+        alone = model.forward(r.q.to(dev), r.qd.to(dev), r.tau.to(dev), batch=r.chains, algo="abia",
+                              robot_id=torch.full((r.chains,), r.robot, dtype=torch.int32, device=dev)).cpu()
+        assert torch.equal(alone, r.out), r.rid
+        per_chain = robots.take(np.full(r.chains, r.robot))
+        ref = oracle.fd(per_chain, r.q.numpy(), r.qd.numpy(), r.tau.numpy())
+        err = oracle.relative_error(r.out.numpy(), ref, per_chain.offsets)
+        kappa = max(np.linalg.cond(m) for m in oracle.crba(per_chain.take(np.arange(1)), r.q.numpy()[:r.n]))
+        assert err.max() <= max(1e-10, 16 * kappa * 2.0 ** -53 * 4), (r.rid, err.max())
+
+
+def test_budget_rejects_a_request_larger_than_the_device_budget(dev):
+    from paper_1609_06779_amd import fd, serve
+
+    lengths = np.array([50, 20], np.int32)
+    model = fd.Model(synth.make_robots(lengths, cfg=4), "f64", device=dev)
+    reqs = serve.make_requests(lengths, count=6, qps=float("inf"), seed=8, max_chains=2000)
+    ex = serve.GpuExecutor(model, lengths)
+    small = min(ex.bytes_needed([r]) for r in reqs)
+    big = max(ex.bytes_needed([r]) for r in reqs)
+    sched = serve.Scheduler(ex, budget_bytes=(small + big) // 2, max_inflight=2, idle=serve.spin_idle)
+    stats = sched.run(reqs)
+    assert stats.rejected >= 1 and stats.completed + stats.rejected == 6
+    for r in reqs:
+        if not r.rejected:
+            assert torch.isfinite(r.out).all()
