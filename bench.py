@@ -48,6 +48,95 @@ def fma_per_solve(algo: str, n: int) -> float:
     raise ValueError(algo)
 
 
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1609_06779_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of ``kernel`` from the committed counter summary, if the
+    kernel sources are unchanged since it was taken (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    import re
+
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return None
+    data = json.loads(m.group(1))
+    if data.get("source_hash") != kernel_source_hash():
+        return None
+    k = data.get("kernels", {}).get(kernel)
+    return None if k is None else k["bytes_per_launch"]
+
+
+KERNEL_PATTERNS = (("abia", r"k_abia<"), ("jsiia", r"k_jsiia"), ("cfa", r"k_cfa<"))
+COPY_CALIB_BYTES = 256 << 20
+
+
+def summarize_pmc(fetch_dir: str, write_dir: str, workload: str, commands, summary_cmd: str) -> str:
+    """Write profiles/<workload>_hbm_traffic.md from two rocprofv3 --pmc runs of
+    ``bench.py --copy-calib`` (one with FETCH_SIZE, one with WRITE_SIZE). Each
+    kernel's counters are scaled by what the same counter reads for the device
+    copy of known size in the same run."""
+    import collections
+    import csv
+    import glob
+    import re
+
+    def load(d, counter):
+        vals = collections.defaultdict(list)
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r.get("Counter_Name") == counter:
+                    vals[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return vals
+
+    def pick(vals, pat):
+        for k, v in vals.items():
+            if re.search(pat, k):
+                return sum(v) / len(v), len(v), k
+        return None
+
+    fe, wr = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    cf, cw = pick(fe, "copyBuffer"), pick(wr, "copyBuffer")
+    if cf is None or cw is None:
+        raise SystemExit("no copy kernel in the counter runs (run bench.py with --copy-calib)")
+    ffac, wfac = COPY_CALIB_BYTES / 1024 / cf[0], COPY_CALIB_BYTES / 1024 / cw[0]
+    out = {"source_hash": kernel_source_hash(), "copy_bytes": COPY_CALIB_BYTES, "copy_fetch_kib": cf[0],
+           "copy_write_kib": cw[0], "fetch_scale": ffac, "write_scale": wfac, "kernels": {}}
+    for algo, pat in KERNEL_PATTERNS:
+        f, w = pick(fe, pat), pick(wr, pat)
+        if f and w:
+            out["kernels"][algo] = {"kernel": f[2].split("(")[0], "dispatches": f[1], "fetch_kib": f[0],
+                                    "write_kib": w[0], "bytes_per_launch": (f[0] * ffac + w[0] * wfac) * 1024}
+    mib = COPY_CALIB_BYTES >> 20
+    lines = [f"# HBM traffic per launch: {workload}", "",
+             "Two counter passes (one counter each) of the same program, then this summary:", "", "```",
+             *commands, summary_cmd, "```",
+             "", f"Calibration: a {mib} MiB device copy (`__amd_rocclr_copyBuffer`) in the same run reads "
+             f"FETCH_SIZE {cf[0]:.0f} KiB and WRITE_SIZE {cw[0]:.0f} KiB for {COPY_CALIB_BYTES >> 10} KiB moved "
+             f"each way; kernel counters are scaled by {ffac:.3f} (fetch) and {wfac:.3f} (write).", "",
+             "| algorithm | kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled bytes / launch |",
+             "|---|---|---|---|---|---|"]
+    for a, k in out["kernels"].items():
+        lines.append(f"| {a} | `{k['kernel']}` | {k['dispatches']} | {k['fetch_kib']:.0f} | {k['write_kib']:.0f} "
+                     f"| {k['bytes_per_launch']:.3e} |")
+    lines += ["", "Machine-readable (bench.py reads `bytes_per_launch` while `source_hash` matches the kernel "
+              "sources):", "", "```json", json.dumps(out, indent=1), "```"]
+    path = os.path.join(ROOT, "profiles", f"{workload}_hbm_traffic.md")
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return path
+
+
 def cpu_baseline(rb, q, qd, tau, chains: int):
     import oracle
     from paper_1609_06779_amd import synth
@@ -169,7 +258,18 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a 256 MiB device copy, the known-size reference for HBM counters")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarise two rocprofv3 --pmc runs into profiles/ and exit (no GPU use)")
+    ap.add_argument("--pmc-command", action="append", default=[],
+                    help="with --pmc-summary: the profiler command lines to record")
     args = ap.parse_args()
+    if args.pmc_summary:
+        print(summarize_pmc(*args.pmc_summary, f"fd_forward_n{args.n}_b{args.batch}_{args.dtype}",
+                            args.pmc_command, f"python bench.py --pmc-summary {' '.join(args.pmc_summary)} --n {args.n} "
+                            f"--batch {args.batch} --dtype {args.dtype} --pmc-command ..."))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); chains are independent, so a "
               "multi-GPU run would shard the batch with no exchange. Nothing was run.", file=sys.stderr)
@@ -202,6 +302,13 @@ def main():
             if events is not None:
                 events[a][1].record(stream)
 
+    if args.copy_calib:
+        src = torch.empty(COPY_CALIB_BYTES, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -250,7 +357,8 @@ def main():
                    "algos": algos, "solves_per_step": len(algos) * args.batch},
         "per_algo": per_algo,
         "roofline": {"bound": "alu", "kernel": dominant, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None},
+                     "frac": achieved / peak,
+                     "traffic": measured_traffic(dominant, f"fd_forward_n{args.n}_b{args.batch}_{args.dtype}")},
     }
     if not args.no_ragged:
         print("[bench] ragged leg", file=sys.stderr, flush=True)
