@@ -7,113 +7,17 @@
 // The inversion (the paper does not fix the method) is Gauss-Jordan
 // elimination of [M | tau_delta] without pivoting (M is SPD, so every pivot is
 // positive): step j removes column j from every other row, after which
-// qdd_i = b_i / m_ii. Chains of up to 64 links keep one row of M per lane in
-// registers; the trailing block stays symmetric, so the pivot row is the
-// pivot column and one LDS column write per step broadcasts it. Longer chains
-// keep M in LDS and use a right-looking Cholesky factorisation with
-// tau_delta as an extra column, then one backward substitution.
+// qdd_i = b_i / m_ii. The trailing block stays symmetric, so the pivot row is
+// the pivot column and one LDS column write per step broadcasts it. Chains of
+// up to 32 links keep one row of M per lane in registers (several chains per
+// wavefront); chains of up to 64 and 128 links spread M over an 8 x 8 or
+// 16 x 16 grid of lanes, 64 entries per lane.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
 #include "rnea.h"
 
 namespace fdk {
-
-template <typename T, int NP> struct JsiiaLds {
-    static constexpr int ld = NP + 1;
-    static constexpr int per_chain = NP * ld + 2 * NP;   // M, y, x
-};
-
-template <typename T, int NP>
-__global__ __launch_bounds__(Geo<NP>::threads) void k_jsiia(ModelView<T> m, ChainMap cm, const T* __restrict__ q,
-                                                             const T* __restrict__ qd, const T* __restrict__ tau,
-                                                             T* __restrict__ qdd, int* __restrict__ status) {
-    using L = JsiiaLds<T, NP>;
-    __shared__ T xbuf[NP > 64 ? 10 * NP : 1];
-    __shared__ T sf[Geo<NP>::chains * NP * 12];
-    extern __shared__ unsigned char dyn_lds[];
-    T* lds = reinterpret_cast<T*>(dyn_lds);
-    const int grp = threadIdx.x / NP, li = threadIdx.x % NP;
-    const int b = blockIdx.x * Geo<NP>::chains + grp;
-    ChainInfo ci{0, 0, 0, 0};
-    if (b < cm.batch) ci = chain_info(m, cm, b);
-    const int n = ci.n;
-    const bool active = li < n;
-    const int64_t st = ci.state0 + li;
-    const int64_t link = ci.link0 + li;
-    T qi = active ? q[st] : T(0), qdi = active ? qd[st] : T(0), ti = active ? tau[st] : T(0);
-
-    LinkLane<T> k;
-    const T tb = rnea_lane<T, NP>(m, link, active, qi, qdi, T(0), true, li, xbuf, k);
-    T y = active ? ti - tb : T(0);
-
-    T f[6];
-    composite_force<T, NP>(k, active, li, xbuf, f);
-    T* my = sf + grp * NP * 12;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        my[c * NP + li] = k.s[c];
-        my[(6 + c) * NP + li] = f[c];
-    }
-    __syncthreads();
-    T* mm = lds + grp * L::per_chain;
-    T* yb = mm + NP * L::ld;
-    T* xb = yb + NP;
-    T* row = mm + li * L::ld;
-    if (active) {
-        for (int kk = 0; kk < n; ++kk) {
-            T acc = T(0);
-            if (kk <= li) {
-#pragma unroll
-                for (int c = 0; c < 6; ++c) acc += my[c * NP + kk] * f[c];
-            } else {
-#pragma unroll
-                for (int c = 0; c < 6; ++c) acc += k.s[c] * my[(6 + c) * NP + kk];
-            }
-            row[kk] = acc;
-        }
-    }
-    __syncthreads();
-
-    // right-looking Cholesky of the n x n block with tau_delta as an extra column
-    bool ok = true;
-    for (int j = 0; j < NP; ++j) {
-        if (active && li == j) {
-            T d = row[j];
-            ok = d > T(0);
-            T l = sqrt(d);
-            row[j] = l;
-            y = y / l;
-            yb[j] = y;
-        }
-        __syncthreads();
-        T lij = T(0);
-        if (active && li > j) {
-            lij = row[j] / mm[j * L::ld + j];
-            row[j] = lij;
-            y -= lij * yb[j];
-        }
-        __syncthreads();
-        if (active && li > j) {
-            for (int kk = j + 1; kk <= li; ++kk) row[kk] -= lij * mm[kk * L::ld + j];
-        }
-        __syncthreads();
-    }
-    // L^T x = y
-    T x = T(0);
-    for (int kk = NP - 1; kk >= 0; --kk) {
-        if (active && li == kk) {
-            x = y / row[kk];
-            xb[kk] = x;
-        }
-        __syncthreads();
-        if (active && li < kk && kk < n) y -= mm[kk * L::ld + li] * xb[kk];
-        __syncthreads();
-    }
-    if (active) qdd[st] = x;
-    if (active && !ok && status) atomicOr(status, 1);
-}
-
 
 // 1/p to full precision from the hardware estimate and two Newton steps (p > 0, normal).
 __device__ __forceinline__ double rcp_refined(double p) {
@@ -194,48 +98,147 @@ __global__ __launch_bounds__(64) void k_jsiia_gj(ModelView<T> m, ChainMap cm, co
     if (active && !ok && status) atomicOr(status, 1);
 }
 
-// largest chain the in-LDS factorisation takes for this precision
-template <typename T> int jsiia_max_np() {
-    int best = 0;
-    for (int p = 8; p <= 256; p *= 2) {
-        int chains = p < 64 ? 64 / p : 1;
-        size_t lds = sizeof(T) * chains * ((size_t)p * (p + 1) + 2 * p) + sizeof(T) * chains * p * 12 +
-                     (p > 64 ? sizeof(T) * 10 * p : 0);
-        if (lds <= 160 * 1024) best = p;
+
+// Gauss-Jordan with M distributed over a G x G grid of lanes, G = NP / 8 (one
+// chain per workgroup: 64 lanes for NP = 64, 256 for NP = 128): lane (r, c)
+// owns the entries (i, k) = (r + G a, c + G b), a, b = 0..7, and the
+// right-hand side of its rows. At step j the lanes of column group j % G
+// publish column j through LDS (it is also the pivot row: the trailing block
+// stays symmetric); every lane then reads its 8 row multipliers and the
+// pivot-row entries of its columns, and updates its block. Column blocks left
+// of j / G hold only eliminated columns and are skipped at compile time. The
+// inverse dynamics before it runs lane per link on all TH = G * G lanes.
+template <typename T, int NP>
+__global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_gj2d(ModelView<T> m, ChainMap cm,
+                                                                     const T* __restrict__ q,
+                                                                     const T* __restrict__ qd,
+                                                                     const T* __restrict__ tau, T* __restrict__ qdd,
+                                                                     int* __restrict__ status) {
+    constexpr int G = NP / 8;
+    constexpr int TH = G * G;
+    static_assert(TH >= NP, "the lane grid must cover one lane per link");
+    __shared__ T xbuf[TH > 64 ? 10 * TH : 1];   // cross-wavefront scan exchange
+    __shared__ T sf[NP * 13];                   // s (6), F (6), tau_delta per link
+    __shared__ T col[2][NP + 1];                // pivot column and the pivot row's right-hand side
+    const int li = threadIdx.x;
+    ChainInfo ci{0, 0, 0, 0};
+    if ((int)blockIdx.x < cm.batch) ci = chain_info(m, cm, blockIdx.x);
+    const int n = ci.n;
+    const bool active = li < n;
+    const int64_t st = ci.state0 + li;
+    T qi = active ? q[st] : T(0), qdi = active ? qd[st] : T(0), ti = active ? tau[st] : T(0);
+
+    LinkLane<T> k;
+    const T tb = rnea_lane<T, TH>(m, ci.link0 + li, active, qi, qdi, T(0), true, li, xbuf, k);
+    T f6[6];
+    composite_force<T, TH>(k, active, li, xbuf, f6);
+    if (li < NP) {
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            sf[e * NP + li] = k.s[e];
+            sf[(6 + e) * NP + li] = f6[e];
+        }
+        sf[12 * NP + li] = active ? ti - tb : T(0);
     }
-    return best;
+    __syncthreads();
+
+    const int r = li / G, c = li % G;
+    T mb[8][8], y[8], diag[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        const int i = r + G * a;
+        T si[6], fi[6];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            si[e] = sf[e * NP + i];
+            fi[e] = sf[(6 + e) * NP + i];
+        }
+        y[a] = sf[12 * NP + i];
+        diag[a] = T(1);
+#pragma unroll
+        for (int bb = 0; bb < 8; ++bb) {
+            const int kk = c + G * bb;
+            T lo = T(0), up = T(0);
+#pragma unroll
+            for (int e = 0; e < 6; ++e) {
+                lo += sf[e * NP + kk] * fi[e];          // k <= i: s_k . F_i
+                up += si[e] * sf[(6 + e) * NP + kk];    // k >  i: s_i . F_k
+            }
+            const T v = kk <= i ? lo : up;
+            mb[a][bb] = (i < n && kk < n) ? v : (i == kk ? T(1) : T(0));
+        }
+    }
+    bool ok = true;
+    // column block jb is a compile-time index (register arrays stay in registers);
+    // the step inside the block, jr, is a run-time value used only in comparisons
+#pragma unroll
+    for (int jb = 0; jb < 8; ++jb)
+#pragma unroll 1
+    for (int jr = 0; jr < G; ++jr) {
+        const int j = G * jb + jr;
+        T* cj = col[j & 1];
+        if (c == jr) {
+#pragma unroll
+            for (int a = 0; a < 8; ++a) cj[r + G * a] = mb[a][jb];
+            if (r == jr) cj[NP] = y[jb];
+        }
+        __syncthreads();
+        const T piv = cj[j];
+        const T rp = rcp_refined(piv);
+        const T yj = cj[NP];
+        T fa[8];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const T v = cj[r + G * a] * rp;
+            fa[a] = (r + G * a == j) ? T(0) : v;
+        }
+        if (r == jr) {
+            diag[jb] = piv;
+            ok = ok && piv > T(0);
+        }
+#pragma unroll
+        for (int bb = jb; bb < 8; ++bb) {
+            T pv = cj[c + G * bb];
+            if (bb == jb) pv = c > jr ? pv : T(0);      // only columns right of the pivot
+#pragma unroll
+            for (int a = 0; a < 8; ++a) mb[a][bb] -= fa[a] * pv;
+        }
+#pragma unroll
+        for (int a = 0; a < 8; ++a) y[a] -= fa[a] * yj;
+    }
+    if (c == 0) {
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const int i = r + G * a;
+            if (i < n) qdd[ci.state0 + i] = y[a] / diag[a];
+        }
+    }
+    if (c == 0 && !ok && status) atomicOr(status, 1);
 }
+
+// longest chain the Gauss-Jordan kernels take (same for both precisions)
+template <typename T> int jsiia_max_np() { return 128; }
 
 template <typename T>
 hipError_t launch_jsiia(int np, const ModelView<T>& m, const ChainMap& cm, const T* q, const T* qd, const T* tau,
                         T* qdd, int* status, hipStream_t st) {
     if (cm.batch <= 0) return hipSuccess;
-    if (np <= 64) {
 #define GJ(P)                                                                                        \
     hipLaunchKernelGGL((k_jsiia_gj<T, P>), dim3((cm.batch + Geo<P>::chains - 1) / Geo<P>::chains),  \
                        dim3(64), 0, st, m, cm, q, qd, tau, qdd, status)
-        switch (np) {
-            case 8: GJ(8); break;
-            case 16: GJ(16); break;
-            case 32: GJ(32); break;
-            case 64: GJ(64); break;
-            default: return hipErrorInvalidValue;
-        }
+#define GJ2D(P)                                                                                      \
+    hipLaunchKernelGGL((k_jsiia_gj2d<T, P>), dim3(cm.batch), dim3((P / 8) * (P / 8)), 0, st, m, cm, q, qd, tau, \
+                       qdd, status)
+    switch (np) {
+        case 8: GJ(8); break;
+        case 16: GJ(16); break;
+        case 32: GJ(32); break;
+        case 64: GJ2D(64); break;
+        case 128: GJ2D(128); break;
+        default: return hipErrorInvalidValue;
+    }
 #undef GJ
-        return hipGetLastError();
-    }
-#define CALL(P)                                                                                           \
-    {                                                                                                     \
-        size_t lds = sizeof(T) * Geo<P>::chains * JsiiaLds<T, P>::per_chain;                              \
-        if (P > jsiia_max_np<T>()) return hipErrorInvalidConfiguration;                                   \
-        hipError_t e = hipFuncSetAttribute((const void*)k_jsiia<T, P>,                                    \
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);         \
-        if (e != hipSuccess) return e;                                                                    \
-        hipLaunchKernelGGL((k_jsiia<T, P>), dim3((cm.batch + Geo<P>::chains - 1) / Geo<P>::chains),      \
-                           dim3(Geo<P>::threads), lds, st, m, cm, q, qd, tau, qdd, status);               \
-    }
-    FDK_NP_SWITCH(np, CALL)
-#undef CALL
+#undef GJ2D
     return hipGetLastError();
 }
 
