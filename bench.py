@@ -137,6 +137,30 @@ def summarize_pmc(fetch_dir: str, write_dir: str, workload: str, commands, summa
     return path
 
 
+def summarize_trace(trace_dir: str, workload: str, commands, summary_cmd: str) -> str:
+    """Write profiles/<workload>_kernel_trace.md from a rocprofv3 --kernel-trace --stats run."""
+    import csv
+    import glob
+
+    files = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no kernel_stats.csv under {trace_dir}")
+    rows = list(csv.DictReader(open(files[0])))
+    lines = [f"# Kernel trace: {workload}", "", "Commands:", "", "```", *commands, summary_cmd, "```", "",
+             "`--stats` summary of the library's kernels (times in microseconds):", "",
+             "| kernel | calls | average | min | max | share of GPU time |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        name = r["Name"].split("(")[0].replace("void ", "")
+        if "fdk::" not in name:
+            continue
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} "
+                     f"| {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f}% |")
+    path = os.path.join(ROOT, "profiles", f"{workload}_kernel_trace.md")
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return path
+
+
 def cpu_baseline(rb, q, qd, tau, chains: int):
     import oracle
     from paper_1609_06779_amd import synth
@@ -263,8 +287,15 @@ def main():
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs into profiles/ and exit (no GPU use)")
     ap.add_argument("--pmc-command", action="append", default=[],
-                    help="with --pmc-summary: the profiler command lines to record")
+                    help="with --pmc-summary or --trace-summary: the profiler command lines to record")
+    ap.add_argument("--trace-summary", metavar="TRACE_DIR",
+                    help="summarise a rocprofv3 --kernel-trace --stats run into profiles/ and exit (no GPU use)")
     args = ap.parse_args()
+    if args.trace_summary:
+        print(summarize_trace(args.trace_summary, f"fd_forward_n{args.n}_b{args.batch}_{args.dtype}",
+                              args.pmc_command, f"python bench.py --trace-summary {args.trace_summary} --n {args.n} "
+                              f"--batch {args.batch} --dtype {args.dtype} --pmc-command ..."))
+        return
     if args.pmc_summary:
         print(summarize_pmc(*args.pmc_summary, f"fd_forward_n{args.n}_b{args.batch}_{args.dtype}",
                             args.pmc_command, f"python bench.py --pmc-summary {' '.join(args.pmc_summary)} --n {args.n} "

@@ -30,14 +30,18 @@ def test_served_results_equal_alone_and_oracle(dev):
     stats = sched.run(reqs)
     assert stats.completed == 60 and stats.rejected == 0 and stats.launches >= 2
     for r in reqs[::7]:
+        # the robots differ in length, so a batch names its chains' offsets
+        offsets = torch.arange(0, (r.chains + 1) * r.n, r.n, dtype=torch.int64, device=dev)
         alone = model.forward(r.q.to(dev), r.qd.to(dev), r.tau.to(dev), batch=r.chains, algo="abia",
-                              robot_id=torch.full((r.chains,), r.robot, dtype=torch.int32, device=dev)).cpu()
+                              robot_id=torch.full((r.chains,), r.robot, dtype=torch.int32, device=dev),
+                              offsets=offsets).cpu()
         assert torch.equal(alone, r.out), r.rid
         per_chain = robots.take(np.full(r.chains, r.robot))
         ref = oracle.fd(per_chain, r.q.numpy(), r.qd.numpy(), r.tau.numpy())
         err = oracle.relative_error(r.out.numpy(), ref, per_chain.offsets)
-        kappa = max(np.linalg.cond(m) for m in oracle.crba(per_chain.take(np.arange(1)), r.q.numpy()[:r.n]))
-        assert err.max() <= max(1e-10, 16 * kappa * 2.0 ** -53 * 4), (r.rid, err.max())
+        kappa = np.array([np.linalg.cond(m) for m in oracle.crba(per_chain, r.q.numpy())])
+        bar = np.maximum(1e-10, 16 * kappa * 2.0 ** -53)      # the ABIA error model of the parity tests
+        assert np.all(err <= bar), (r.rid, (err / bar).max())
 
 
 def test_budget_rejects_a_request_larger_than_the_device_budget(dev):
