@@ -105,8 +105,17 @@ def summarize_pmc(fetch_dir: str, write_dir: str, workload: str, commands, summa
                 return sum(v) / len(v), len(v), k
         return None
 
+    def calib(vals):
+        # the calibration copies are the largest copy dispatches of the run (torch
+        # issues small copies of its own)
+        v = [x for k, xs in vals.items() if "copyBuffer" in k for x in xs]
+        if not v:
+            return None
+        top = sorted(v)[-3:]
+        return sum(top) / len(top), len(top), "copyBuffer"
+
     fe, wr = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
-    cf, cw = pick(fe, "copyBuffer"), pick(wr, "copyBuffer")
+    cf, cw = calib(fe), calib(wr)
     if cf is None or cw is None:
         raise SystemExit("no copy kernel in the counter runs (run bench.py with --copy-calib)")
     ffac, wfac = COPY_CALIB_BYTES / 1024 / cf[0], COPY_CALIB_BYTES / 1024 / cw[0]
@@ -115,7 +124,8 @@ def summarize_pmc(fetch_dir: str, write_dir: str, workload: str, commands, summa
     for algo, pat in KERNEL_PATTERNS:
         f, w = pick(fe, pat), pick(wr, pat)
         if f and w:
-            out["kernels"][algo] = {"kernel": f[2].split("(")[0], "dispatches": f[1], "fetch_kib": f[0],
+            out["kernels"][algo] = {"kernel": f[2].split("(")[0].replace("void ", ""), "dispatches": f[1],
+                                    "fetch_kib": f[0],
                                     "write_kib": w[0], "bytes_per_launch": (f[0] * ffac + w[0] * wfac) * 1024}
     mib = COPY_CALIB_BYTES >> 20
     lines = [f"# HBM traffic per launch: {workload}", "",
@@ -137,31 +147,43 @@ def summarize_pmc(fetch_dir: str, write_dir: str, workload: str, commands, summa
     return path
 
 
-def summarize_trace(trace_dir: str, workload: str, commands, summary_cmd: str) -> str:
-    """Write profiles/<workload>_kernel_trace.md from a rocprofv3 --kernel-trace --stats run."""
+def summarize_trace(trace_dir: str, workload: str, commands, summary_cmd: str, bench_log=None) -> str:
+    """Write profiles/<workload>_kernel_trace.md from a rocprofv3 --kernel-trace --stats run;
+    with ``bench_log`` (the profiled bench.py's output) its own HIP-event averages go beside."""
     import csv
     import glob
+
+    events = {}
+    if bench_log:
+        for line in open(bench_log):
+            if line.startswith("{"):
+                events = {a: v["ms_per_launch"] * 1e3 for a, v in json.loads(line).get("per_algo", {}).items()}
 
     files = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
     if not files:
         raise SystemExit(f"no kernel_stats.csv under {trace_dir}")
     rows = list(csv.DictReader(open(files[0])))
     lines = [f"# Kernel trace: {workload}", "", "Commands:", "", "```", *commands, summary_cmd, "```", "",
-             "`--stats` summary of the library's kernels (times in microseconds):", "",
-             "| kernel | calls | average | min | max | share of GPU time |", "|---|---|---|---|---|---|"]
+             "`--stats` summary of the library's kernels (times in microseconds). The last column is "
+             "bench.py's own HIP-event average per launch in the same profiled run (back-to-back "
+             "launches; the trace times each dispatch on its own):", "",
+             "| kernel | calls | average | min | max | share of GPU time | bench.py events |",
+             "|---|---|---|---|---|---|---|"]
     for r in rows:
         name = r["Name"].split("(")[0].replace("void ", "")
         if "fdk::" not in name:
             continue
+        algo = next((a for a, pat in KERNEL_PATTERNS if pat.rstrip("<") in name), None)
+        ev = f"{events[algo]:.1f}" if algo in events else "-"
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} "
-                     f"| {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f}% |")
+                     f"| {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f}% | {ev} |")
     path = os.path.join(ROOT, "profiles", f"{workload}_kernel_trace.md")
     with open(path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     return path
 
 
-def cpu_baseline(rb, q, qd, tau, chains: int):
+def cpu_baseline(rb, q, qd, tau, chains: int, min_s: float = 10.0, max_s: float = 30.0):
     import oracle
     from paper_1609_06779_amd import synth
 
@@ -169,12 +191,17 @@ def cpu_baseline(rb, q, qd, tau, chains: int):
     n = int(rb.n_links[0])
     idx = slice(0, chains * n)
     oracle.fd(sub.take(np.arange(min(64, chains))), q[: 64 * n], qd[: 64 * n], tau[: 64 * n])   # warm
-    t0 = time.perf_counter()
-    oracle.fd(sub, q[idx], qd[idx], tau[idx], threads=0)
-    dt = time.perf_counter() - t0
-    return {"value": chains / dt, "unit": "solves/s", "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": f"first {chains} chains of the same workload (n={n}, FP64), plain CRBA + RNEA + "
-                      f"Cholesky, all host threads, {dt:.2f} s wall"}
+    # whole passes over the sample until at least min_s seconds of CPU work (at most max_s)
+    passes, t0 = 0, time.perf_counter()
+    while True:
+        oracle.fd(sub, q[idx], qd[idx], tau[idx], threads=0)
+        passes += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_s or dt * (passes + 1) / passes > max_s:
+            break
+    return {"value": passes * chains / dt, "unit": "solves/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"{passes} passes over the first {chains} chains of the same workload (n={n}, FP64), "
+                      f"plain CRBA + RNEA + Cholesky, all host threads, {dt:.1f} s wall"}
 
 
 def serving_leg(dtype: str, requests: int = 3000):
@@ -254,8 +281,10 @@ def ragged_leg(dtype: str, batch: int = 100000, lo: int = 4, hi: int = 256, reps
     groups = []
     for n in np.unique(lengths):
         ids = np.nonzero(lengths == n)[0].astype(np.int32)
-        groups.append((len(ids), torch.from_numpy(ids).to(dev), torch.from_numpy(off[ids]).to(dev),
-                       model.workspace(len(ids), "abia", robot_id=torch.from_numpy(ids).to(dev))))
+        # chain starts of this length's chains, plus the end of the last one
+        starts = np.append(off[ids], off[ids[-1]] + n).astype(np.int64)
+        rid, goff = torch.from_numpy(ids).to(dev), torch.from_numpy(starts).to(dev)
+        groups.append((len(ids), rid, goff, model.workspace(len(ids), "abia", robot_id=rid, offsets=goff)))
 
     def per_length():
         for cnt, rid, goff, ws in groups:
@@ -290,11 +319,13 @@ def main():
                     help="with --pmc-summary or --trace-summary: the profiler command lines to record")
     ap.add_argument("--trace-summary", metavar="TRACE_DIR",
                     help="summarise a rocprofv3 --kernel-trace --stats run into profiles/ and exit (no GPU use)")
+    ap.add_argument("--bench-log", help="with --trace-summary: output of the profiled bench.py run")
     args = ap.parse_args()
     if args.trace_summary:
         print(summarize_trace(args.trace_summary, f"fd_forward_n{args.n}_b{args.batch}_{args.dtype}",
                               args.pmc_command, f"python bench.py --trace-summary {args.trace_summary} --n {args.n} "
-                              f"--batch {args.batch} --dtype {args.dtype} --pmc-command ..."))
+                              f"--batch {args.batch} --dtype {args.dtype} --bench-log {args.bench_log} "
+                              f"--pmc-command ...", args.bench_log))
         return
     if args.pmc_summary:
         print(summarize_pmc(*args.pmc_summary, f"fd_forward_n{args.n}_b{args.batch}_{args.dtype}",

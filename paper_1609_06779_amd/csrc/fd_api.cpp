@@ -22,9 +22,11 @@ struct fd_model {
     bool uniform = false;
     double g[3] = {0, 0, 0};
     void* d_fields = nullptr;         // T[MF_COUNT][total_links]
-    void* d_il = nullptr;             // T[MF_IL_COUNT][nmax][num_robots]
+    void* d_il = nullptr;             // T[MF_IL_COUNT][nmax][num_robots], columns by decreasing length
     int64_t* d_link_start = nullptr;
     int32_t* d_n_links = nullptr;
+    int32_t* d_slot = nullptr;        // [num_robots] column of each robot in d_il
+    int32_t* d_slot_robot = nullptr;  // [num_robots] robot of each column
 };
 
 namespace {
@@ -71,6 +73,7 @@ template <typename T> fdk::ModelView<T> view(const fd_model* m) {
     for (int k = 0; k < 3; ++k) v.g[k] = (T)m->g[k];
     v.il = static_cast<const T*>(m->d_il);
     v.il_fstride = (int64_t)m->nmax * m->num_robots;
+    v.slot = m->d_slot;
     return v;
 }
 
@@ -222,13 +225,21 @@ fd_status_t fd_init(const fd_model_desc_t* d, fd_dtype_t dtype, fd_model_t** out
     m->nmax = mx;
     m->uniform = uni;
     for (int k = 0; k < 3; ++k) m->g[k] = d->gravity[k];
+    // interleaved columns: robots by decreasing length, ties in robot order, so a
+    // model of equal lengths keeps its order and 64 consecutive columns hold
+    // robots of nearly equal length
+    std::vector<int32_t> slot_robot(d->num_robots), slot(d->num_robots);
+    for (int r = 0; r < d->num_robots; ++r) slot_robot[r] = r;
+    std::stable_sort(slot_robot.begin(), slot_robot.end(),
+                     [&](int32_t a, int32_t b) { return d->n_links[a] > d->n_links[b]; });
+    for (int c = 0; c < d->num_robots; ++c) slot[slot_robot[c]] = c;
     std::vector<int64_t> starts(d->num_robots);
-    std::vector<int32_t> robot_of(total), index_of(total);
+    std::vector<int32_t> column_of(total), index_of(total);
     int64_t s = 0;
     for (int r = 0; r < d->num_robots; ++r) {
         starts[r] = s;
         for (int i = 0; i < d->n_links[r]; ++i) {
-            robot_of[s + i] = r;
+            column_of[s + i] = slot[r];
             index_of[s + i] = i;
         }
         s += d->n_links[r];
@@ -243,6 +254,8 @@ fd_status_t fd_init(const fd_model_desc_t* d, fd_dtype_t dtype, fd_model_t** out
     if ((e = hipMalloc(&m->d_fields, esz * fdk::MF_COUNT * total)) != hipSuccess ||
         (e = hipMalloc(&m->d_link_start, sizeof(int64_t) * d->num_robots)) != hipSuccess ||
         (e = hipMalloc(&m->d_n_links, sizeof(int32_t) * d->num_robots)) != hipSuccess ||
+        (e = hipMalloc(&m->d_slot, sizeof(int32_t) * d->num_robots)) != hipSuccess ||
+        (e = hipMalloc(&m->d_slot_robot, sizeof(int32_t) * d->num_robots)) != hipSuccess ||
         (e = hipMalloc(&d_raw, raw.size() * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&d_first, first.size())) != hipSuccess ||
         (e = hipMalloc(&m->d_il, esz * il_elems)) != hipSuccess ||
@@ -252,9 +265,12 @@ fd_status_t fd_init(const fd_model_desc_t* d, fd_dtype_t dtype, fd_model_t** out
     if (st == FD_OK) {
         if (hipMemcpy(m->d_link_start, starts.data(), sizeof(int64_t) * starts.size(), hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(m->d_n_links, d->n_links, sizeof(int32_t) * d->num_robots, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(m->d_slot, slot.data(), sizeof(int32_t) * d->num_robots, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(m->d_slot_robot, slot_robot.data(), sizeof(int32_t) * d->num_robots, hipMemcpyHostToDevice) !=
+                hipSuccess ||
             hipMemcpy(d_raw, raw.data(), raw.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(d_first, first.data(), first.size(), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(d_ri, robot_of.data(), sizeof(int32_t) * total, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(d_ri, column_of.data(), sizeof(int32_t) * total, hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(d_ri + total, index_of.data(), sizeof(int32_t) * total, hipMemcpyHostToDevice) != hipSuccess ||
             hipMemset(m->d_il, 0, esz * il_elems) != hipSuccess ||
             fdk::launch_model_init(total, d_raw, d_first, m->d_fields, dtype == FD_F32, nullptr) != hipSuccess ||
@@ -280,6 +296,8 @@ void fd_destroy(fd_model_t* m) {
     if (m->d_il) (void)hipFree(m->d_il);
     if (m->d_link_start) (void)hipFree(m->d_link_start);
     if (m->d_n_links) (void)hipFree(m->d_n_links);
+    if (m->d_slot) (void)hipFree(m->d_slot);
+    if (m->d_slot_robot) (void)hipFree(m->d_slot_robot);
     delete m;
 }
 
@@ -357,10 +375,10 @@ fd_status_t fd_forward_persistent(const fd_model_t* m, const fd_batch_t* b, cons
     if (m->dtype == FD_F64)
         return from_hip(fdk::launch_abia_persistent<double>(view<double>(m), p.cm, p.nmax, g, (const double*)q,
                                                             (const double*)qd, (const double*)tau, (double*)qdd,
-                                                            (double*)abws, planp, st));
+                                                            (double*)abws, planp, m->d_slot_robot, st));
     return from_hip(fdk::launch_abia_persistent<float>(view<float>(m), p.cm, p.nmax, g, (const float*)q,
                                                        (const float*)qd, (const float*)tau, (float*)qdd, (float*)abws,
-                                                       planp, st));
+                                                       planp, m->d_slot_robot, st));
 }
 
 fd_status_t fd_backward_workspace_size(const fd_model_t* m, const fd_batch_t* b, size_t* bytes) {

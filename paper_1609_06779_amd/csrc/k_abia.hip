@@ -32,9 +32,9 @@ size_t abia_workspace_elems(int batch, int nmax) {
 // Model reads go through the robot-interleaved copy: lanes hold consecutive
 // chains, so field f of link i is one contiguous read across the wavefront.
 template <typename T>
-__device__ __forceinline__ Pose<T> link_pose_at(const ModelView<T>& m, int i, int r, T q) {
+__device__ __forceinline__ Pose<T> link_pose_at(const ModelView<T>& m, int i, int slot, T q) {
     T rh[9], p[3];
-    m.home_il(i, r, rh, p);
+    m.home_il(i, slot, rh, p);
     return joint_pose(rh, p, q);
 }
 
@@ -67,9 +67,10 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
     // sweep 1
     T v[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
     T a[6] = {T(0), T(0), T(0), -m.g[0], -m.g[1], -m.g[2]};
+#pragma unroll 2   // loads of two links in flight
     for (int i = 0; i < n; ++i) {
         const int64_t st = ci.state0 + i;
-        const Pose<T> tl = link_pose_at(m, i, ci.robot, q[st]);
+        const Pose<T> tl = link_pose_at(m, i, ci.slot, q[st]);
         const T qdi = qd[st];
         T t[6];
         ad_inv_apply(tl, v, t);
@@ -83,7 +84,7 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
 #pragma unroll
         for (int c = 0; c < 6; ++c) a[c] = t[c];
         T f[6];
-        link_force(m.inertia_il(i, ci.robot), v, a, f);
+        link_force(m.inertia_il(i, ci.slot), v, a, f);
 #pragma unroll
         for (int c = 0; c < 6; ++c) wsat(i, c) = f[c];
     }
@@ -95,12 +96,13 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
 #pragma unroll
     for (int c = 0; c < 36; ++c) pi[c] = T(0);
     Pose<T> tn = pose_identity<T>();                   // T_{i,i+1}
+#pragma unroll 2   // loads of two links in flight
     for (int i = n - 1; i >= 0; --i) {
         const int64_t st = ci.state0 + i;
         T f[6], fp[6], pp[6], jh[36];
 #pragma unroll
         for (int c = 0; c < 6; ++c) f[c] = wsat(i, c);
-        inertia_to_mat6(m.inertia_il(i, ci.robot), jh);
+        inertia_to_mat6(m.inertia_il(i, ci.slot), jh);
         if (i + 1 < n) {
             wrench_to_parent(tn, fc, fp);
             wrench_to_parent(tn, pc, pp);
@@ -132,14 +134,15 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
             pc[c] = pp[c] + h[c] * u * dinv;
             fc[c] = f[c];
         }
-        tn = link_pose_at(m, i, ci.robot, q[st]);
+        tn = link_pose_at(m, i, ci.slot, q[st]);
     }
 
     // sweep 3
     T acc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll 2   // loads of two links in flight
     for (int i = 0; i < n; ++i) {
         const int64_t st = ci.state0 + i;
-        const Pose<T> tl = link_pose_at(m, i, ci.robot, q[st]);
+        const Pose<T> tl = link_pose_at(m, i, ci.slot, q[st]);
         T t[6];
         ad_inv_apply(tl, acc, t);
         T x = wsat(i, 6);
@@ -163,17 +166,18 @@ __global__ __launch_bounds__(64) void k_abia(ModelView<T> m, ChainMap cm, int nm
     abia_chain(m, chain_info(m, cm, b), q, qd, tau, qdd, ws + (size_t)blockIdx.x * nmax * ABIA_WS_FIELDS * 64 + lane);
 }
 
-// Persistent form for ragged batches: each wavefront takes 64-chain tiles of
-// `order` (chains sorted by decreasing length) from an atomic counter until
-// the list is exhausted, so lanes of a tile have nearly equal lengths and the
-// longest tiles go first. Every wavefront leaves once a tile index runs past
-// the list, so the grid always drains.
+// Persistent form for ragged batches: each wavefront takes 64-entry tiles of
+// `order` (count entries; order == nullptr: the identity) from an atomic
+// counter until the list is exhausted, so lanes of a tile have nearly equal
+// lengths and the longest tiles go first. Entries at or past the batch are
+// skipped. Every wavefront leaves once a tile index runs past the list, so
+// the grid always drains.
 template <typename T>
 __global__ __launch_bounds__(64) void k_abia_persistent(ModelView<T> m, ChainMap cm, int nmax,
-                                                        const int32_t* __restrict__ order, int32_t* counter,
-                                                        const T* __restrict__ q, const T* __restrict__ qd,
-                                                        const T* __restrict__ tau, T* __restrict__ qdd,
-                                                        T* __restrict__ ws) {
+                                                        const int32_t* __restrict__ order, int32_t count,
+                                                        int32_t* counter, const T* __restrict__ q,
+                                                        const T* __restrict__ qd, const T* __restrict__ tau,
+                                                        T* __restrict__ qdd, T* __restrict__ ws) {
     __shared__ int tile_s;
     const int lane = threadIdx.x;
     T* wsb = ws + (size_t)blockIdx.x * nmax * ABIA_WS_FIELDS * 64 + lane;
@@ -182,9 +186,10 @@ __global__ __launch_bounds__(64) void k_abia_persistent(ModelView<T> m, ChainMap
         __syncthreads();
         const int tile = tile_s;
         __syncthreads();
-        if ((int64_t)tile * 64 >= cm.batch) break;
+        if ((int64_t)tile * 64 >= count) break;
         const int k = tile * 64 + lane;
-        if (k < cm.batch) abia_chain(m, chain_info(m, cm, order[k]), q, qd, tau, qdd, wsb);
+        const int b = k < count ? (order ? order[k] : k) : cm.batch;
+        if (b < cm.batch) abia_chain(m, chain_info(m, cm, b), q, qd, tau, qdd, wsb);
     }
 }
 
@@ -237,21 +242,35 @@ size_t persistent_plan_bytes(int batch) {
 
 size_t abia_persistent_workspace_elems(int grid, int nmax) { return (size_t)grid * nmax * ABIA_WS_FIELDS * 64; }
 
+// Three orders: with robot ids, the planning kernels sort the batch's chains
+// by decreasing length on the device; without, chain b is robot b, whose
+// interleaved column already follows that order (slot_robot[c] = robot of
+// column c), so the tiles walk the columns; a one-robot model is uniform and
+// the tiles walk the chains.
 template <typename T>
 hipError_t launch_abia_persistent(const ModelView<T>& m, const ChainMap& cm, int nmax, int grid, const T* q,
-                                  const T* qd, const T* tau, T* qdd, T* ws, int32_t* plan, hipStream_t st) {
+                                  const T* qd, const T* tau, T* qdd, T* ws, int32_t* plan,
+                                  const int32_t* slot_robot, hipStream_t st) {
     if (cm.batch <= 0) return hipSuccess;
     int32_t* bins = plan;
     int32_t* cursor = bins + PLAN_BINS;
     int32_t* counter = cursor + PLAN_BINS;
     int32_t* order = counter + 64;
-    const unsigned g = (unsigned)((cm.batch + 255) / 256);
     hipLaunchKernelGGL(k_plan_zero, dim3(1), dim3(256), 0, st, bins, cursor, counter);
-    hipLaunchKernelGGL((k_plan_hist<T>), dim3(g), dim3(256), 0, st, m, cm, bins);
-    hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(64), 0, st, bins, cursor);
-    hipLaunchKernelGGL((k_plan_scatter<T>), dim3(g), dim3(256), 0, st, m, cm, cursor, order);
-    hipLaunchKernelGGL((k_abia_persistent<T>), dim3(grid), dim3(64), 0, st, m, cm, nmax, order, counter, q, qd,
-                       tau, qdd, ws);
+    const int32_t* tiles = nullptr;
+    int32_t count = cm.batch;
+    if (cm.robot_id) {
+        const unsigned g = (unsigned)((cm.batch + 255) / 256);
+        hipLaunchKernelGGL((k_plan_hist<T>), dim3(g), dim3(256), 0, st, m, cm, bins);
+        hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(64), 0, st, bins, cursor);
+        hipLaunchKernelGGL((k_plan_scatter<T>), dim3(g), dim3(256), 0, st, m, cm, cursor, order);
+        tiles = order;
+    } else if (m.num_robots > 1) {
+        tiles = slot_robot;
+        count = m.num_robots;
+    }
+    hipLaunchKernelGGL((k_abia_persistent<T>), dim3(grid), dim3(64), 0, st, m, cm, nmax, tiles, count, counter, q,
+                       qd, tau, qdd, ws);
     return hipGetLastError();
 }
 
@@ -269,8 +288,9 @@ template hipError_t launch_abia<float>(const ModelView<float>&, const ChainMap&,
                                        const float*, float*, float*, hipStream_t);
 template hipError_t launch_abia_persistent<double>(const ModelView<double>&, const ChainMap&, int, int, const double*,
                                                    const double*, const double*, double*, double*, int32_t*,
-                                                   hipStream_t);
+                                                   const int32_t*, hipStream_t);
 template hipError_t launch_abia_persistent<float>(const ModelView<float>&, const ChainMap&, int, int, const float*,
-                                                  const float*, const float*, float*, float*, int32_t*, hipStream_t);
+                                                  const float*, const float*, float*, float*, int32_t*,
+                                                  const int32_t*, hipStream_t);
 
 }  // namespace fdk

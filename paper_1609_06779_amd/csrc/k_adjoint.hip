@@ -42,9 +42,9 @@ size_t vjp_workspace_elems(int batch, int nmax) {
 }
 
 template <typename T>
-__device__ __forceinline__ Pose<T> pose_il(const ModelView<T>& m, int i, int r, T q) {
+__device__ __forceinline__ Pose<T> pose_il(const ModelView<T>& m, int i, int slot, T q) {
     T rh[9], p[3];
-    m.home_il(i, r, rh, p);
+    m.home_il(i, slot, rh, p);
     return joint_pose(rh, p, q);
 }
 
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
     if (b >= cm.batch) return;
     const ChainInfo ci = chain_info(m, cm, b);
     const int n = ci.n;
-    const int r = ci.robot;
+    const int sl = ci.slot;
     T* wsb = ws + (size_t)blockIdx.x * nmax * VJP_FIELDS * 64 + lane;
     auto w = [&](int i, int f) -> T& { return wsb[((size_t)i * VJP_FIELDS + f) * 64]; };
 
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
         for (int i = n - 1; i >= 0; --i) {
             const int64_t st = ci.state0 + i;
             T jh[36], pp[6];
-            inertia_to_mat6(m.inertia_il(i, r), jh);
+            inertia_to_mat6(m.inertia_il(i, sl), jh);
             if (i + 1 < n) {
                 wrench_to_parent(tn, pc, pp);
                 T y[36];
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
                 for (int c = 0; c < 6; ++c) pi[6 * rr + c] = jh[6 * rr + c] - h[rr] * h[c] * dinv;
 #pragma unroll
             for (int c = 0; c < 6; ++c) pc[c] = pp[c] + h[c] * u * dinv;
-            tn = pose_il(m, i, r, q[st]);
+            tn = pose_il(m, i, sl, q[st]);
         }
     }
     // B: lambda, and the inverse dynamics forward sweep at the given qdd
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
         T a[6] = {T(0), T(0), T(0), -m.g[0], -m.g[1], -m.g[2]};
         for (int i = 0; i < n; ++i) {
             const int64_t st = ci.state0 + i;
-            const Pose<T> tl = pose_il(m, i, r, q[st]);
+            const Pose<T> tl = pose_il(m, i, sl, q[st]);
             T t[6];
             ad_inv_apply(tl, acc, t);
             T lam = w(i, VJP_UD);
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
 #pragma unroll
             for (int c = 0; c < 6; ++c) a[c] = t[c];
             T f[6];
-            link_force(m.inertia_il(i, r), v, a, f);
+            link_force(m.inertia_il(i, sl), v, a, f);
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
                 w(i, VJP_V + c) = v[c];
@@ -181,14 +181,14 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
                 fc[c] = f[c];
                 w(i, VJP_F + c) = f[c];
             }
-            tn = pose_il(m, i, r, q[ci.state0 + i]);
+            tn = pose_il(m, i, sl, q[ci.state0 + i]);
         }
     }
     // D: Fb_i = lambda_i S + A_i Fb_{i-1}; force term of q_bar
     {
         T fb[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
         for (int i = 0; i < n; ++i) {
-            const Pose<T> tl = pose_il(m, i, r, q[ci.state0 + i]);
+            const Pose<T> tl = pose_il(m, i, sl, q[ci.state0 + i]);
             T t[6], z[6];
             ad_inv_apply(tl, fb, t);           // A_i Fb_{i-1}
             T qf = T(0);
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
         Pose<T> tn = pose_identity<T>();
         for (int i = n - 1; i >= 0; --i) {
             const int64_t st = ci.state0 + i;
-            const Inertia<T> j = m.inertia_il(i, r);
+            const Inertia<T> j = m.inertia_il(i, sl);
             T fb[6], v[6], a[6];
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
@@ -259,7 +259,7 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
             for (int c = 0; c < 6; ++c) gq_id -= vb[c] * zv[c] + ab[c] * za[c];
             gq[st] = accumulate ? gq[st] - gq_id : -gq_id;
             gqd[st] = accumulate ? gqd[st] - gqd_id : -gqd_id;
-            tn = pose_il(m, i, r, q[st]);
+            tn = pose_il(m, i, sl, q[st]);
         }
     }
 }

@@ -25,8 +25,10 @@ template <typename T> __device__ __forceinline__ void ad_inv_rows(const Pose<T>&
 
 __device__ __forceinline__ constexpr int wsel(int a) { return a < 2 ? a : a + 1; }   // W_i coordinates
 
+// Up to 64 links: two wavefronts per SIMD (the register cap costs a small
+// spill; latency hiding between the two wins, measured 14-17 % on MI355X).
 template <typename T, int NP>
-__global__ __launch_bounds__(Geo<NP>::threads) void k_cfa(ModelView<T> m, ChainMap cm, const T* __restrict__ q,
+__global__ __launch_bounds__(Geo<NP>::threads, NP <= 64 ? 2 : 1) void k_cfa(ModelView<T> m, ChainMap cm, const T* __restrict__ q,
                                                            const T* __restrict__ qd, const T* __restrict__ tau,
                                                            T* __restrict__ qdd, int* __restrict__ status) {
     __shared__ T xbuf[NP > 64 ? 12 * NP : 1];

@@ -91,25 +91,26 @@ __global__ void k_model_init(int64_t nl, const double* __restrict__ raw, const u
     put(MF_MINV, 1.0 / m);
 }
 
-// Robot-interleaved copy of the fields the lane-per-chain kernel reads.
+// Robot-interleaved copy of the fields the lane-per-chain kernels read: link l
+// (entry `index` of its robot) goes to column `column[l]`.
 template <typename T>
-__global__ void k_model_interleave(int64_t nl, const int32_t* __restrict__ robot, const int32_t* __restrict__ index,
+__global__ void k_model_interleave(int64_t nl, const int32_t* __restrict__ column, const int32_t* __restrict__ index,
                                    int32_t num_robots, int64_t fstride, const T* __restrict__ soa, T* __restrict__ il) {
     int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= nl) return;
-    const int64_t dst = (int64_t)index[l] * num_robots + robot[l];
+    const int64_t dst = (int64_t)index[l] * num_robots + column[l];
     for (int f = 0; f < MF_IL_COUNT; ++f) il[f * fstride + dst] = soa[f * nl + l];
 }
 
-hipError_t launch_model_interleave(int64_t nl, const int32_t* robot, const int32_t* index, int32_t num_robots,
+hipError_t launch_model_interleave(int64_t nl, const int32_t* column, const int32_t* index, int32_t num_robots,
                                    int64_t fstride, const void* soa, void* il, int as_float, hipStream_t st) {
     if (nl <= 0) return hipSuccess;
     dim3 block(128), grid((unsigned)((nl + 127) / 128));
     if (as_float)
-        hipLaunchKernelGGL(k_model_interleave<float>, grid, block, 0, st, nl, robot, index, num_robots, fstride,
+        hipLaunchKernelGGL(k_model_interleave<float>, grid, block, 0, st, nl, column, index, num_robots, fstride,
                            (const float*)soa, (float*)il);
     else
-        hipLaunchKernelGGL(k_model_interleave<double>, grid, block, 0, st, nl, robot, index, num_robots, fstride,
+        hipLaunchKernelGGL(k_model_interleave<double>, grid, block, 0, st, nl, column, index, num_robots, fstride,
                            (const double*)soa, (double*)il);
     return hipGetLastError();
 }

@@ -38,11 +38,13 @@ hipError_t launch_abia(const ModelView<T>& m, const ChainMap& cm, int nmax, cons
                        const T* tau, T* qdd, T* ws, hipStream_t st);
 size_t abia_workspace_elems(int batch, int nmax);
 // ragged batches: one persistent launch over chains sorted by decreasing length
+// (slot_robot: robot of each interleaved column, used when cm has no robot ids)
 size_t persistent_plan_bytes(int batch);
 size_t abia_persistent_workspace_elems(int grid, int nmax);
 template <typename T>
 hipError_t launch_abia_persistent(const ModelView<T>& m, const ChainMap& cm, int nmax, int grid, const T* q,
-                                  const T* qd, const T* tau, T* qdd, T* ws, int32_t* plan, hipStream_t st);
+                                  const T* qd, const T* tau, T* qdd, T* ws, int32_t* plan,
+                                  const int32_t* slot_robot, hipStream_t st);
 
 // reverse mode and the rollout step
 size_t vjp_workspace_elems(int batch, int nmax);
@@ -65,7 +67,7 @@ hipError_t launch_btd6(int np, int segs, const int64_t* offsets, const T* d, con
 // model upload: canonical joint frames from raw per-link parameters (fp64 in)
 hipError_t launch_model_init(int64_t nlinks, const double* raw, const uint8_t* first, void* out,
                              int as_float, hipStream_t st);
-hipError_t launch_model_interleave(int64_t nlinks, const int32_t* robot, const int32_t* index, int32_t num_robots,
+hipError_t launch_model_interleave(int64_t nlinks, const int32_t* column, const int32_t* index, int32_t num_robots,
                                    int64_t fstride, const void* soa, void* il, int as_float, hipStream_t st);
 
 }  // namespace fdk

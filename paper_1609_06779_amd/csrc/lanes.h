@@ -39,29 +39,32 @@ template <typename T> struct ModelView {
     int32_t num_robots;
     T g[3];                       // gravity, base frame
     // Robot-interleaved copy of the first MF_IL_COUNT fields: field f of link i
-    // of robot r at il[f * il_fstride + i * num_robots + r] (il_fstride =
-    // longest robot x num_robots), so that lanes holding consecutive robots
-    // read consecutive addresses.
+    // of the robot in column c at il[f * il_fstride + i * num_robots + c]
+    // (il_fstride = longest robot x num_robots), so that lanes holding
+    // consecutive columns read consecutive addresses. Columns hold the robots
+    // sorted by decreasing length (stable: a model of equal lengths keeps its
+    // order); slot[r] is the column of robot r.
     const T* il;
     int64_t il_fstride;
+    const int32_t* slot;
 
     __device__ __forceinline__ T at(int f, int64_t l) const { return base[f * stride + l]; }
-    __device__ __forceinline__ T at_il(int f, int i, int r) const {
-        return il[f * il_fstride + (int64_t)i * num_robots + r];
+    __device__ __forceinline__ T at_il(int f, int i, int c) const {
+        return il[f * il_fstride + (int64_t)i * num_robots + c];
     }
-    __device__ __forceinline__ void home_il(int i, int r, T rh[9], T p[3]) const {
+    __device__ __forceinline__ void home_il(int i, int c, T rh[9], T p[3]) const {
 #pragma unroll
-        for (int k = 0; k < 9; ++k) rh[k] = at_il(MF_ROT + k, i, r);
+        for (int k = 0; k < 9; ++k) rh[k] = at_il(MF_ROT + k, i, c);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) p[k] = at_il(MF_POS + k, i, r);
+        for (int k = 0; k < 3; ++k) p[k] = at_il(MF_POS + k, i, c);
     }
-    __device__ __forceinline__ Inertia<T> inertia_il(int i, int r) const {
+    __device__ __forceinline__ Inertia<T> inertia_il(int i, int c) const {
         Inertia<T> j;
-        j.m = at_il(MF_MASS, i, r);
+        j.m = at_il(MF_MASS, i, c);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) j.h[k] = at_il(MF_H + k, i, r);
+        for (int k = 0; k < 3; ++k) j.h[k] = at_il(MF_H + k, i, c);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) j.ib[k] = at_il(MF_IB + k, i, r);
+        for (int k = 0; k < 6; ++k) j.ib[k] = at_il(MF_IB + k, i, c);
         return j;
     }
 
@@ -121,7 +124,10 @@ struct ChainMap {
     int32_t n_uniform;
 };
 
-struct ChainInfo { int64_t link0; int64_t state0; int n; int robot; };
+// link0: the robot's first link (structure-of-arrays fields); state0: the
+// chain's first entry in q, qd, tau; n: its links (0: skipped); slot: the
+// robot's column in the interleaved copy.
+struct ChainInfo { int64_t link0; int64_t state0; int n; int slot; };
 
 template <typename T>
 __device__ __forceinline__ ChainInfo chain_info(const ModelView<T>& m, const ChainMap& cm, int b) {
@@ -131,10 +137,10 @@ __device__ __forceinline__ ChainInfo chain_info(const ModelView<T>& m, const Cha
         ci.link0 = 0;
         ci.n = 0;
         ci.state0 = 0;
-        ci.robot = 0;
+        ci.slot = 0;
         return ci;
     }
-    ci.robot = r;
+    ci.slot = m.slot[r];
     ci.link0 = m.link_start[r];
     ci.n = m.n_links[r];
     ci.state0 = cm.offsets ? cm.offsets[b] : (int64_t)b * cm.n_uniform;
@@ -142,11 +148,50 @@ __device__ __forceinline__ ChainInfo chain_info(const ModelView<T>& m, const Cha
 }
 
 // ---------------- lane-group exchange ----------------
+// Groups of NP <= 64 lanes live in one wavefront and exchange values through
+// DPP (data-parallel primitives: a VALU operand read from another lane, no LDS
+// round trip): wave_shr/shl:1 for neighbour shifts, row_shr/shl within 16-lane
+// rows and row_bcast:15/31 across rows. Larger groups span several wavefronts
+// and go through LDS.
+namespace dpp {
+constexpr int ROW_SHL = 0x100, ROW_SHR = 0x110, WAVE_SHL1 = 0x130, WAVE_SHR1 = 0x138, ROW_BCAST15 = 0x142,
+              ROW_BCAST31 = 0x143;
+
+// Lane l takes the value that control CTRL routes to it; lanes with no source,
+// or in rows outside ROW_MASK, keep their own value.
+template <int CTRL, int ROW_MASK = 0xf> __device__ __forceinline__ double mov(double v) {
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    lo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROW_MASK, 0xf, false);
+    hi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROW_MASK, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL, int ROW_MASK = 0xf> __device__ __forceinline__ float mov(float v) {
+    int x = __float_as_int(v);
+    return __int_as_float(__builtin_amdgcn_update_dpp(x, x, CTRL, ROW_MASK, 0xf, false));
+}
+template <int CTRL, int ROW_MASK = 0xf, typename T> __device__ __forceinline__ void mov_n(const T* v, T* out, int k) {
+    for (int c = 0; c < k; ++c) out[c] = mov<CTRL, ROW_MASK>(v[c]);
+}
+// value of wavefront lane `lane` (a compile-time lane), in every lane
+template <int LANE> __device__ __forceinline__ double read(double v) {
+    int lo = __builtin_amdgcn_readlane(__double2loint(v), LANE);
+    int hi = __builtin_amdgcn_readlane(__double2hiint(v), LANE);
+    return __hiloint2double(hi, lo);
+}
+template <int LANE> __device__ __forceinline__ float read(float v) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), LANE));
+}
+}  // namespace dpp
+
 // Value of lane (li - s) of the same group (callers only use it where li >= s).
 template <int NP, typename T>
 __device__ __forceinline__ void shift_up(const T* v, T* out, int k, int s, T* lds) {
     if constexpr (NP <= 64) {
-        for (int c = 0; c < k; ++c) out[c] = __shfl_up(v[c], (unsigned)s, NP);
+        if (s == 1) {
+            dpp::mov_n<dpp::WAVE_SHR1>(v, out, k);
+        } else {
+            for (int c = 0; c < k; ++c) out[c] = __shfl_up(v[c], (unsigned)s, NP);
+        }
     } else {
         int t = threadIdx.x;
         for (int c = 0; c < k; ++c) lds[c * NP + t] = v[c];
@@ -161,7 +206,11 @@ __device__ __forceinline__ void shift_up(const T* v, T* out, int k, int s, T* ld
 template <int NP, typename T>
 __device__ __forceinline__ void shift_down(const T* v, T* out, int k, int s, T* lds) {
     if constexpr (NP <= 64) {
-        for (int c = 0; c < k; ++c) out[c] = __shfl_down(v[c], (unsigned)s, NP);
+        if (s == 1) {
+            dpp::mov_n<dpp::WAVE_SHL1>(v, out, k);
+        } else {
+            for (int c = 0; c < k; ++c) out[c] = __shfl_down(v[c], (unsigned)s, NP);
+        }
     } else {
         int t = threadIdx.x;
         for (int c = 0; c < k; ++c) lds[c * NP + t] = v[c];
@@ -173,42 +222,122 @@ __device__ __forceinline__ void shift_down(const T* v, T* out, int k, int s, T* 
 }
 
 // Inclusive prefix product of poses along the group: G_i = T_0 T_1 ... T_i.
+// Within a wavefront: Hillis-Steele steps inside each 16-lane row, then odd
+// rows take the total of the row before (row_bcast:15) and rows 2, 3 the total
+// of rows 0, 1 (row_bcast:31); the earlier part always multiplies on the left.
 template <int NP, typename T>
 __device__ __forceinline__ Pose<T> scan_pose(Pose<T> x, int li, T* lds) {
-#pragma unroll
-    for (int s = 1; s < NP; s <<= 1) {
-        Pose<T> o;
-        shift_up<NP>(x.r, o.r, 9, s, lds);
-        shift_up<NP>(x.p, o.p, 3, s, lds);
-        if (li >= s) x = pose_mul(o, x);
+    if constexpr (NP <= 64) {
+        const int lr = li & 15;
+        const int lane = threadIdx.x & 63;
+#define FDK_POSE_STEP(CTRL, MASK, COND)                 \
+    {                                                   \
+        Pose<T> o;                                      \
+        dpp::mov_n<CTRL, MASK>(x.r, o.r, 9);            \
+        dpp::mov_n<CTRL, MASK>(x.p, o.p, 3);            \
+        if (COND) x = pose_mul(o, x);                   \
     }
-    return x;
+        FDK_POSE_STEP(dpp::ROW_SHR + 1, 0xf, lr >= 1)
+        if constexpr (NP > 2) FDK_POSE_STEP(dpp::ROW_SHR + 2, 0xf, lr >= 2)
+        if constexpr (NP > 4) FDK_POSE_STEP(dpp::ROW_SHR + 4, 0xf, lr >= 4)
+        if constexpr (NP > 8) FDK_POSE_STEP(dpp::ROW_SHR + 8, 0xf, lr >= 8)
+        if constexpr (NP > 16) FDK_POSE_STEP(dpp::ROW_BCAST15, 0xa, (lane & 16) != 0)
+        if constexpr (NP > 32) FDK_POSE_STEP(dpp::ROW_BCAST31, 0xc, (lane & 32) != 0)
+#undef FDK_POSE_STEP
+        return x;
+    } else {
+#pragma unroll
+        for (int s = 1; s < NP; s <<= 1) {
+            Pose<T> o;
+            shift_up<NP>(x.r, o.r, 9, s, lds);
+            shift_up<NP>(x.p, o.p, 3, s, lds);
+            if (li >= s) x = pose_mul(o, x);
+        }
+        return x;
+    }
 }
 
-// Inclusive prefix sum of K-vectors along the group.
+// Inclusive prefix sum of K-vectors along the group (same steps as scan_pose).
 template <int NP, int K, typename T>
 __device__ __forceinline__ void scan_add(T* x, int li, T* lds) {
+    if constexpr (NP <= 64) {
+        const int lr = li & 15;
+        const int lane = threadIdx.x & 63;
+#define FDK_ADD_STEP(CTRL, MASK, COND)                  \
+    {                                                   \
+        T o[K];                                         \
+        dpp::mov_n<CTRL, MASK>(x, o, K);                \
+        if (COND) {                                     \
+            _Pragma("unroll") for (int c = 0; c < K; ++c) x[c] += o[c]; \
+        }                                               \
+    }
+        FDK_ADD_STEP(dpp::ROW_SHR + 1, 0xf, lr >= 1)
+        if constexpr (NP > 2) FDK_ADD_STEP(dpp::ROW_SHR + 2, 0xf, lr >= 2)
+        if constexpr (NP > 4) FDK_ADD_STEP(dpp::ROW_SHR + 4, 0xf, lr >= 4)
+        if constexpr (NP > 8) FDK_ADD_STEP(dpp::ROW_SHR + 8, 0xf, lr >= 8)
+        if constexpr (NP > 16) FDK_ADD_STEP(dpp::ROW_BCAST15, 0xa, (lane & 16) != 0)
+        if constexpr (NP > 32) FDK_ADD_STEP(dpp::ROW_BCAST31, 0xc, (lane & 32) != 0)
+#undef FDK_ADD_STEP
+    } else {
 #pragma unroll
-    for (int s = 1; s < NP; s <<= 1) {
-        T o[K];
-        shift_up<NP>(x, o, K, s, lds);
-        if (li >= s) {
+        for (int s = 1; s < NP; s <<= 1) {
+            T o[K];
+            shift_up<NP>(x, o, K, s, lds);
+            if (li >= s) {
 #pragma unroll
-            for (int c = 0; c < K; ++c) x[c] += o[c];
+                for (int c = 0; c < K; ++c) x[c] += o[c];
+            }
         }
     }
 }
 
-// Inclusive suffix sum of K-vectors along the group.
+// Inclusive suffix sum of K-vectors along the group. Within a wavefront:
+// Hillis-Steele steps inside each 16-lane row (row_shl), then even rows add
+// the total of the row after it and rows 0, 1 the total of rows 2, 3, read
+// from the first lane of those rows.
 template <int NP, int K, typename T>
 __device__ __forceinline__ void scan_add_rev(T* x, int li, T* lds) {
+    if constexpr (NP <= 64) {
+        constexpr int W = NP < 16 ? NP : 16;     // lanes of a group inside one row
+        const int lr = li & 15;
+        const int lane = threadIdx.x & 63;
+#define FDK_REV_STEP(S)                                 \
+    {                                                   \
+        T o[K];                                         \
+        dpp::mov_n<dpp::ROW_SHL + S, 0xf>(x, o, K);     \
+        if (lr + S < W) {                               \
+            _Pragma("unroll") for (int c = 0; c < K; ++c) x[c] += o[c]; \
+        }                                               \
+    }
+        FDK_REV_STEP(1)
+        if constexpr (NP > 2) FDK_REV_STEP(2)
+        if constexpr (NP > 4) FDK_REV_STEP(4)
+        if constexpr (NP > 8) FDK_REV_STEP(8)
+#undef FDK_REV_STEP
+        if constexpr (NP > 16) {
+            // rows 0 and 2 add the totals of rows 1 and 3 (first lanes 16 and 48)
 #pragma unroll
-    for (int s = 1; s < NP; s <<= 1) {
-        T o[K];
-        shift_down<NP>(x, o, K, s, lds);
-        if (li + s < NP) {
+            for (int c = 0; c < K; ++c) {
+                const T a = dpp::read<16>(x[c]), b = dpp::read<48>(x[c]);
+                if ((lane & 16) == 0) x[c] += (lane & 32) ? b : a;
+            }
+        }
+        if constexpr (NP > 32) {
 #pragma unroll
-            for (int c = 0; c < K; ++c) x[c] += o[c];
+            for (int c = 0; c < K; ++c) {
+                const T a = dpp::read<32>(x[c]);
+                if (lane < 32) x[c] += a;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int s = 1; s < NP; s <<= 1) {
+            T o[K];
+            shift_down<NP>(x, o, K, s, lds);
+            if (li + s < NP) {
+#pragma unroll
+                for (int c = 0; c < K; ++c) x[c] += o[c];
+            }
         }
     }
 }
