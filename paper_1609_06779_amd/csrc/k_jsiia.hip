@@ -99,27 +99,32 @@ __global__ __launch_bounds__(64) void k_jsiia_gj(ModelView<T> m, ChainMap cm, co
 }
 
 
-// Gauss-Jordan with M distributed over a G x G grid of lanes, G = NP / 8 (one
-// chain per workgroup: 64 lanes for NP = 64, 256 for NP = 128): lane (r, c)
-// owns the entries (i, k) = (r + G a, c + G b), a, b = 0..7, and the
-// right-hand side of its rows. At step j the lanes of column group j % G
-// publish column j through LDS (it is also the pivot row: the trailing block
-// stays symmetric); every lane then reads its 8 row multipliers and the
-// pivot-row entries of its columns, and updates its block. Column blocks left
-// of j / G hold only eliminated columns and are skipped at compile time. The
-// inverse dynamics before it runs lane per link on all TH = G * G lanes.
+// Chains of up to 64 or 128 links: M spread over a G x G grid of lanes,
+// G = NP / 8 (one chain per workgroup: 64 lanes for NP = 64, 256 for
+// NP = 128). Lane (r, c) owns the entries (i, k) = (r + G a, c + G b) with
+// a >= b, a, b = 0..7 (the lower triangle, 36 entries), and the right-hand
+// side of its rows. M is SPD, so symmetric elimination without pivoting
+// (M = L D L^T) is stable:
+//  * step j: the lanes of column group j % G publish column j (rows >= j)
+//    through LDS; every lane reads its row multipliers m_ij / m_jj and the
+//    column entries m_kj of its columns and updates m_ik -= m_ij m_kj / m_jj
+//    for i >= k > j, and b_i -= (m_ij / m_jj) b_j (forward substitution);
+//    column j then holds D and L (L_ij = m_ij / m_jj);
+//  * back substitution L^T x = D^-1 b by blocks of G rows (below).
+// Blocks outside the trailing part are skipped at compile time. The inverse
+// dynamics before it runs lane per link on all TH = G * G lanes.
 template <typename T, int NP>
-__global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_gj2d(ModelView<T> m, ChainMap cm,
-                                                                     const T* __restrict__ q,
-                                                                     const T* __restrict__ qd,
-                                                                     const T* __restrict__ tau, T* __restrict__ qdd,
-                                                                     int* __restrict__ status) {
+__global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> m, ChainMap cm,
+                                                                    const T* __restrict__ q,
+                                                                    const T* __restrict__ qd,
+                                                                    const T* __restrict__ tau, T* __restrict__ qdd,
+                                                                    int* __restrict__ status) {
     constexpr int G = NP / 8;
     constexpr int TH = G * G;
     static_assert(TH >= NP, "the lane grid must cover one lane per link");
     __shared__ T xbuf[TH > 64 ? 10 * TH : 1];   // cross-wavefront scan exchange
     __shared__ T sf[NP * 13];                   // s (6), F (6), tau_delta per link
-    __shared__ T col[2][NP + 1];                // pivot column and the pivot row's right-hand side
+    __shared__ T col[2][NP + 1];                // published column (row) and its right-hand side entry
     const int li = threadIdx.x;
     ChainInfo ci{0, 0, 0, 0};
     if ((int)blockIdx.x < cm.batch) ci = chain_info(m, cm, blockIdx.x);
@@ -143,74 +148,103 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_gj2d(ModelView<T>
     __syncthreads();
 
     const int r = li / G, c = li % G;
-    T mb[8][8], y[8], diag[8];
+    // lower blocks a >= b, packed: index a (a + 1) / 2 + b
+    T mb[36], y[8], rd[8];
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
         const int i = r + G * a;
-        T si[6], fi[6];
+        T fi[6];
 #pragma unroll
-        for (int e = 0; e < 6; ++e) {
-            si[e] = sf[e * NP + i];
-            fi[e] = sf[(6 + e) * NP + i];
-        }
+        for (int e = 0; e < 6; ++e) fi[e] = sf[(6 + e) * NP + i];
         y[a] = sf[12 * NP + i];
-        diag[a] = T(1);
 #pragma unroll
-        for (int bb = 0; bb < 8; ++bb) {
+        for (int bb = 0; bb <= a; ++bb) {
             const int kk = c + G * bb;
-            T lo = T(0), up = T(0);
+            T v = T(0);
 #pragma unroll
-            for (int e = 0; e < 6; ++e) {
-                lo += sf[e * NP + kk] * fi[e];          // k <= i: s_k . F_i
-                up += si[e] * sf[(6 + e) * NP + kk];    // k >  i: s_i . F_k
-            }
-            const T v = kk <= i ? lo : up;
-            mb[a][bb] = (i < n && kk < n) ? v : (i == kk ? T(1) : T(0));
+            for (int e = 0; e < 6; ++e) v += sf[e * NP + kk] * fi[e];   // k <= i: s_k . F_i
+            mb[a * (a + 1) / 2 + bb] = (i < n && kk < n) ? v : (i == kk ? T(1) : T(0));
         }
     }
     bool ok = true;
-    // column block jb is a compile-time index (register arrays stay in registers);
-    // the step inside the block, jr, is a run-time value used only in comparisons
+    // Column block jb is a compile-time index (register arrays stay in
+    // registers); the step inside the block, jr, is a run-time value used only
+    // in comparisons.
 #pragma unroll
     for (int jb = 0; jb < 8; ++jb)
 #pragma unroll 1
     for (int jr = 0; jr < G; ++jr) {
         const int j = G * jb + jr;
-        T* cj = col[j & 1];
+        T* cj = col[jr & 1];
         if (c == jr) {
 #pragma unroll
-            for (int a = 0; a < 8; ++a) cj[r + G * a] = mb[a][jb];
+            for (int a = jb; a < 8; ++a) cj[r + G * a] = mb[a * (a + 1) / 2 + jb];
             if (r == jr) cj[NP] = y[jb];
         }
         __syncthreads();
         const T piv = cj[j];
         const T rp = rcp_refined(piv);
         const T yj = cj[NP];
-        T fa[8];
-#pragma unroll
-        for (int a = 0; a < 8; ++a) {
-            const T v = cj[r + G * a] * rp;
-            fa[a] = (r + G * a == j) ? T(0) : v;
-        }
         if (r == jr) {
-            diag[jb] = piv;
+            rd[jb] = rp;
             ok = ok && piv > T(0);
         }
+        T fa[8], pv[8];
 #pragma unroll
-        for (int bb = jb; bb < 8; ++bb) {
-            T pv = cj[c + G * bb];
-            if (bb == jb) pv = c > jr ? pv : T(0);      // only columns right of the pivot
-#pragma unroll
-            for (int a = 0; a < 8; ++a) mb[a][bb] -= fa[a] * pv;
+        for (int a = jb; a < 8; ++a) {
+            const T v = cj[r + G * a] * rp;
+            fa[a] = (r + G * a > j) ? v : T(0);             // L_ij, rows below the pivot
+            const T w = cj[c + G * a];
+            pv[a] = (c + G * a > j) ? w : T(0);             // m_kj, columns right of the pivot
         }
 #pragma unroll
-        for (int a = 0; a < 8; ++a) y[a] -= fa[a] * yj;
+        for (int a = jb; a < 8; ++a) {
+#pragma unroll
+            for (int bb = jb; bb <= a; ++bb) mb[a * (a + 1) / 2 + bb] -= fa[a] * pv[bb];
+            y[a] -= fa[a] * yj;
+        }
+    }
+    // Back substitution L^T x = D^-1 b in blocks of G rows, last block first.
+    // Row block jb is published once (entries m_jk, k <= j, and the block's
+    // z = D^-1 b and 1 / d). Lane (r, c) then carries x of the block's row c:
+    // each unknown of the block, and each correction of a row above it, is a
+    // sum over the block's rows, one term per lane of a row group (G
+    // consecutive lanes), summed by dpp::group_sum. The buffer reuses LDS that
+    // is free after the M build.
+    T* wbuf = TH > 64 ? xbuf : sf;                          // G rows of NP entries, then z (G), 1/d (G)
+    static_assert((TH > 64 ? 10 * TH : NP * 13) >= G * NP + 2 * G, "block rows fit the reused buffer");
+    T* zb = wbuf + G * NP;
+    T* rb = zb + G;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) y[a] *= rd[a];
+#pragma unroll
+    for (int jb = 7; jb >= 0; --jb) {
+        __syncthreads();                                    // earlier reads of the buffer are done
+#pragma unroll
+        for (int bb = 0; bb <= jb; ++bb) wbuf[r * NP + c + G * bb] = mb[jb * (jb + 1) / 2 + bb];
+        if (c == 0) {
+            zb[r] = y[jb];
+            rb[r] = rd[jb];
+        }
+        __syncthreads();
+        // x_t = z_t - (1 / d_t) sum_{u > t} m_ut x_u within the block
+        T xc = T(0);
+#pragma unroll
+        for (int t = G - 1; t >= 0; --t) {
+            const T part = c > t ? wbuf[c * NP + G * jb + t] * xc : T(0);
+            const T xt = zb[t] - dpp::group_sum<G>(part) * rb[t];
+            xc = c == t ? xt : xc;
+            if (r == t) y[jb] = xt;
+        }
+        // rows k above the block: z_k -= (1 / d_k) sum_t m_tk x_t
+#pragma unroll
+        for (int a = 0; a < jb; ++a) y[a] -= dpp::group_sum<G>(wbuf[c * NP + r + G * a] * xc) * rd[a];
     }
     if (c == 0) {
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
             const int i = r + G * a;
-            if (i < n) qdd[ci.state0 + i] = y[a] / diag[a];
+            if (i < n) qdd[ci.state0 + i] = y[a];
         }
     }
     if (c == 0 && !ok && status) atomicOr(status, 1);
@@ -227,7 +261,7 @@ hipError_t launch_jsiia(int np, const ModelView<T>& m, const ChainMap& cm, const
     hipLaunchKernelGGL((k_jsiia_gj<T, P>), dim3((cm.batch + Geo<P>::chains - 1) / Geo<P>::chains),  \
                        dim3(64), 0, st, m, cm, q, qd, tau, qdd, status)
 #define GJ2D(P)                                                                                      \
-    hipLaunchKernelGGL((k_jsiia_gj2d<T, P>), dim3(cm.batch), dim3((P / 8) * (P / 8)), 0, st, m, cm, q, qd, tau, \
+    hipLaunchKernelGGL((k_jsiia_ldl<T, P>), dim3(cm.batch), dim3((P / 8) * (P / 8)), 0, st, m, cm, q, qd, tau, \
                        qdd, status)
     switch (np) {
         case 8: GJ(8); break;

@@ -155,7 +155,8 @@ __device__ __forceinline__ ChainInfo chain_info(const ModelView<T>& m, const Cha
 // and go through LDS.
 namespace dpp {
 constexpr int ROW_SHL = 0x100, ROW_SHR = 0x110, WAVE_SHL1 = 0x130, WAVE_SHR1 = 0x138, ROW_BCAST15 = 0x142,
-              ROW_BCAST31 = 0x143;
+              ROW_BCAST31 = 0x143, QUAD_XOR1 = 0xB1, QUAD_XOR2 = 0x4E, ROW_MIRROR = 0x140,
+              ROW_HALF_MIRROR = 0x141;
 
 // Lane l takes the value that control CTRL routes to it; lanes with no source,
 // or in rows outside ROW_MASK, keep their own value.
@@ -180,6 +181,18 @@ template <int LANE> __device__ __forceinline__ double read(double v) {
 }
 template <int LANE> __device__ __forceinline__ float read(float v) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), LANE));
+}
+// Sum over each aligned group of W = 8 or 16 consecutive lanes, in every lane
+// of the group: a butterfly (lane i pairs with i^1, i^2, then the mirrored
+// half), so every lane adds the same operands in the same order and the
+// groups' lanes hold bitwise equal sums.
+template <int W, typename T> __device__ __forceinline__ T group_sum(T v) {
+    static_assert(W == 8 || W == 16, "groups of 8 or 16 lanes");
+    v += mov<QUAD_XOR1>(v);
+    v += mov<QUAD_XOR2>(v);
+    v += mov<ROW_HALF_MIRROR>(v);
+    if constexpr (W == 16) v += mov<ROW_MIRROR>(v);
+    return v;
 }
 }  // namespace dpp
 
