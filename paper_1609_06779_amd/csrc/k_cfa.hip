@@ -17,12 +17,6 @@
 
 namespace fdk {
 
-// rows of Ad(T^-1) X for X given by rows: y_row = Ad(T^-1) x_row
-template <typename T> __device__ __forceinline__ void ad_inv_rows(const Pose<T>& t, const T x[36], T y[36]) {
-#pragma unroll
-    for (int r = 0; r < 6; ++r) ad_inv_apply(t, x + 6 * r, y + 6 * r);
-}
-
 __device__ __forceinline__ constexpr int wsel(int a) { return a < 2 ? a : a + 1; }   // W_i coordinates
 
 // Up to 64 links: two wavefronts per SIMD (the register cap costs a small
@@ -48,44 +42,41 @@ __global__ __launch_bounds__(Geo<NP>::threads, NP <= 64 ? 2 : 1) void k_cfa(Mode
     const T tb = rnea_lane<T, NP>(m, link, active, qi, qdi, T(0), true, li, xbuf, k);
     const T td = active ? ti - tb : T(0);
 
-    // Phi_ii
-    T phi[36];
-    T pnx[36];            // Phi_{i,i+1}
+    // Phi_ii = J_i^-1 + Ad_i J_{i-1}^-1 Ad_i^T. The second term is link i-1's
+    // inverse inertia re-expressed in frame i, built from its parameters
+    // (taken from lane li - 1) moved into frame i.
+    T ip[10], iq[10];
     if (active) {
-        m.inertia_inv(link, phi);
-        if (li > 0) {
-            T jp[36], y[36], z[36];
-            m.inertia_inv(link - 1, jp);
-            ad_inv_rows(k.tl, jp, y);            // rows of Ad jp (jp symmetric: rows = columns)
-            // (Ad jp Ad^T): row r = Ad (row r of (Ad jp))^T ... use symmetry of Ad jp Ad^T:
-            // z = Ad * y^T applied column-wise, i.e. z_row_r = Ad (column r of y)
-#pragma unroll
-            for (int r = 0; r < 6; ++r) {
-                T col[6];
-#pragma unroll
-                for (int c = 0; c < 6; ++c) col[c] = y[6 * c + r];
-                ad_inv_apply(k.tl, col, z + 6 * r);
-            }
-#pragma unroll
-            for (int c = 0; c < 36; ++c) phi[c] += z[c];
-        }
+        m.inertia_inv_params(link, ip);
     } else {
 #pragma unroll
-        for (int c = 0; c < 36; ++c) phi[c] = T(0);
+        for (int c = 0; c < 10; ++c) ip[c] = (c < 3 || c == 9) ? T(1) : T(0);
+    }
+    shift_up<NP>(ip, iq, 10, 1, xbuf);
+    T jinv[36], phi[36];
+    inv_inertia6(ip, jinv);
+    if (active && li > 0) {
+        T ic[10], z[36];
+        inv_inertia_to_child(k.tl, iq, ic);
+        inv_inertia6(ic, z);
+#pragma unroll
+        for (int c = 0; c < 36; ++c) phi[c] = jinv[c] + z[c];
+    } else {
+#pragma unroll
+        for (int c = 0; c < 36; ++c) phi[c] = active ? jinv[c] : T(0);
     }
     // Phi_{i,i+1} = -J_i^-1 Ad_{i+1}^T: row r = -(Ad_{i+1} (row r of J_i^-1))^T
+    T pnx[36];
     Pose<T> tn;
     shift_down<NP>(k.tl.r, tn.r, 9, 1, xbuf);
     shift_down<NP>(k.tl.p, tn.p, 3, 1, xbuf);
     const bool has_next = active && li + 1 < n;
     const bool has_prev = active && li > 0;
     if (has_next) {
-        T ji[36];
-        m.inertia_inv(link, ji);
 #pragma unroll
         for (int r = 0; r < 6; ++r) {
             T y[6];
-            ad_inv_apply(tn, ji + 6 * r, y);
+            ad_inv_apply(tn, jinv + 6 * r, y);
 #pragma unroll
             for (int c = 0; c < 6; ++c) pnx[6 * r + c] = -y[c];
         }

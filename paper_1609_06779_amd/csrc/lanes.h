@@ -31,6 +31,55 @@ enum ModelField {
     MF_IL_COUNT = 22   // fields MF_ROT .. MF_IB also kept robot-interleaved
 };
 
+// J^-1 = [[Ic^-1, -Ic^-1 [c]], [[c] Ic^-1, 1/m - [c] Ic^-1 [c]]] (row-major 6x6)
+// from p = (Ic^-1 as xx yy zz xy xz yz, c, 1/m): the inverse of the spatial
+// inertia about the frame origin.
+template <typename T> __device__ __forceinline__ void inv_inertia6(const T p[10], T m[36]) {
+    const T* s = p;
+    const T* c = p + 6;
+    const T mi = p[9];
+    T a[9] = {s[0], s[3], s[4], s[3], s[1], s[5], s[4], s[5], s[2]};
+    // X = a [c]  (X[r][k] = sum_j a[r][j] [c][j][k])
+    T cx[9] = {T(0), -c[2], c[1], c[2], T(0), -c[0], -c[1], c[0], T(0)};
+    T x[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            x[3 * r + k] = a[3 * r] * cx[k] + a[3 * r + 1] * cx[3 + k] + a[3 * r + 2] * cx[6 + k];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            m[6 * r + k] = a[3 * r + k];
+            m[6 * r + k + 3] = -x[3 * r + k];        // -a [c]
+            m[6 * (r + 3) + k] = -x[3 * k + r];      // [c] a = -(a [c])^T
+            // 1/m - [c] a [c] = 1/m + (a [c])^T [c]
+            T y = cx[r] * x[k] + cx[3 + r] * x[3 + k] + cx[6 + r] * x[6 + k];
+            m[6 * (r + 3) + k + 3] = (r == k ? mi : T(0)) + y;
+        }
+}
+
+// The same body's inverse-inertia parameters in the child frame of t = (R, p):
+// c' = R^T (c - p), Ic'^-1 = R^T Ic^-1 R, 1/m unchanged. inv_inertia6 of the
+// result equals Ad(t^-1) J^-1 Ad(t^-1)^T.
+template <typename T> __device__ __forceinline__ void inv_inertia_to_child(const Pose<T>& t, const T p[10], T o[10]) {
+    const T* s = p;
+    const T a[9] = {s[0], s[3], s[4], s[3], s[1], s[5], s[4], s[5], s[2]};
+    T b[9];                                          // a R
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) b[3 * r + k] = a[3 * r] * t.r[k] + a[3 * r + 1] * t.r[3 + k] + a[3 * r + 2] * t.r[6 + k];
+    // (R^T b)[i][k] = sum_j R[j][i] b[j][k]
+    auto rtb = [&](int i, int k) { return t.r[i] * b[k] + t.r[3 + i] * b[3 + k] + t.r[6 + i] * b[6 + k]; };
+    o[0] = rtb(0, 0); o[1] = rtb(1, 1); o[2] = rtb(2, 2);
+    o[3] = rtb(0, 1); o[4] = rtb(0, 2); o[5] = rtb(1, 2);
+    const T d[3] = {p[6] - t.p[0], p[7] - t.p[1], p[8] - t.p[2]};
+    matTvec3(t.r, d, o + 6);
+    o[9] = p[9];
+}
+
 template <typename T> struct ModelView {
     const T* base;
     int64_t stride;               // total links of the model
@@ -85,34 +134,18 @@ template <typename T> struct ModelView {
         return j;
     }
 
-    // J^-1 = [[Ic^-1, -Ic^-1 [c]], [[c] Ic^-1, 1/m - [c] Ic^-1 [c]]] as a full 6x6 (row-major)
+    // inverse-inertia parameters of link l: Ic^-1 (xx yy zz xy xz yz), c, 1/m
+    __device__ __forceinline__ void inertia_inv_params(int64_t l, T p[10]) const {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) p[k] = at(MF_ICINV + k, l);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) p[6 + k] = at(MF_COM + k, l);
+        p[9] = at(MF_MINV, l);
+    }
     __device__ __forceinline__ void inertia_inv(int64_t l, T m[36]) const {
-        T s[6], c[3];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) s[k] = at(MF_ICINV + k, l);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) c[k] = at(MF_COM + k, l);
-        T mi = at(MF_MINV, l);
-        T a[9] = {s[0], s[3], s[4], s[3], s[1], s[5], s[4], s[5], s[2]};
-        // X = a [c]  (X[r][k] = sum_j a[r][j] [c][j][k])
-        T cx[9] = {T(0), -c[2], c[1], c[2], T(0), -c[0], -c[1], c[0], T(0)};
-        T x[9];
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-                x[3 * r + k] = a[3 * r] * cx[k] + a[3 * r + 1] * cx[3 + k] + a[3 * r + 2] * cx[6 + k];
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                m[6 * r + k] = a[3 * r + k];
-                m[6 * r + k + 3] = -x[3 * r + k];        // -a [c]
-                m[6 * (r + 3) + k] = -x[3 * k + r];      // [c] a = -(a [c])^T
-                // 1/m - [c] a [c] = 1/m + (a [c])^T [c]
-                T y = cx[r] * x[k] + cx[3 + r] * x[3 + k] + cx[6 + r] * x[6 + k];
-                m[6 * (r + 3) + k + 3] = (r == k ? mi : T(0)) + y;
-            }
+        T p[10];
+        inertia_inv_params(l, p);
+        inv_inertia6(p, m);
     }
 };
 
