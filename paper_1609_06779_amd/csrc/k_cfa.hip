@@ -25,8 +25,11 @@ template <typename T, int NP>
 __global__ __launch_bounds__(Geo<NP>::threads, NP <= 64 ? 2 : 1) void k_cfa(ModelView<T> m, ChainMap cm, const T* __restrict__ q,
                                                            const T* __restrict__ qd, const T* __restrict__ tau,
                                                            T* __restrict__ qdd, int* __restrict__ status) {
-    __shared__ T xbuf[NP > 64 ? 12 * NP : 1];
-    __shared__ T oslot[Geo<NP>::chains * NP * OeeSlot<5>::size];
+    // one array: the cross-wavefront scan exchange (NP > 64 only), then the OEE slots
+    constexpr int XB = NP > 64 ? 12 * NP : 0;
+    __shared__ T lds_all[XB + Geo<NP>::chains * NP * OeeSlot<5>::size];
+    T* xbuf = lds_all;
+    T* oslot = lds_all + XB;
     const int grp = threadIdx.x / NP, li = threadIdx.x % NP;
     const int b = blockIdx.x * Geo<NP>::chains + grp;
     ChainInfo ci{0, 0, 0, 0};

@@ -10,25 +10,26 @@
 //   R_i <- R_i - E_i R_{i+s} - K_i R_{i-s}
 //   U_i <- -E_i U_{i+s}             (zero once i + 2s is past the last row)
 // After ceil(log2 n) levels the system is block diagonal and x_i = D_i^-1 R_i.
-// Each row publishes its Cholesky factor, U and R once per level through LDS,
-// so every D is factored once per level.
+// Every D is factored once per level, by its own row, which publishes through
+// LDS what its neighbours need (two phases per level, see oee_solve_rows).
 #pragma once
 #include "spatial.h"
 
 namespace fdk {
 
 template <int K> struct OeeSlot {
-    static constexpr int L = K * (K + 1) / 2;   // packed lower factor (diagonal = 1/L_jj)
-    static constexpr int U = K * K;
-    static constexpr int R = K;
-    static constexpr int size = L + U + R;
+    static constexpr int L = K * (K + 1) / 2;   // packed lower factor of D (diagonal = 1/L_jj)
+    static constexpr int A = 2 * L + 2 * K;     // phase A: factor, L^-1 R, U^T D^-1 U (packed), U^T D^-1 R
+    static constexpr int B = K * K;             // phase B: D^-1 U
+    static constexpr int size = A > B ? A : B;
 };
 
 template <int K> __device__ __forceinline__ constexpr int tri(int r, int c) { return r * (r + 1) / 2 + c; }
 
-// Solve (L L^T) x = b with a packed factor read from LDS (component stride np).
+// x <- L^-1 x with a packed factor (diagonal = 1/L_jj); component c of the
+// factor at lf[c * np] (np = 1 for a register array).
 template <typename T, int K>
-__device__ __forceinline__ void packed_solve(const T* lf, int np, T x[K]) {
+__device__ __forceinline__ void packed_fwd(const T* lf, int np, T x[K]) {
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         T s = x[i];
@@ -36,28 +37,46 @@ __device__ __forceinline__ void packed_solve(const T* lf, int np, T x[K]) {
         for (int k = 0; k < i; ++k) s -= lf[tri<K>(i, k) * np] * x[k];
         x[i] = s * lf[tri<K>(i, i) * np];
     }
+}
+
+// x <- L^-T x with a packed factor held in registers
+template <typename T, int K> __device__ __forceinline__ void packed_bwd(const T lp[], T x[K]) {
 #pragma unroll
     for (int i = K - 1; i >= 0; --i) {
         T s = x[i];
 #pragma unroll
-        for (int k = i + 1; k < K; ++k) s -= lf[tri<K>(k, i) * np] * x[k];
-        x[i] = s * lf[tri<K>(i, i) * np];
+        for (int k = i + 1; k < K; ++k) s -= lp[tri<K>(k, i)] * x[k];
+        x[i] = s * lp[tri<K>(i, i)];
     }
 }
 
 // slot: this group's LDS area, OeeSlot<K>::size * NP values, component-major
 // (component c of row r at slot[c * NP + r]). All threads of the block must
 // call this (it synchronises); rows with active == false only take part in the
-// barriers. On return r holds x_i. Returns false if a pivot was not positive.
+// barriers. Only the lower triangle of d is read or written. On return r
+// holds x_i. Returns false if a pivot was not positive.
+//
+// Each level runs in two phases, so that one row's slot holds at most
+// max(A, B) values:
+//  A. every row factors its own D = L L^T and publishes L, L^-1 R and, for
+//     the row below it (i + s), the whole K-part: K_{i+s} U_i = U^T D^-1 U
+//     and K_{i+s} R_i = U^T D^-1 R. The E-part reads L_{i+s} and L^-1 R_{i+s}:
+//     with T = L_{i+s}^-1 U_i^T, E_i U_i^T = T^T T and E_i R_{i+s} =
+//     T^T (L^-1 R)_{i+s}.
+//  B. every row publishes D^-1 U; the E-part sets U_i <- -U_i (D^-1 U)_{i+s}.
 template <typename T, int K, int NP>
 __device__ bool oee_solve_rows(T d[K * K], T u[K * K], T r[K], int i, int n, bool active, T* slot) {
     using S = OeeSlot<K>;
-    T* sl = slot;
-    T* su = slot + S::L * NP;
-    T* sr = su + S::U * NP;
+    constexpr int L = S::L;
+    T* sl = slot;                 // phase A
+    T* sw = sl + L * NP;
+    T* sg = sw + K * NP;
+    T* sq = sg + L * NP;
+    T* sv = slot;                 // phase B
     bool ok = true;
 #pragma unroll 1
     for (int s = 1; s < NP; s <<= 1) {
+        T lp[L];                                   // own factor, kept for phase B
         if (active) {
             T l[K * K];
 #pragma unroll
@@ -66,45 +85,103 @@ __device__ bool oee_solve_rows(T d[K * K], T u[K * K], T r[K], int i, int n, boo
 #pragma unroll
             for (int a = 0; a < K; ++a)
 #pragma unroll
-                for (int b = 0; b <= a; ++b) sl[tri<K>(a, b) * NP + i] = l[a * K + b];
+                for (int b = 0; b <= a; ++b) lp[tri<K>(a, b)] = l[a * K + b];
+            T w[K][K], wr[K];                      // w[b] = L^-1 (column b of U), wr = L^-1 R
 #pragma unroll
-            for (int c = 0; c < K * K; ++c) su[c * NP + i] = u[c];
+            for (int b = 0; b < K; ++b) {
 #pragma unroll
-            for (int c = 0; c < K; ++c) sr[c * NP + i] = r[c];
+                for (int c = 0; c < K; ++c) w[b][c] = u[c * K + b];
+                packed_fwd<T, K>(lp, 1, w[b]);
+            }
+#pragma unroll
+            for (int c = 0; c < K; ++c) wr[c] = r[c];
+            packed_fwd<T, K>(lp, 1, wr);
+#pragma unroll
+            for (int c = 0; c < L; ++c) sl[c * NP + i] = lp[c];
+#pragma unroll
+            for (int c = 0; c < K; ++c) sw[c * NP + i] = wr[c];
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+#pragma unroll
+                for (int b = 0; b <= a; ++b) {
+                    T g = T(0);
+#pragma unroll
+                    for (int c = 0; c < K; ++c) g += w[a][c] * w[b][c];
+                    sg[tri<K>(a, b) * NP + i] = g;
+                }
+                T q = T(0);
+#pragma unroll
+                for (int c = 0; c < K; ++c) q += w[a][c] * wr[c];
+                sq[a * NP + i] = q;
+            }
         }
         __syncthreads();
         if (active && i + s < n) {
-            // E-part: rows processed last to first so D's lower triangle reads old U rows.
             const int j = i + s;
-            T un[K * K];
+            T wj[K];
 #pragma unroll
-            for (int c = 0; c < K * K; ++c) un[c] = su[c * NP + j];
-            T rn[K];
+            for (int c = 0; c < K; ++c) wj[c] = sw[c * NP + j];
+            T t[K][K];                             // t[a] = L_j^-1 (row a of U_i)
 #pragma unroll
-            for (int c = 0; c < K; ++c) rn[c] = sr[c * NP + j];
-            const bool keep_u = i + 2 * s < n;
+            for (int a = 0; a < K; ++a) {
 #pragma unroll
-            for (int a = K - 1; a >= 0; --a) {
-                T e[K];
+                for (int c = 0; c < K; ++c) t[a][c] = u[a * K + c];
+                packed_fwd<T, K>(sl + j, NP, t[a]);
+            }
 #pragma unroll
-                for (int c = 0; c < K; ++c) e[c] = u[a * K + c];
-                packed_solve<T, K>(sl + j, NP, e);          // e = row a of E_i
+            for (int a = 0; a < K; ++a) {
 #pragma unroll
                 for (int b = 0; b <= a; ++b) {
                     T acc = T(0);
 #pragma unroll
-                    for (int c = 0; c < K; ++c) acc += e[c] * u[b * K + c];
+                    for (int c = 0; c < K; ++c) acc += t[a][c] * t[b][c];
                     d[a * K + b] -= acc;
                 }
                 T acc = T(0);
 #pragma unroll
-                for (int c = 0; c < K; ++c) acc += e[c] * rn[c];
+                for (int c = 0; c < K; ++c) acc += t[a][c] * wj[c];
                 r[a] -= acc;
+            }
+        }
+        if (active && i - s >= 0) {
+            const int p = i - s;
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+#pragma unroll
+                for (int b = 0; b <= a; ++b) d[a * K + b] -= sg[tri<K>(a, b) * NP + p];
+                r[a] -= sq[a * NP + p];
+            }
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int b = 0; b < K; ++b) {
+                T x[K];
+#pragma unroll
+                for (int c = 0; c < K; ++c) x[c] = u[c * K + b];
+                packed_fwd<T, K>(lp, 1, x);
+                packed_bwd<T, K>(lp, x);
+#pragma unroll
+                for (int c = 0; c < K; ++c) sv[(c * K + b) * NP + i] = x[c];
+            }
+        }
+        __syncthreads();
+        if (active && i + s < n) {
+            const int j = i + s;
+            const bool keep_u = i + 2 * s < n;
+            T vj[K * K];
+#pragma unroll
+            for (int c = 0; c < K * K; ++c) vj[c] = sv[c * NP + j];
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+                T row[K];
+#pragma unroll
+                for (int c = 0; c < K; ++c) row[c] = u[a * K + c];
 #pragma unroll
                 for (int b = 0; b < K; ++b) {
                     T v = T(0);
 #pragma unroll
-                    for (int c = 0; c < K; ++c) v += e[c] * un[c * K + b];
+                    for (int c = 0; c < K; ++c) v += row[c] * vj[c * K + b];
                     u[a * K + b] = keep_u ? -v : T(0);
                 }
             }
@@ -112,41 +189,7 @@ __device__ bool oee_solve_rows(T d[K * K], T u[K * K], T r[K], int i, int n, boo
 #pragma unroll
             for (int c = 0; c < K * K; ++c) u[c] = T(0);
         }
-        if (active && i - s >= 0) {
-            // K-part: (K_i U_{i-s})[a][b] = y_a . U_{i-s}[:, b] with y_a = D_{i-s}^-1 U_{i-s}[:, a]
-            const int j = i - s;
-            T up[K * K];
-#pragma unroll
-            for (int c = 0; c < K * K; ++c) up[c] = su[c * NP + j];
-            T rp[K];
-#pragma unroll
-            for (int c = 0; c < K; ++c) rp[c] = sr[c * NP + j];
-#pragma unroll
-            for (int a = 0; a < K; ++a) {
-                T y[K];
-#pragma unroll
-                for (int c = 0; c < K; ++c) y[c] = up[c * K + a];
-                packed_solve<T, K>(sl + j, NP, y);
-#pragma unroll
-                for (int b = 0; b <= a; ++b) {
-                    T acc = T(0);
-#pragma unroll
-                    for (int c = 0; c < K; ++c) acc += y[c] * up[c * K + b];
-                    d[a * K + b] -= acc;
-                }
-                T acc = T(0);
-#pragma unroll
-                for (int c = 0; c < K; ++c) acc += y[c] * rp[c];
-                r[a] -= acc;
-            }
-        }
-        if (active) {
-#pragma unroll
-            for (int a = 0; a < K; ++a)
-#pragma unroll
-                for (int b = a + 1; b < K; ++b) d[a * K + b] = d[b * K + a];
-        }
-        __syncthreads();
+        __syncthreads();                           // phase B reads done before the next level's writes
     }
     if (active) {
         ok = chol_inplace<T, K>(d) && ok;
