@@ -124,7 +124,7 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> 
     static_assert(TH >= NP, "the lane grid must cover one lane per link");
     __shared__ T xbuf[TH > 64 ? 10 * TH : 1];   // cross-wavefront scan exchange
     __shared__ T sf[NP * 13];                   // s (6), F (6), tau_delta per link
-    __shared__ T col[2][NP + 1];                // published column (row) and its right-hand side entry
+    __shared__ T col[2][NP + 2];                // column j (zero at rows <= j), b_j, m_jj
     const int li = threadIdx.x;
     ChainInfo ci{0, 0, 0, 0};
     if ((int)blockIdx.x < cm.batch) ci = chain_info(m, cm, blockIdx.x);
@@ -177,12 +177,19 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> 
         const int j = G * jb + jr;
         T* cj = col[jr & 1];
         if (c == jr) {
+            // entries at rows <= j go out as zero, so readers need no masks
 #pragma unroll
-            for (int a = jb; a < 8; ++a) cj[r + G * a] = mb[a * (a + 1) / 2 + jb];
-            if (r == jr) cj[NP] = y[jb];
+            for (int a = jb; a < 8; ++a) {
+                const T v = mb[a * (a + 1) / 2 + jb];
+                cj[r + G * a] = (a > jb || r > jr) ? v : T(0);
+            }
+            if (r == jr) {
+                cj[NP] = y[jb];
+                cj[NP + 1] = mb[jb * (jb + 1) / 2 + jb];
+            }
         }
         __syncthreads();
-        const T piv = cj[j];
+        const T piv = cj[NP + 1];
         const T rp = rcp_refined(piv);
         const T yj = cj[NP];
         if (r == jr) {
@@ -192,10 +199,8 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> 
         T fa[8], pv[8];
 #pragma unroll
         for (int a = jb; a < 8; ++a) {
-            const T v = cj[r + G * a] * rp;
-            fa[a] = (r + G * a > j) ? v : T(0);             // L_ij, rows below the pivot
-            const T w = cj[c + G * a];
-            pv[a] = (c + G * a > j) ? w : T(0);             // m_kj, columns right of the pivot
+            fa[a] = cj[r + G * a] * rp;                     // L_ij, zero at rows <= j
+            pv[a] = cj[c + G * a];                          // m_kj, zero at columns <= j
         }
 #pragma unroll
         for (int a = jb; a < 8; ++a) {
@@ -211,9 +216,10 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> 
     // sum over the block's rows, one term per lane of a row group (G
     // consecutive lanes), summed by dpp::group_sum. The buffer reuses LDS that
     // is free after the M build.
-    T* wbuf = TH > 64 ? xbuf : sf;                          // G rows of NP entries, then z (G), 1/d (G)
-    static_assert((TH > 64 ? 10 * TH : NP * 13) >= G * NP + 2 * G, "block rows fit the reused buffer");
-    T* zb = wbuf + G * NP;
+    constexpr int WS = NP + 1;                              // row stride: one extra entry spreads the rows over the LDS banks
+    T* wbuf = TH > 64 ? xbuf : sf;                          // G rows of WS entries, then z (G), 1/d (G)
+    static_assert((TH > 64 ? 10 * TH : NP * 13) >= G * WS + 2 * G, "block rows fit the reused buffer");
+    T* zb = wbuf + G * WS;
     T* rb = zb + G;
 #pragma unroll
     for (int a = 0; a < 8; ++a) y[a] *= rd[a];
@@ -221,7 +227,7 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> 
     for (int jb = 7; jb >= 0; --jb) {
         __syncthreads();                                    // earlier reads of the buffer are done
 #pragma unroll
-        for (int bb = 0; bb <= jb; ++bb) wbuf[r * NP + c + G * bb] = mb[jb * (jb + 1) / 2 + bb];
+        for (int bb = 0; bb <= jb; ++bb) wbuf[r * WS + c + G * bb] = mb[jb * (jb + 1) / 2 + bb];
         if (c == 0) {
             zb[r] = y[jb];
             rb[r] = rd[jb];
@@ -231,14 +237,14 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> 
         T xc = T(0);
 #pragma unroll
         for (int t = G - 1; t >= 0; --t) {
-            const T part = c > t ? wbuf[c * NP + G * jb + t] * xc : T(0);
+            const T part = c > t ? wbuf[c * WS + G * jb + t] * xc : T(0);
             const T xt = zb[t] - dpp::group_sum<G>(part) * rb[t];
             xc = c == t ? xt : xc;
             if (r == t) y[jb] = xt;
         }
         // rows k above the block: z_k -= (1 / d_k) sum_t m_tk x_t
 #pragma unroll
-        for (int a = 0; a < jb; ++a) y[a] -= dpp::group_sum<G>(wbuf[c * NP + r + G * a] * xc) * rd[a];
+        for (int a = 0; a < jb; ++a) y[a] -= dpp::group_sum<G>(wbuf[c * WS + r + G * a] * xc) * rd[a];
     }
     if (c == 0) {
 #pragma unroll
