@@ -13,6 +13,7 @@ TFLOP/s) and the CPU oracle timed on the host cores.
 from __future__ import annotations
 
 import argparse
+import collections
 import json
 import math
 import os
@@ -204,7 +205,7 @@ def cpu_baseline(rb, q, qd, tau, chains: int, min_s: float = 10.0, max_s: float 
                       f"plain CRBA + RNEA + Cholesky, all host threads, {dt:.1f} s wall"}
 
 
-def serving_leg(dtype: str, requests: int = 3000):
+def serving_leg(dtype: str, requests: int = 10000):
     """Continuous batching over 32 resident robots (n ~ U{7..200}), requests of
     1..4096 chains (log-uniform), Poisson arrivals at 50% and 80% of the
     measured saturation rate; latency is arrival to result in host memory."""
@@ -215,7 +216,7 @@ def serving_leg(dtype: str, requests: int = 3000):
     dev = torch.device("cuda:0")
     lengths = synth.ragged_lengths(32, 7, 200, cfg=4)
     model = fd.Model(synth.make_robots(lengths, cfg=4), dtype, device=dev)
-    ex = serve.GpuExecutor(model, lengths, algo="abia", streams=4)
+    ex = serve.GpuExecutor(model, lengths, algo="auto", streams=4)
     budget = 8 << 30
 
     def run(qps, count, seed):
@@ -225,11 +226,13 @@ def serving_leg(dtype: str, requests: int = 3000):
         return sched.run(reqs), reqs
 
     run(float("inf"), 64, 1)                     # warm up allocator and kernels
-    sat, reqs = run(float("inf"), requests // 2, 2)
+    sat, reqs = run(float("inf"), requests, 2)
     mean_chains = float(np.mean([r.chains for r in reqs]))
+    algos = collections.Counter(r.algo for r in reqs)
     out = {"robots": 32, "n_links": "U{7..200}", "chains_per_request": "log-uniform 1..4096",
-           "budget_bytes": budget, "streams": 4, "saturation_solves_per_s": sat.solves_per_s,
-           "saturation_launches": sat.launches}
+           "algo": "per request, tuned table", "requests_per_load": requests, "budget_bytes": budget,
+           "streams": 4, "saturation_solves_per_s": sat.solves_per_s, "saturation_launches": sat.launches,
+           "saturation_algo_mix": dict(algos)}
     for load in (0.5, 0.8):
         qps = load * sat.solves_per_s / mean_chains
         st, _ = run(qps, requests, 3 + int(load * 10))

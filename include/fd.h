@@ -81,6 +81,11 @@ typedef struct {
                                   (every chain uses robot 0 when the model has one robot) */
     const int64_t* offsets;    /* [batch + 1] first entry of chain b, or NULL when all chains of
                                   the batch have the same length (start_b = b * n) */
+    int32_t max_links;         /* 0, or an upper bound on the links of every chain of the batch:
+                                  lane groups and workspaces are sized to the smaller of it and
+                                  the longest robot the batch can name (with robot ids, the
+                                  model's longest). A chain longer than the bound is not solved:
+                                  its outputs are set to NaN. Must be 0..256. */
 } fd_batch_t;
 
 /* Upload a robot set in the given precision (FD_F32 rounds every parameter).

@@ -37,6 +37,7 @@ class Batch(ctypes.Structure):
         ("batch", ctypes.c_int32),
         ("robot_id", ctypes.c_void_p),
         ("offsets", ctypes.c_void_p),
+        ("max_links", ctypes.c_int32),
     ]
 
 

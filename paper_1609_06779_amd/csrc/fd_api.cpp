@@ -83,11 +83,12 @@ struct BatchPlan {
 };
 
 fd_status_t plan_batch(const fd_model* m, const fd_batch_t* b, BatchPlan* p) {
-    if (!m || !b || b->batch < 0) return FD_ERR_INVALID_ARG;
+    if (!m || !b || b->batch < 0 || b->max_links < 0 || b->max_links > kMaxLinks) return FD_ERR_INVALID_ARG;
     p->cm.robot_id = b->robot_id;
     p->cm.offsets = b->offsets;
     p->cm.batch = b->batch;
     p->cm.n_uniform = 0;
+    p->cm.n_cap = 0;
     p->nmax = 0;
     if (b->batch == 0) return FD_OK;
     bool uni;
@@ -111,6 +112,8 @@ fd_status_t plan_batch(const fd_model* m, const fd_batch_t* b, BatchPlan* p) {
         if (!uni) return FD_ERR_INVALID_ARG;
         p->cm.n_uniform = n0;
     }
+    if (b->max_links > 0) p->nmax = std::min(p->nmax, b->max_links);
+    p->cm.n_cap = p->nmax;
     return FD_OK;
 }
 

@@ -61,6 +61,10 @@ template <typename T>
 __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInfo& ci, const T* __restrict__ q,
                                            const T* __restrict__ qd, const T* __restrict__ tau,
                                            T* __restrict__ qdd, T* __restrict__ wsb) {
+    if (ci.unsolved) {                                 // longer than the workspace is sized for
+        fill_unsolved(qdd, ci.state0, ci.unsolved, 0, 1);
+        return;
+    }
     const int n = ci.n;
     auto wsat = [&](int i, int f) -> T& { return wsb[((size_t)i * ABIA_WS_FIELDS + f) * 64]; };
 

@@ -80,6 +80,12 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
     const int b = blockIdx.x * 64 + lane;
     if (b >= cm.batch) return;
     const ChainInfo ci = chain_info(m, cm, b);
+    if (ci.unsolved) {                                 // longer than the workspace is sized for
+        fill_unsolved(gq, ci.state0, ci.unsolved, 0, 1);
+        fill_unsolved(gqd, ci.state0, ci.unsolved, 0, 1);
+        fill_unsolved(gtau, ci.state0, ci.unsolved, 0, 1);
+        return;
+    }
     const int n = ci.n;
     const int sl = ci.slot;
     T* wsb = ws + (size_t)blockIdx.x * nmax * VJP_FIELDS * 64 + lane;

@@ -32,7 +32,7 @@ __global__ __launch_bounds__(Geo<NP>::threads, NP <= 64 ? 2 : 1) void k_cfa(Mode
     T* oslot = lds_all + XB;
     const int grp = threadIdx.x / NP, li = threadIdx.x % NP;
     const int b = blockIdx.x * Geo<NP>::chains + grp;
-    ChainInfo ci{0, 0, 0, 0};
+    ChainInfo ci{0, 0, 0, 0, 0};
     if (b < cm.batch) ci = chain_info(m, cm, b);
     const int n = ci.n;
     const bool active = li < n;
@@ -145,6 +145,7 @@ __global__ __launch_bounds__(Geo<NP>::threads, NP <= 64 ? 2 : 1) void k_cfa(Mode
     for (int c = 0; c < 6; ++c) acc += prow[c] * f[c] + (has_next ? nrow[c] * fn[c] : T(0));
     if (has_prev) acc += cprev;
     if (active) qdd[st] = acc;
+    if (ci.unsolved) fill_unsolved(qdd, ci.state0, ci.unsolved, li, NP);
     if (active && !ok && status) atomicOr(status, 1);
 }
 

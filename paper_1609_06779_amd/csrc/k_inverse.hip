@@ -15,7 +15,7 @@ __global__ __launch_bounds__(Geo<NP>::threads) void k_inverse(ModelView<T> m, Ch
     __shared__ T xbuf[NP > 64 ? 9 * NP : 1];
     const int grp = threadIdx.x / NP, li = threadIdx.x % NP;
     const int b = blockIdx.x * Geo<NP>::chains + grp;
-    ChainInfo ci{0, 0, 0, 0};
+    ChainInfo ci{0, 0, 0, 0, 0};
     if (b < cm.batch) ci = chain_info(m, cm, b);
     const bool active = li < ci.n;
     const int64_t st = ci.state0 + li;
@@ -23,6 +23,7 @@ __global__ __launch_bounds__(Geo<NP>::threads) void k_inverse(ModelView<T> m, Ch
     LinkLane<T> k;
     T t = rnea_lane<T, NP>(m, ci.link0 + li, active, qi, qdi, qai, gravity != 0, li, xbuf, k);
     if (active) tau[st] = t;
+    if (ci.unsolved) fill_unsolved(tau, ci.state0, ci.unsolved, li, NP);
 }
 
 template <typename T, int NP>
@@ -32,7 +33,7 @@ __global__ __launch_bounds__(Geo<NP>::threads) void k_mass(ModelView<T> m, Chain
     __shared__ T sf[Geo<NP>::chains * NP * 12];
     const int grp = threadIdx.x / NP, li = threadIdx.x % NP;
     const int b = blockIdx.x * Geo<NP>::chains + grp;
-    ChainInfo ci{0, 0, 0, 0};
+    ChainInfo ci{0, 0, 0, 0, 0};
     if (b < cm.batch) ci = chain_info(m, cm, b);
     const bool active = li < ci.n;
     T qi = active ? q[ci.state0 + li] : T(0);
@@ -63,6 +64,7 @@ __global__ __launch_bounds__(Geo<NP>::threads) void k_mass(ModelView<T> m, Chain
             row[kk] = acc;
         }
     }
+    if (ci.unsolved) fill_unsolved(mout, (int64_t)b * ci.unsolved * ci.unsolved, (int64_t)ci.unsolved * ci.unsolved, li, NP);
 }
 
 template <typename T>

@@ -41,7 +41,7 @@ __global__ __launch_bounds__(64) void k_jsiia_gj(ModelView<T> m, ChainMap cm, co
     __shared__ T col[2][CH][2 * NP];   // double-buffered pivot column and right-hand sides
     const int grp = threadIdx.x / NP, li = threadIdx.x % NP;
     const int b = blockIdx.x * CH + grp;
-    ChainInfo ci{0, 0, 0, 0};
+    ChainInfo ci{0, 0, 0, 0, 0};
     if (b < cm.batch) ci = chain_info(m, cm, b);
     const int n = ci.n;
     const bool active = li < n;
@@ -95,6 +95,7 @@ __global__ __launch_bounds__(64) void k_jsiia_gj(ModelView<T> m, ChainMap cm, co
         for (int kk = j + 1; kk < NP; ++kk) row[kk] -= fj * cj[kk];
     }
     if (active) qdd[st] = y / diag;
+    if (ci.unsolved) fill_unsolved(qdd, ci.state0, ci.unsolved, li, NP);
     if (active && !ok && status) atomicOr(status, 1);
 }
 
@@ -126,7 +127,7 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> 
     __shared__ T sf[NP * 13];                   // s (6), F (6), tau_delta per link
     __shared__ T col[2][NP + 2];                // column j (zero at rows <= j), b_j, m_jj
     const int li = threadIdx.x;
-    ChainInfo ci{0, 0, 0, 0};
+    ChainInfo ci{0, 0, 0, 0, 0};
     if ((int)blockIdx.x < cm.batch) ci = chain_info(m, cm, blockIdx.x);
     const int n = ci.n;
     const bool active = li < n;
@@ -173,8 +174,7 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> 
 #pragma unroll
     for (int jb = 0; jb < 8; ++jb)
 #pragma unroll 1
-    for (int jr = 0; jr < G; ++jr) {
-        const int j = G * jb + jr;
+    for (int jr = 0; jr < G; ++jr) {                       // step j = G jb + jr
         T* cj = col[jr & 1];
         if (c == jr) {
             // entries at rows <= j go out as zero, so readers need no masks
@@ -253,6 +253,7 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> 
             if (i < n) qdd[ci.state0 + i] = y[a];
         }
     }
+    if (ci.unsolved) fill_unsolved(qdd, ci.state0, ci.unsolved, li, TH);
     if (c == 0 && !ok && status) atomicOr(status, 1);
 }
 

@@ -155,17 +155,20 @@ struct ChainMap {
     const int64_t* offsets;    // device [batch+1] or null: chain b starts at b * n_uniform
     int32_t batch;
     int32_t n_uniform;
+    int32_t n_cap;             // longest chain the launch is sized for; longer ones are not solved
 };
 
 // link0: the robot's first link (structure-of-arrays fields); state0: the
 // chain's first entry in q, qd, tau; n: its links (0: skipped); slot: the
-// robot's column in the interleaved copy.
-struct ChainInfo { int64_t link0; int64_t state0; int n; int slot; };
+// robot's column in the interleaved copy; unsolved: the length of a chain
+// longer than the launch is sized for (n is then 0), else 0.
+struct ChainInfo { int64_t link0; int64_t state0; int n; int slot; int unsolved; };
 
 template <typename T>
 __device__ __forceinline__ ChainInfo chain_info(const ModelView<T>& m, const ChainMap& cm, int b) {
     int r = cm.robot_id ? cm.robot_id[b] : (m.num_robots == 1 ? 0 : b);
     ChainInfo ci;
+    ci.unsolved = 0;
     if (r < 0 || r >= m.num_robots) {   // out-of-range robot id: the chain is skipped
         ci.link0 = 0;
         ci.n = 0;
@@ -177,7 +180,18 @@ __device__ __forceinline__ ChainInfo chain_info(const ModelView<T>& m, const Cha
     ci.link0 = m.link_start[r];
     ci.n = m.n_links[r];
     ci.state0 = cm.offsets ? cm.offsets[b] : (int64_t)b * cm.n_uniform;
+    if (ci.n > cm.n_cap) {
+        ci.unsolved = ci.n;
+        ci.n = 0;
+    }
     return ci;
+}
+
+// NaN over the `count` outputs of an unsolved chain starting at out + first,
+// written by `lanes` lanes (this one is `lane`).
+template <typename T>
+__device__ __forceinline__ void fill_unsolved(T* out, int64_t first, int64_t count, int lane, int lanes) {
+    for (int64_t k = lane; k < count; k += lanes) out[first + k] = T(__builtin_nan(""));
 }
 
 // ---------------- lane-group exchange ----------------

@@ -103,27 +103,30 @@ class Model:
         return int(_lib.load().fd_max_links(self._h, _lib.ALGOS[algo]))
 
     # ---- batches ----
-    def _batch(self, batch: int, robot_id=None, offsets=None) -> _lib.Batch:
+    def _batch(self, batch: int, robot_id=None, offsets=None, max_links: int = 0) -> _lib.Batch:
         b = _lib.Batch()
         b.batch = int(batch)
+        b.max_links = int(max_links)
         b.robot_id = _ptr(_dev_tensor(robot_id, torch.int32, self.device, "robot_id")).value if robot_id is not None else None
         b.offsets = _ptr(_dev_tensor(offsets, torch.int64, self.device, "offsets")).value if offsets is not None else None
         return b
 
-    def workspace_size(self, batch: int, algo: str = "auto", robot_id=None, offsets=None) -> int:
+    def workspace_size(self, batch: int, algo: str = "auto", robot_id=None, offsets=None, max_links: int = 0) -> int:
         n = ctypes.c_size_t()
-        b = self._batch(batch, robot_id, offsets)
+        b = self._batch(batch, robot_id, offsets, max_links)
         _lib.check(_lib.load().fd_workspace_size(self._h, ctypes.byref(b), _lib.ALGOS[algo], ctypes.byref(n)),
                    "fd_workspace_size")
         return int(n.value)
 
-    def workspace(self, batch: int, algo: str = "auto", robot_id=None, offsets=None):
-        nbytes = self.workspace_size(batch, algo, robot_id, offsets)
+    def workspace(self, batch: int, algo: str = "auto", robot_id=None, offsets=None, max_links: int = 0):
+        nbytes = self.workspace_size(batch, algo, robot_id, offsets, max_links)
         return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=self.device)
 
     def forward(self, q, qd, tau, batch: int, algo: str = "auto", robot_id=None, offsets=None, out=None,
-                workspace=None, stream=None):
-        """qdd = M(q)^-1 (tau - tau_bias(q, qd)) for every chain of the batch."""
+                workspace=None, stream=None, max_links: int = 0):
+        """qdd = M(q)^-1 (tau - tau_bias(q, qd)) for every chain of the batch.
+        max_links > 0 bounds the links of every chain (lane groups are sized to it;
+        a longer chain is not solved and gets NaN)."""
         dt = self.torch_dtype
         q = _dev_tensor(q, dt, self.device, "q")
         qd = _dev_tensor(qd, dt, self.device, "qd")
@@ -131,9 +134,9 @@ class Model:
         if out is None:
             out = torch.empty_like(q)
         _dev_tensor(out, dt, self.device, "out")
-        b = self._batch(batch, robot_id, offsets)
+        b = self._batch(batch, robot_id, offsets, max_links)
         if workspace is None:
-            workspace = self.workspace(batch, algo, robot_id, offsets)
+            workspace = self.workspace(batch, algo, robot_id, offsets, max_links)
         _lib.check(_lib.load().fd_forward(self._h, ctypes.byref(b), _ptr(q), _ptr(qd), _ptr(tau), _ptr(out),
                                           _lib.ALGOS[algo], _ptr(workspace), workspace.numel(), _stream(stream)),
                    "fd_forward")

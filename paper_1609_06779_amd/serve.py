@@ -10,7 +10,9 @@ at every turn,
      of mixed robots (robot ids and chain offsets) for one ``fd_forward`` call;
   3. issues that launch on the next stream of a small pool, so the work of
      requests admitted at different times overlaps on the device.
-A request larger than the whole budget is rejected. With the articulated-body
+Within a round, requests are grouped by algorithm (the tuned choice for
+their robot length and chain count, by default), one launch per group. A
+request larger than the whole budget is rejected. With the articulated-body
 algorithm every chain stays on its own lane, so a chain's result does not
 depend on what else shares its launch (the tests check it bit for bit).
 
@@ -39,6 +41,7 @@ class Request:
     qd: object = None
     tau: object = None
     out: object = None           # host tensor receiving qdd
+    algo: str = ""               # algorithm that served it (set at launch)
     admitted: float = math.nan
     done: float = math.nan
     rejected: bool = False
@@ -158,35 +161,68 @@ class Scheduler:
 
 
 class GpuExecutor(Executor):
-    """Launches ``fd_forward`` over a packed ragged batch on a pool of streams.
+    """Launches ``fd_forward`` over packed ragged batches on a pool of streams.
 
-    Each launch copies its requests' pinned host inputs into fresh device
-    buffers, runs one forward-dynamics call with robot ids and chain offsets,
-    copies qdd back into the requests' pinned outputs and records an event.
+    Each launch round copies its requests' pinned host inputs into fresh device
+    buffers and runs one forward-dynamics call per algorithm among its
+    requests (robot ids and chain offsets), copies qdd back into the requests'
+    pinned outputs and records one event. ``algo`` is an algorithm name,
+    "auto" (the tuned table's choice for the request's robot length and chain
+    count) or a function of the request.
     """
 
-    def __init__(self, model, n_links: np.ndarray, algo: str = "abia", streams: int = 4):
+    def __init__(self, model, n_links: np.ndarray, algo="auto", streams: int = 4):
         import torch
+
+        from . import tune
 
         self.torch = torch
         self.model = model
         self.n_links = np.asarray(n_links, dtype=np.int64)
-        self.algo = algo
+        if algo == "auto":
+            self.pick = lambda r: tune.best_algo(model.dtype, r.n, r.chains)
+        elif callable(algo):
+            self.pick = algo
+        else:
+            self.pick = lambda r, a=algo: a
         self.streams = [torch.cuda.Stream(device=model.device) for _ in range(streams)]   # default priority
         self.turn = 0
         self.esz = 8 if model.dtype == "f64" else 4
-        self.nmax = int(self.n_links.max())
+
+    def _groups(self, reqs):
+        groups = collections.OrderedDict()
+        for r in reqs:
+            algo = self.pick(r)
+            if r.n > self.model.max_links(algo):
+                algo = "abia"
+            groups.setdefault(algo, []).append(r)
+        return groups
 
     def bytes_needed(self, reqs):
-        chains = sum(r.chains for r in reqs)
-        links = sum(r.chains * r.n for r in reqs)
-        ws = ((chains + 63) // 64) * self.nmax * 7 * 64 * self.esz if self.algo == "abia" else 0
-        return 4 * links * self.esz + 12 * chains + 8 + ws
+        total = 0
+        for algo, grp in self._groups(reqs).items():
+            chains = sum(r.chains for r in grp)
+            links = sum(r.chains * r.n for r in grp)
+            nmax = max(r.n for r in grp)
+            ws = ((chains + 63) // 64) * nmax * 7 * 64 * self.esz if algo == "abia" else 0
+            total += 4 * links * self.esz + 12 * chains + 8 + ws
+        return total
 
     def launch(self, reqs):
         torch = self.torch
         stream = self.streams[self.turn % len(self.streams)]
         self.turn += 1
+        keep = []
+        with torch.cuda.stream(stream):
+            for algo, grp in self._groups(reqs).items():
+                keep.append(self._launch_group(algo, grp, stream))
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        # keep the device buffers and pinned staging alive until the event fires
+        return (ev, keep)
+
+    def _launch_group(self, algo, reqs, stream):
+        torch = self.torch
         dev = self.model.device
         dt = self.model.torch_dtype
         chains = sum(r.chains for r in reqs)
@@ -201,32 +237,30 @@ class GpuExecutor(Executor):
             c += r.chains
             pos += r.chains * r.n
         off_np[chains] = pos
-        with torch.cuda.stream(stream):
-            q = torch.empty(links, dtype=dt, device=dev)
-            qd = torch.empty_like(q)
-            tau = torch.empty_like(q)
-            out = torch.empty_like(q)
-            rid = rid_h.to(dev, non_blocking=True)
-            off = off_h.to(dev, non_blocking=True)
-            pos = 0
-            for r in reqs:
-                k = r.chains * r.n
-                q[pos:pos + k].copy_(r.q, non_blocking=True)
-                qd[pos:pos + k].copy_(r.qd, non_blocking=True)
-                tau[pos:pos + k].copy_(r.tau, non_blocking=True)
-                pos += k
-            ws = self.model.workspace(chains, self.algo, robot_id=rid, offsets=off)
-            self.model.forward(q, qd, tau, batch=chains, algo=self.algo, robot_id=rid, offsets=off, out=out,
-                               workspace=ws, stream=stream)
-            pos = 0
-            for r in reqs:
-                k = r.chains * r.n
-                r.out.copy_(out[pos:pos + k], non_blocking=True)
-                pos += k
-            ev = torch.cuda.Event()
-            ev.record(stream)
-        # keep the device buffers and pinned staging alive until the event fires
-        return (ev, (q, qd, tau, out, rid, off, ws, rid_h, off_h))
+        q = torch.empty(links, dtype=dt, device=dev)
+        qd = torch.empty_like(q)
+        tau = torch.empty_like(q)
+        out = torch.empty_like(q)
+        rid = rid_h.to(dev, non_blocking=True)
+        off = off_h.to(dev, non_blocking=True)
+        pos = 0
+        for r in reqs:
+            k = r.chains * r.n
+            q[pos:pos + k].copy_(r.q, non_blocking=True)
+            qd[pos:pos + k].copy_(r.qd, non_blocking=True)
+            tau[pos:pos + k].copy_(r.tau, non_blocking=True)
+            pos += k
+        nmax = max(r.n for r in reqs)                  # lane groups sized to this group's longest robot
+        ws = self.model.workspace(chains, algo, robot_id=rid, offsets=off, max_links=nmax)
+        self.model.forward(q, qd, tau, batch=chains, algo=algo, robot_id=rid, offsets=off, out=out,
+                           workspace=ws, stream=stream, max_links=nmax)
+        pos = 0
+        for r in reqs:
+            k = r.chains * r.n
+            r.out.copy_(out[pos:pos + k], non_blocking=True)
+            r.algo = algo
+            pos += k
+        return (q, qd, tau, out, rid, off, ws, rid_h, off_h)
 
     def poll(self, handle):
         return handle[0].query()

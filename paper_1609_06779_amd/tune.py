@@ -10,6 +10,7 @@ of one call against the number of links and against the number of robots
 (Sec. V).
 
     python -m paper_1609_06779_amd.tune --out paper_1609_06779_amd/tuning_gfx950.json
+    python -m paper_1609_06779_amd.tune --experiments --dtypes f64 --out experiments.json
 """
 from __future__ import annotations
 
@@ -117,6 +118,33 @@ def table_array(entry):
     return arr
 
 
+_TABLES = {}
+
+
+def best_algo(dtype: str, n: int, batch: int, path=DEFAULT_TABLE) -> str:
+    """The algorithm the tuned table picks for ``batch`` chains of ``n`` links (the
+    library's AUTO rule on the same table); "abia" when there is no table."""
+    key = (path, dtype)
+    if key not in _TABLES:
+        entry = json.load(open(path)).get("best", {}).get(dtype) if os.path.exists(path) else None
+        _TABLES[key] = None if entry is None else table_array(entry)
+    arr = _TABLES[key]
+    if arr is None:
+        return "abia"
+    return ALGOS[int(arr[min(256, max(1, n)), batch_bucket(batch)])]
+
+
+def batch_bucket(batch: int) -> int:
+    """Column of the choice table for a batch: the nearest power of two 2^k, k <= 20
+    (the same rule as the library's AUTO lookup)."""
+    k = 0
+    while k < 20 and (1 << (k + 1)) <= batch:
+        k += 1
+    if k < 20 and batch - (1 << k) > (1 << (k + 1)) - batch:
+        k += 1
+    return k
+
+
 def ragged_grid(dtype: str, path=DEFAULT_TABLE) -> int:
     """Persistent grid size for ragged batches chosen by ``tune_ragged`` (0 = resident capacity)."""
     if not os.path.exists(path):
@@ -160,6 +188,78 @@ def tune_ragged(dtype: str = "f64", batch: int = 100000, lo: int = 4, hi: int = 
     return res
 
 
+EXP1_N = (2, 4, 8, 16, 32, 64, 96, 128, 160, 200, 256)
+EXP2_N = (10, 200)
+EXP2_GROUPS = (1, 10, 100, 1000, 10000, 100000)
+
+
+def _time_calls(model, tq, tqd, ttau, n, batch, algo, calls):
+    """Mean ms of one fd_forward call over ``calls`` back-to-back calls, each on its
+    own slice of pre-drawn random inputs (launch overhead included)."""
+    import torch
+
+    out = torch.empty(batch * n, dtype=tq.dtype, device=tq.device)
+    ws = model.workspace(batch, algo)
+    stream = torch.cuda.current_stream()
+    per = batch * n
+    slices = max(1, tq.numel() // per)
+
+    def call(k):
+        o = (k % slices) * per
+        model.forward(tq[o:o + per], tqd[o:o + per], ttau[o:o + per], batch=batch, algo=algo, out=out,
+                      workspace=ws, stream=stream)
+
+    for k in range(3):
+        call(k)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for k in range(calls):
+        call(k)
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / calls
+
+
+def experiments(dtype="f64", calls=1000, log=None):
+    """The paper's two experiments (Sec. V) on this GPU: the time of one call for one
+    robot against its number of links, and the time of one call over a group of
+    independent robots of 10 and of 200 links against the group size. Each robot
+    has its own random parameters; each call gets its own random joint inputs."""
+    import torch
+
+    from . import fd, synth
+
+    dev = torch.device("cuda:0")
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    rows = []
+
+    def run(n, batch, exp, reps):
+        lengths = synth.uniform_lengths(batch, n)
+        rb = synth.make_robots(lengths, cfg=6)
+        slices = max(1, min(reps, (1 << 22) // (batch * n)))      # distinct inputs, at most 4M entries
+        q, qd, tau = synth.make_state(synth.uniform_lengths(batch * slices, n), cfg=6)
+        model = fd.Model(rb, dtype, device=dev)
+        tq, tqd, ttau = (torch.from_numpy(x).to(dev, tdt) for x in (q, qd, tau))
+        for algo in ALGOS:
+            row = {"exp": exp, "n": n, "groups": batch, "algo": algo, "dtype": dtype}
+            if n > model.max_links(algo):
+                row["ms"] = None                                    # longer than this algorithm's kernels take
+            else:
+                row["ms"] = _time_calls(model, tq, tqd, ttau, n, batch, algo, reps)
+            rows.append(row)
+            if log:
+                print(json.dumps(row), file=log, flush=True)
+        model.close()
+
+    for n in EXP1_N:
+        run(n, 1, 1, calls)
+    for n in EXP2_N:
+        for g in EXP2_GROUPS:
+            run(n, g, 2, calls if g * n <= 100000 else max(10, calls * 100000 // (g * n)))
+    return rows
+
+
 def load_table(path=DEFAULT_TABLE):
     """Hand the tuned table to the library (per precision). Returns False if there is none."""
     if not os.path.exists(path):
@@ -184,8 +284,18 @@ def main():
     ap.add_argument("--ns", default=",".join(map(str, N_GRID)))
     ap.add_argument("--batches", default=",".join(map(str, BATCH_GRID)))
     ap.add_argument("--ragged-only", action="store_true", help="keep the existing sweep, redo the ragged grid")
+    ap.add_argument("--experiments", action="store_true",
+                    help="run the paper's two experiment shapes instead and write them to --out")
     args = ap.parse_args()
     import torch
+
+    if args.experiments:
+        rows = []
+        for dtype in args.dtypes.split(","):
+            rows += experiments(dtype, log=sys.stderr)
+        with open(args.out, "w") as f:
+            json.dump({"arch": torch.cuda.get_device_properties(0).gcnArchName, "rows": rows}, f, indent=1)
+        return
 
     if args.ragged_only and os.path.exists(args.out):
         data = json.load(open(args.out))

@@ -324,3 +324,46 @@ def test_btd_solve6_reports_non_spd(fdm, dev):
     _, status = fdm.btd_solve6(torch.from_numpy(d).to(dev), torch.from_numpy(u).to(dev),
                                torch.from_numpy(r).to(dev), torch.from_numpy(np.array([0, 4])).to(dev), max_len=4)
     assert int(status.item()) & 1
+
+
+# ---------------- the batch's length bound (max_links) ----------------
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_length_bound_sizes_the_launch(fdm, dev, algo):
+    """Robot ids into a model whose longest robot has 200 links: with max_links set to
+    the batch's longest chain (30) every algorithm runs at that size and matches the
+    oracle; ABIA is bit for bit the unbounded launch; a bound of 12 leaves the longer
+    chains unsolved (NaN) and the others exact."""
+    from paper_1609_06779_amd import _lib
+
+    lengths = np.array([200, 30, 12, 7, 30, 25], np.int32)
+    rb, _, _, _ = _prep(lengths, "f64", cfg=7)
+    model = fdm.Model(rb, "f64", device=dev)
+    ids = np.array([1, 2, 3, 4, 5, 1, 3, 2, 4, 5] * 3, np.int32)
+    sub = rb.take(ids)
+    q, qd, tau = synth.make_state(sub.n_links, cfg=7)
+    off = sub.offsets
+    tq, tqd, ttau = _t(q, "f64", dev), _t(qd, "f64", dev), _t(tau, "f64", dev)
+    rid, toff = torch.from_numpy(ids).to(dev), torch.from_numpy(off).to(dev)
+    ref = oracle.fd(sub, q, qd, tau)
+    got = model.forward(tq, tqd, ttau, batch=len(ids), algo=algo, robot_id=rid, offsets=toff, max_links=30)
+    _check(got.cpu().numpy(), ref, off, "f64", sub, q, f"{algo} bounded", algo)
+    if algo == "abia":
+        free = model.forward(tq, tqd, ttau, batch=len(ids), algo=algo, robot_id=rid, offsets=toff)
+        assert torch.equal(got, free)
+    short = model.forward(tq, tqd, ttau, batch=len(ids), algo=algo, robot_id=rid, offsets=toff,
+                          max_links=12).cpu().numpy()
+    for b, n in enumerate(sub.n_links):
+        sl = slice(off[b], off[b + 1])
+        if n > 12:
+            assert np.all(np.isnan(short[sl])), b
+        else:
+            assert np.all(np.isfinite(short[sl])), b
+    ok = sub.n_links <= 12
+    keep = np.concatenate([np.arange(off[b], off[b + 1]) for b in np.nonzero(ok)[0]])
+    sub_ok = sub.take(np.nonzero(ok)[0])
+    _check(short[keep], ref[keep], sub_ok.offsets, "f64", sub_ok, q[keep], f"{algo} short bound", algo)
+    for bad in (-1, 257):
+        with pytest.raises(_lib.FdError) as ei:
+            model.forward(tq, tqd, ttau, batch=len(ids), algo=algo, robot_id=rid, offsets=toff, max_links=bad)
+        assert ei.value.status == _lib.FD_ERR_INVALID_ARG

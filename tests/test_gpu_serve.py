@@ -1,11 +1,14 @@
 """Serving on the GPU: every request's result is the same alone and inside the
 continuous-batching mix (bit for bit with one lane per chain), and matches
-the oracle."""
+the oracle, also when the requests of one round use different algorithms."""
 import numpy as np
 import pytest
 
 import oracle
+from oracle import dense
 from paper_1609_06779_amd import synth
+
+U64 = 2.0 ** -53
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -59,3 +62,43 @@ def test_budget_rejects_a_request_larger_than_the_device_budget(dev):
     for r in reqs:
         if not r.rejected:
             assert torch.isfinite(r.out).all()
+
+
+def _bar(algo, rb, q, off):
+    """Per-chain forward-error bar: 1e-10, or the factorisation's error model
+    (ABIA, JSIIA: 16 cond(M) u; CFA: 64 ||C|| ||M|| u, Sec. III)."""
+    ms = oracle.crba(rb, q, offsets=off)
+    if algo == "cfa":
+        kap = np.array([np.linalg.norm(dense.cfa_c_matrix(dense.Chain(rb, off[b], int(off[b + 1] - off[b])),
+                                                          q[off[b]:off[b + 1]]), 2) * np.linalg.norm(m, 2)
+                        for b, m in enumerate(ms)])
+        return np.maximum(1e-10, 64 * kap * U64)
+    return np.maximum(1e-10, 16 * np.array([np.linalg.cond(m) for m in ms]) * U64)
+
+
+@pytest.mark.parametrize("mode", ["mixed", "auto"])
+def test_rounds_with_several_algorithms_match_the_oracle(dev, mode):
+    """Requests served by all three algorithms in the same rounds (cycled by request
+    id, or the tuned per-request choice) match the oracle on sampled chains."""
+    from paper_1609_06779_amd import fd, serve
+
+    lengths = synth.ragged_lengths(32, 7, 200, cfg=4)
+    robots = synth.make_robots(lengths, cfg=4)
+    model = fd.Model(robots, "f64", device=dev)
+    reqs = serve.make_requests(lengths, count=48, qps=20000.0, seed=11, max_chains=256)
+    algo = (lambda r: ("abia", "jsiia", "cfa")[r.rid % 3]) if mode == "mixed" else "auto"
+    ex = serve.GpuExecutor(model, lengths, algo=algo, streams=4)
+    stats = serve.Scheduler(ex, budget_bytes=64 << 20, max_inflight=4, idle=serve.spin_idle).run(reqs)
+    assert stats.completed == 48 and stats.rejected == 0
+    used = {r.algo for r in reqs}
+    if mode == "mixed":
+        assert used == {"abia", "jsiia", "cfa"} or used == {"abia", "cfa"}   # JSIIA gives way past 128 links
+    for r in reqs:
+        pick = np.unique(np.minimum([0, r.chains // 2, r.chains - 1], r.chains - 1))
+        sub = robots.take(np.full(len(pick), r.robot))
+        idx = np.concatenate([np.arange(r.n * b, r.n * b + r.n) for b in pick])
+        q, qd, tau = (x.numpy()[idx] for x in (r.q, r.qd, r.tau))
+        ref = oracle.fd(sub, q, qd, tau)
+        err = oracle.relative_error(r.out.numpy()[idx], ref, sub.offsets)
+        bar = _bar(r.algo, sub, q, sub.offsets)
+        assert np.all(err <= bar), (r.rid, r.algo, r.n, (err / bar).max())
