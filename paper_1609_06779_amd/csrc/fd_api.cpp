@@ -117,6 +117,16 @@ fd_status_t plan_batch(const fd_model* m, const fd_batch_t* b, BatchPlan* p) {
     return FD_OK;
 }
 
+// Bytes of interleaved model and workspace that a lane-per-chain launch
+// streams per sweep. Past the last-level cache (256 MB Infinity Cache on
+// MI355X) nothing survives until the next sweep, so the kernels stream them
+// with non-temporal accesses and leave the cache to the chain state.
+constexpr size_t kLastLevelCache = size_t(256) << 20;
+bool stream_model(const fd_model* m, int batch, int nmax) {
+    const size_t esz = m->dtype == FD_F64 ? sizeof(double) : sizeof(float);
+    return (size_t)batch * nmax * (fdk::MF_IL_COUNT + 7) * esz > kLastLevelCache;
+}
+
 fd_status_t from_hip(hipError_t e) {
     if (e == hipSuccess) return FD_OK;
     if (e == hipErrorInvalidConfiguration) return FD_ERR_UNSUPPORTED;
@@ -154,7 +164,8 @@ fd_status_t forward_t(const fd_model* m, const BatchPlan& p, const void* q, cons
         case FD_ALGO_ABIA: {
             size_t need = fdk::abia_workspace_elems(p.cm.batch, p.nmax) * sizeof(T);
             if (!ws || ws_bytes < need) return FD_ERR_WORKSPACE;
-            return from_hip(fdk::launch_abia<T>(v, p.cm, p.nmax, tq, tqd, tt, out, static_cast<T*>(ws), st));
+            return from_hip(fdk::launch_abia<T>(v, p.cm, p.nmax, tq, tqd, tt, out, static_cast<T*>(ws),
+                                                stream_model(m, p.cm.batch, p.nmax), st));
         }
         case FD_ALGO_JSIIA:
             if (np > fdk::jsiia_max_np<T>()) return FD_ERR_UNSUPPORTED;
@@ -378,10 +389,11 @@ fd_status_t fd_forward_persistent(const fd_model_t* m, const fd_batch_t* b, cons
     if (m->dtype == FD_F64)
         return from_hip(fdk::launch_abia_persistent<double>(view<double>(m), p.cm, p.nmax, g, (const double*)q,
                                                             (const double*)qd, (const double*)tau, (double*)qdd,
-                                                            (double*)abws, planp, m->d_slot_robot, st));
+                                                            (double*)abws, planp, m->d_slot_robot,
+                                                            stream_model(m, b->batch, p.nmax), st));
     return from_hip(fdk::launch_abia_persistent<float>(view<float>(m), p.cm, p.nmax, g, (const float*)q,
                                                        (const float*)qd, (const float*)tau, (float*)qdd, (float*)abws,
-                                                       planp, m->d_slot_robot, st));
+                                                       planp, m->d_slot_robot, stream_model(m, b->batch, p.nmax), st));
 }
 
 fd_status_t fd_backward_workspace_size(const fd_model_t* m, const fd_batch_t* b, size_t* bytes) {

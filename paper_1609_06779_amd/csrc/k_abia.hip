@@ -31,10 +31,10 @@ size_t abia_workspace_elems(int batch, int nmax) {
 
 // Model reads go through the robot-interleaved copy: lanes hold consecutive
 // chains, so field f of link i is one contiguous read across the wavefront.
-template <typename T>
+template <bool NT, typename T>
 __device__ __forceinline__ Pose<T> link_pose_at(const ModelView<T>& m, int i, int slot, T q) {
     T rh[9], p[3];
-    m.home_il(i, slot, rh, p);
+    m.template home_il<NT>(i, slot, rh, p);
     return joint_pose(rh, p, q);
 }
 
@@ -56,8 +56,9 @@ template <typename T> __device__ __forceinline__ void congruence_to_parent(const
 }
 
 // One chain on one lane. wsb: this lane's workspace column, field f of link i
-// at wsb[(i * ABIA_WS_FIELDS + f) * 64].
-template <typename T>
+// at wsb[(i * ABIA_WS_FIELDS + f) * 64]. NT: model and workspace streamed with
+// non-temporal accesses (see ModelView::at_il).
+template <bool NT, typename T>
 __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInfo& ci, const T* __restrict__ q,
                                            const T* __restrict__ qd, const T* __restrict__ tau,
                                            T* __restrict__ qdd, T* __restrict__ wsb) {
@@ -66,7 +67,7 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
         return;
     }
     const int n = ci.n;
-    auto wsat = [&](int i, int f) -> T& { return wsb[((size_t)i * ABIA_WS_FIELDS + f) * 64]; };
+    auto wsp = [&](int i, int f) -> T* { return &wsb[((size_t)i * ABIA_WS_FIELDS + f) * 64]; };
 
     // sweep 1
     T v[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
@@ -74,7 +75,7 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
 #pragma unroll 2   // loads of two links in flight
     for (int i = 0; i < n; ++i) {
         const int64_t st = ci.state0 + i;
-        const Pose<T> tl = link_pose_at(m, i, ci.slot, q[st]);
+        const Pose<T> tl = link_pose_at<NT>(m, i, ci.slot, q[st]);
         const T qdi = qd[st];
         T t[6];
         ad_inv_apply(tl, v, t);
@@ -88,9 +89,9 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
 #pragma unroll
         for (int c = 0; c < 6; ++c) a[c] = t[c];
         T f[6];
-        link_force(m.inertia_il(i, ci.slot), v, a, f);
+        link_force(m.template inertia_il<NT>(i, ci.slot), v, a, f);
 #pragma unroll
-        for (int c = 0; c < 6; ++c) wsat(i, c) = f[c];
+        for (int c = 0; c < 6; ++c) st_ws<NT>(f[c], wsp(i, c));
     }
 
     // sweep 2
@@ -105,8 +106,8 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
         const int64_t st = ci.state0 + i;
         T f[6], fp[6], pp[6], jh[36];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) f[c] = wsat(i, c);
-        inertia_to_mat6(m.inertia_il(i, ci.slot), jh);
+        for (int c = 0; c < 6; ++c) f[c] = ld_ws<NT>(wsp(i, c));
+        inertia_to_mat6(m.template inertia_il<NT>(i, ci.slot), jh);
         if (i + 1 < n) {
             wrench_to_parent(tn, fc, fp);
             wrench_to_parent(tn, pc, pp);
@@ -127,8 +128,8 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
 #pragma unroll
         for (int c = 0; c < 6; ++c) h[c] = jh[6 * c + 2];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) wsat(i, c) = h[c] * dinv;
-        wsat(i, 6) = u * dinv;
+        for (int c = 0; c < 6; ++c) st_ws<NT>(h[c] * dinv, wsp(i, c));
+        st_ws<NT>(u * dinv, wsp(i, 6));
 #pragma unroll
         for (int r = 0; r < 6; ++r)
 #pragma unroll
@@ -138,7 +139,7 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
             pc[c] = pp[c] + h[c] * u * dinv;
             fc[c] = f[c];
         }
-        tn = link_pose_at(m, i, ci.slot, q[st]);
+        tn = link_pose_at<NT>(m, i, ci.slot, q[st]);
     }
 
     // sweep 3
@@ -146,12 +147,12 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
 #pragma unroll 2   // loads of two links in flight
     for (int i = 0; i < n; ++i) {
         const int64_t st = ci.state0 + i;
-        const Pose<T> tl = link_pose_at(m, i, ci.slot, q[st]);
+        const Pose<T> tl = link_pose_at<NT>(m, i, ci.slot, q[st]);
         T t[6];
         ad_inv_apply(tl, acc, t);
-        T x = wsat(i, 6);
+        T x = ld_ws<NT>(wsp(i, 6));
 #pragma unroll
-        for (int c = 0; c < 6; ++c) x -= wsat(i, c) * t[c];
+        for (int c = 0; c < 6; ++c) x -= ld_ws<NT>(wsp(i, c)) * t[c];
         t[2] += x;
 #pragma unroll
         for (int c = 0; c < 6; ++c) acc[c] = t[c];
@@ -159,7 +160,7 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
     }
 }
 
-template <typename T>
+template <typename T, bool NT>
 __global__ __launch_bounds__(64) void k_abia(ModelView<T> m, ChainMap cm, int nmax, const T* __restrict__ q,
                                              const T* __restrict__ qd, const T* __restrict__ tau,
                                              T* __restrict__ qdd, T* __restrict__ ws) {
@@ -167,7 +168,7 @@ __global__ __launch_bounds__(64) void k_abia(ModelView<T> m, ChainMap cm, int nm
     const int b = blockIdx.x * 64 + lane;
     if (b >= cm.batch) return;
     // workspace: [block][link][field][lane]
-    abia_chain(m, chain_info(m, cm, b), q, qd, tau, qdd, ws + (size_t)blockIdx.x * nmax * ABIA_WS_FIELDS * 64 + lane);
+    abia_chain<NT>(m, chain_info(m, cm, b), q, qd, tau, qdd, ws + (size_t)blockIdx.x * nmax * ABIA_WS_FIELDS * 64 + lane);
 }
 
 // Persistent form for ragged batches: each wavefront takes 64-entry tiles of
@@ -176,7 +177,7 @@ __global__ __launch_bounds__(64) void k_abia(ModelView<T> m, ChainMap cm, int nm
 // lengths and the longest tiles go first. Entries at or past the batch are
 // skipped. Every wavefront leaves once a tile index runs past the list, so
 // the grid always drains.
-template <typename T>
+template <typename T, bool NT>
 __global__ __launch_bounds__(64) void k_abia_persistent(ModelView<T> m, ChainMap cm, int nmax,
                                                         const int32_t* __restrict__ order, int32_t count,
                                                         int32_t* counter, const T* __restrict__ q,
@@ -193,7 +194,7 @@ __global__ __launch_bounds__(64) void k_abia_persistent(ModelView<T> m, ChainMap
         if ((int64_t)tile * 64 >= count) break;
         const int k = tile * 64 + lane;
         const int b = k < count ? (order ? order[k] : k) : cm.batch;
-        if (b < cm.batch) abia_chain(m, chain_info(m, cm, b), q, qd, tau, qdd, wsb);
+        if (b < cm.batch) abia_chain<NT>(m, chain_info(m, cm, b), q, qd, tau, qdd, wsb);
     }
 }
 
@@ -254,7 +255,7 @@ size_t abia_persistent_workspace_elems(int grid, int nmax) { return (size_t)grid
 template <typename T>
 hipError_t launch_abia_persistent(const ModelView<T>& m, const ChainMap& cm, int nmax, int grid, const T* q,
                                   const T* qd, const T* tau, T* qdd, T* ws, int32_t* plan,
-                                  const int32_t* slot_robot, hipStream_t st) {
+                                  const int32_t* slot_robot, bool stream_model, hipStream_t st) {
     if (cm.batch <= 0) return hipSuccess;
     int32_t* bins = plan;
     int32_t* cursor = bins + PLAN_BINS;
@@ -273,28 +274,36 @@ hipError_t launch_abia_persistent(const ModelView<T>& m, const ChainMap& cm, int
         tiles = slot_robot;
         count = m.num_robots;
     }
-    hipLaunchKernelGGL((k_abia_persistent<T>), dim3(grid), dim3(64), 0, st, m, cm, nmax, tiles, count, counter, q,
-                       qd, tau, qdd, ws);
+    if (stream_model)
+        hipLaunchKernelGGL((k_abia_persistent<T, true>), dim3(grid), dim3(64), 0, st, m, cm, nmax, tiles, count,
+                           counter, q, qd, tau, qdd, ws);
+    else
+        hipLaunchKernelGGL((k_abia_persistent<T, false>), dim3(grid), dim3(64), 0, st, m, cm, nmax, tiles, count,
+                           counter, q, qd, tau, qdd, ws);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_abia(const ModelView<T>& m, const ChainMap& cm, int nmax, const T* q, const T* qd, const T* tau,
-                       T* qdd, T* ws, hipStream_t st) {
+                       T* qdd, T* ws, bool stream_model, hipStream_t st) {
     if (cm.batch <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_abia<T>), dim3((cm.batch + 63) / 64), dim3(64), 0, st, m, cm, nmax, q, qd, tau, qdd, ws);
+    const dim3 grid((cm.batch + 63) / 64);
+    if (stream_model)
+        hipLaunchKernelGGL((k_abia<T, true>), grid, dim3(64), 0, st, m, cm, nmax, q, qd, tau, qdd, ws);
+    else
+        hipLaunchKernelGGL((k_abia<T, false>), grid, dim3(64), 0, st, m, cm, nmax, q, qd, tau, qdd, ws);
     return hipGetLastError();
 }
 
 template hipError_t launch_abia<double>(const ModelView<double>&, const ChainMap&, int, const double*, const double*,
-                                        const double*, double*, double*, hipStream_t);
+                                        const double*, double*, double*, bool, hipStream_t);
 template hipError_t launch_abia<float>(const ModelView<float>&, const ChainMap&, int, const float*, const float*,
-                                       const float*, float*, float*, hipStream_t);
+                                       const float*, float*, float*, bool, hipStream_t);
 template hipError_t launch_abia_persistent<double>(const ModelView<double>&, const ChainMap&, int, int, const double*,
                                                    const double*, const double*, double*, double*, int32_t*,
-                                                   const int32_t*, hipStream_t);
+                                                   const int32_t*, bool, hipStream_t);
 template hipError_t launch_abia_persistent<float>(const ModelView<float>&, const ChainMap&, int, int, const float*,
                                                   const float*, const float*, float*, float*, int32_t*,
-                                                  const int32_t*, hipStream_t);
+                                                  const int32_t*, bool, hipStream_t);
 
 }  // namespace fdk

@@ -60,7 +60,7 @@ __global__ __launch_bounds__(64) void k_jsiia_gj(ModelView<T> m, ChainMap cm, co
         my[c * NP + li] = k.s[c];
         my[(6 + c) * NP + li] = f[c];
     }
-    __syncthreads();
+    block_sync<64>();
     // row li of M: M_ik = s_min(i,k) . F_max(i,k); padding rows/columns are the identity
     T row[NP];
 #pragma unroll
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(64) void k_jsiia_gj(ModelView<T> m, ChainMap cm, co
         T* cj = col[j & 1][grp];
         cj[li] = row[j];
         cj[NP + li] = y;
-        __syncthreads();
+        block_sync<64>();
         const T piv = cj[j];
         const T rp = rcp_refined(piv);
         const bool me = li == j;
@@ -146,7 +146,7 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> 
         }
         sf[12 * NP + li] = active ? ti - tb : T(0);
     }
-    __syncthreads();
+    block_sync<TH>();
 
     const int r = li / G, c = li % G;
     // lower blocks a >= b, packed: index a (a + 1) / 2 + b
@@ -188,7 +188,7 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> 
                 cj[NP + 1] = mb[jb * (jb + 1) / 2 + jb];
             }
         }
-        __syncthreads();
+        block_sync<TH>();
         const T piv = cj[NP + 1];
         const T rp = rcp_refined(piv);
         const T yj = cj[NP];
@@ -225,14 +225,14 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> 
     for (int a = 0; a < 8; ++a) y[a] *= rd[a];
 #pragma unroll
     for (int jb = 7; jb >= 0; --jb) {
-        __syncthreads();                                    // earlier reads of the buffer are done
+        block_sync<TH>();                                    // earlier reads of the buffer are done
 #pragma unroll
         for (int bb = 0; bb <= jb; ++bb) wbuf[r * WS + c + G * bb] = mb[jb * (jb + 1) / 2 + bb];
         if (c == 0) {
             zb[r] = y[jb];
             rb[r] = rd[jb];
         }
-        __syncthreads();
+        block_sync<TH>();
         // x_t = z_t - (1 / d_t) sum_{u > t} m_ut x_u within the block
         T xc = T(0);
 #pragma unroll

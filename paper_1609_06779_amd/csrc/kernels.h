@@ -33,9 +33,11 @@ hipError_t launch_jsiia(int np, const ModelView<T>& m, const ChainMap& cm, const
                         const T* tau, T* qdd, int* status, hipStream_t st);
 template <typename T> int jsiia_max_np();
 // lane-per-chain kernel
+// stream_model: non-temporal model and workspace accesses (for launches whose
+// footprint outgrows the last-level cache; see stream_footprint)
 template <typename T>
 hipError_t launch_abia(const ModelView<T>& m, const ChainMap& cm, int nmax, const T* q, const T* qd,
-                       const T* tau, T* qdd, T* ws, hipStream_t st);
+                       const T* tau, T* qdd, T* ws, bool stream_model, hipStream_t st);
 size_t abia_workspace_elems(int batch, int nmax);
 // ragged batches: one persistent launch over chains sorted by decreasing length
 // (slot_robot: robot of each interleaved column, used when cm has no robot ids)
@@ -44,7 +46,7 @@ size_t abia_persistent_workspace_elems(int grid, int nmax);
 template <typename T>
 hipError_t launch_abia_persistent(const ModelView<T>& m, const ChainMap& cm, int nmax, int grid, const T* q,
                                   const T* qd, const T* tau, T* qdd, T* ws, int32_t* plan,
-                                  const int32_t* slot_robot, hipStream_t st);
+                                  const int32_t* slot_robot, bool stream_model, hipStream_t st);
 
 // reverse mode and the rollout step
 size_t vjp_workspace_elems(int batch, int nmax);

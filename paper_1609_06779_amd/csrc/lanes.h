@@ -98,22 +98,27 @@ template <typename T> struct ModelView {
     const int32_t* slot;
 
     __device__ __forceinline__ T at(int f, int64_t l) const { return base[f * stride + l]; }
-    __device__ __forceinline__ T at_il(int f, int i, int c) const {
-        return il[f * il_fstride + (int64_t)i * num_robots + c];
+    // NT: a non-temporal load, for launches whose model and workspace outgrow
+    // the last-level cache; then these lines, streamed once per sweep, do not
+    // push out the chain state the lane-per-chain kernels reuse across links.
+    template <bool NT = false> __device__ __forceinline__ T at_il(int f, int i, int c) const {
+        const T* p = &il[f * il_fstride + (int64_t)i * num_robots + c];
+        if constexpr (NT) return __builtin_nontemporal_load(p);
+        else return *p;
     }
-    __device__ __forceinline__ void home_il(int i, int c, T rh[9], T p[3]) const {
+    template <bool NT = false> __device__ __forceinline__ void home_il(int i, int c, T rh[9], T p[3]) const {
 #pragma unroll
-        for (int k = 0; k < 9; ++k) rh[k] = at_il(MF_ROT + k, i, c);
+        for (int k = 0; k < 9; ++k) rh[k] = at_il<NT>(MF_ROT + k, i, c);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) p[k] = at_il(MF_POS + k, i, c);
+        for (int k = 0; k < 3; ++k) p[k] = at_il<NT>(MF_POS + k, i, c);
     }
-    __device__ __forceinline__ Inertia<T> inertia_il(int i, int c) const {
+    template <bool NT = false> __device__ __forceinline__ Inertia<T> inertia_il(int i, int c) const {
         Inertia<T> j;
-        j.m = at_il(MF_MASS, i, c);
+        j.m = at_il<NT>(MF_MASS, i, c);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) j.h[k] = at_il(MF_H + k, i, c);
+        for (int k = 0; k < 3; ++k) j.h[k] = at_il<NT>(MF_H + k, i, c);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) j.ib[k] = at_il(MF_IB + k, i, c);
+        for (int k = 0; k < 6; ++k) j.ib[k] = at_il<NT>(MF_IB + k, i, c);
         return j;
     }
 
@@ -192,6 +197,23 @@ __device__ __forceinline__ ChainInfo chain_info(const ModelView<T>& m, const Cha
 template <typename T>
 __device__ __forceinline__ void fill_unsolved(T* out, int64_t first, int64_t count, int lane, int lanes) {
     for (int64_t k = lane; k < count; k += lanes) out[first + k] = T(__builtin_nan(""));
+}
+
+// Workspace access with the same cache policy as at_il<NT>.
+template <bool NT, typename T> __device__ __forceinline__ T ld_ws(const T* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT, typename T> __device__ __forceinline__ void st_ws(T v, T* p) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+// Block-wide LDS ordering. A block of one wavefront needs none: its LDS
+// operations complete in program order, so a write is seen by every later
+// read of the same wavefront. Larger blocks need the barrier.
+template <int THREADS> __device__ __forceinline__ void block_sync() {
+    if constexpr (THREADS > 64) __syncthreads();
 }
 
 // ---------------- lane-group exchange ----------------

@@ -13,6 +13,7 @@
 // Every D is factored once per level, by its own row, which publishes through
 // LDS what its neighbours need (two phases per level, see oee_solve_rows).
 #pragma once
+#include "lanes.h"
 #include "spatial.h"
 
 namespace fdk {
@@ -52,8 +53,8 @@ template <typename T, int K> __device__ __forceinline__ void packed_bwd(const T 
 
 // slot: this group's LDS area, OeeSlot<K>::size * NP values, component-major
 // (component c of row r at slot[c * NP + r]). All threads of the block must
-// call this (it synchronises); rows with active == false only take part in the
-// barriers. Only the lower triangle of d is read or written. On return r
+// call this (blocks of more than one wavefront synchronise); rows with
+// active == false only take part in the barriers. Only the lower triangle of d is read or written. On return r
 // holds x_i. Returns false if a pivot was not positive.
 //
 // Each level runs in two phases, so that one row's slot holds at most
@@ -115,7 +116,7 @@ __device__ bool oee_solve_rows(T d[K * K], T u[K * K], T r[K], int i, int n, boo
                 sq[a * NP + i] = q;
             }
         }
-        __syncthreads();
+        block_sync<(NP < 64 ? 64 : NP)>();
         if (active && i + s < n) {
             const int j = i + s;
             T wj[K];
@@ -152,7 +153,7 @@ __device__ bool oee_solve_rows(T d[K * K], T u[K * K], T r[K], int i, int n, boo
                 r[a] -= sq[a * NP + p];
             }
         }
-        __syncthreads();
+        block_sync<(NP < 64 ? 64 : NP)>();
         if (active) {
 #pragma unroll
             for (int b = 0; b < K; ++b) {
@@ -165,7 +166,7 @@ __device__ bool oee_solve_rows(T d[K * K], T u[K * K], T r[K], int i, int n, boo
                 for (int c = 0; c < K; ++c) sv[(c * K + b) * NP + i] = x[c];
             }
         }
-        __syncthreads();
+        block_sync<(NP < 64 ? 64 : NP)>();
         if (active && i + s < n) {
             const int j = i + s;
             const bool keep_u = i + 2 * s < n;
@@ -189,7 +190,7 @@ __device__ bool oee_solve_rows(T d[K * K], T u[K * K], T r[K], int i, int n, boo
 #pragma unroll
             for (int c = 0; c < K * K; ++c) u[c] = T(0);
         }
-        __syncthreads();                           // phase B reads done before the next level's writes
+        block_sync<(NP < 64 ? 64 : NP)>();                           // phase B reads done before the next level's writes
     }
     if (active) {
         ok = chol_inplace<T, K>(d) && ok;
