@@ -227,17 +227,16 @@ constexpr int ROW_SHL = 0x100, ROW_SHR = 0x110, WAVE_SHL1 = 0x130, WAVE_SHR1 = 0
               ROW_BCAST31 = 0x143, QUAD_XOR1 = 0xB1, QUAD_XOR2 = 0x4E, ROW_MIRROR = 0x140,
               ROW_HALF_MIRROR = 0x141;
 
-// Lane l takes the value that control CTRL routes to it; lanes with no source,
-// or in rows outside ROW_MASK, keep their own value.
+// Lane l takes the value that control CTRL routes to it. Lanes with no source
+// lane read 0; lanes in rows outside ROW_MASK are left undefined. (No "old"
+// operand: the result needs no copy of the source into the destination first.)
 template <int CTRL, int ROW_MASK = 0xf> __device__ __forceinline__ double mov(double v) {
-    int lo = __double2loint(v), hi = __double2hiint(v);
-    lo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROW_MASK, 0xf, false);
-    hi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROW_MASK, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, ROW_MASK, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, ROW_MASK, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 template <int CTRL, int ROW_MASK = 0xf> __device__ __forceinline__ float mov(float v) {
-    int x = __float_as_int(v);
-    return __int_as_float(__builtin_amdgcn_update_dpp(x, x, CTRL, ROW_MASK, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, ROW_MASK, 0xf, true));
 }
 template <int CTRL, int ROW_MASK = 0xf, typename T> __device__ __forceinline__ void mov_n(const T* v, T* out, int k) {
     for (int c = 0; c < k; ++c) out[c] = mov<CTRL, ROW_MASK>(v[c]);
@@ -353,10 +352,12 @@ __device__ __forceinline__ void scan_add(T* x, int li, T* lds) {
             _Pragma("unroll") for (int c = 0; c < K; ++c) x[c] += o[c]; \
         }                                               \
     }
-        FDK_ADD_STEP(dpp::ROW_SHR + 1, 0xf, lr >= 1)
-        if constexpr (NP > 2) FDK_ADD_STEP(dpp::ROW_SHR + 2, 0xf, lr >= 2)
-        if constexpr (NP > 4) FDK_ADD_STEP(dpp::ROW_SHR + 4, 0xf, lr >= 4)
-        if constexpr (NP > 8) FDK_ADD_STEP(dpp::ROW_SHR + 8, 0xf, lr >= 8)
+        // inside a row, lanes with no source read 0: groups of whole rows add unconditionally
+        constexpr bool rows = NP >= 16;
+        FDK_ADD_STEP(dpp::ROW_SHR + 1, 0xf, rows || lr >= 1)
+        if constexpr (NP > 2) FDK_ADD_STEP(dpp::ROW_SHR + 2, 0xf, rows || lr >= 2)
+        if constexpr (NP > 4) FDK_ADD_STEP(dpp::ROW_SHR + 4, 0xf, rows || lr >= 4)
+        if constexpr (NP > 8) FDK_ADD_STEP(dpp::ROW_SHR + 8, 0xf, rows || lr >= 8)
         if constexpr (NP > 16) FDK_ADD_STEP(dpp::ROW_BCAST15, 0xa, (lane & 16) != 0)
         if constexpr (NP > 32) FDK_ADD_STEP(dpp::ROW_BCAST31, 0xc, (lane & 32) != 0)
 #undef FDK_ADD_STEP
@@ -387,7 +388,7 @@ __device__ __forceinline__ void scan_add_rev(T* x, int li, T* lds) {
     {                                                   \
         T o[K];                                         \
         dpp::mov_n<dpp::ROW_SHL + S, 0xf>(x, o, K);     \
-        if (lr + S < W) {                               \
+        if (W == 16 || lr + S < W) {                    \
             _Pragma("unroll") for (int c = 0; c < K; ++c) x[c] += o[c]; \
         }                                               \
     }
