@@ -21,7 +21,7 @@ namespace fdk {
 template <int K> struct OeeSlot {
     static constexpr int L = K * (K + 1) / 2;   // packed lower factor of D (diagonal = 1/L_jj)
     static constexpr int A = 2 * L + 2 * K;     // phase A: factor, L^-1 R, U^T D^-1 U (packed), U^T D^-1 R
-    static constexpr int B = K * K;             // phase B: D^-1 U
+    static constexpr int B = K * K;             // phase B: L^-1 U
     static constexpr int size = A > B ? A : B;
 };
 
@@ -40,31 +40,20 @@ __device__ __forceinline__ void packed_fwd(const T* lf, int np, T x[K]) {
     }
 }
 
-// x <- L^-T x with a packed factor held in registers
-template <typename T, int K> __device__ __forceinline__ void packed_bwd(const T lp[], T x[K]) {
-#pragma unroll
-    for (int i = K - 1; i >= 0; --i) {
-        T s = x[i];
-#pragma unroll
-        for (int k = i + 1; k < K; ++k) s -= lp[tri<K>(k, i)] * x[k];
-        x[i] = s * lp[tri<K>(i, i)];
-    }
-}
-
 // slot: this group's LDS area, OeeSlot<K>::size * NP values, component-major
 // (component c of row r at slot[c * NP + r]). All threads of the block must
 // call this (blocks of more than one wavefront synchronise); rows with
-// active == false only take part in the barriers. Only the lower triangle of d is read or written. On return r
-// holds x_i. Returns false if a pivot was not positive.
+// active == false only take part in the barriers. Only the lower triangle of
+// d is read or written. On return r holds x_i. Returns false if a pivot was
+// not positive.
 //
 // Each level runs in two phases, so that one row's slot holds at most
-// max(A, B) values:
-//  A. every row factors its own D = L L^T and publishes L, L^-1 R and, for
-//     the row below it (i + s), the whole K-part: K_{i+s} U_i = U^T D^-1 U
-//     and K_{i+s} R_i = U^T D^-1 R. The E-part reads L_{i+s} and L^-1 R_{i+s}:
-//     with T = L_{i+s}^-1 U_i^T, E_i U_i^T = T^T T and E_i R_{i+s} =
-//     T^T (L^-1 R)_{i+s}.
-//  B. every row publishes D^-1 U; the E-part sets U_i <- -U_i (D^-1 U)_{i+s}.
+// max(A, B) values. With D = L L^T and W = L^-1 U (per row):
+//  A. every row publishes L, L^-1 R and, for the row below it (i + s), the
+//     whole K-part: K_{i+s} U_i = W^T W and K_{i+s} R_i = W^T (L^-1 R). The
+//     E-part of row i forms T = L_{i+s}^-1 U_i^T, then E_i U_i^T = T^T T and
+//     E_i R_{i+s} = T^T (L^-1 R)_{i+s}.
+//  B. every row publishes W; the E-part sets U_i <- -E_i U_{i+s} = -T^T W_{i+s}.
 template <typename T, int K, int NP>
 __device__ bool oee_solve_rows(T d[K * K], T u[K * K], T r[K], int i, int n, bool active, T* slot) {
     using S = OeeSlot<K>;
@@ -77,9 +66,10 @@ __device__ bool oee_solve_rows(T d[K * K], T u[K * K], T r[K], int i, int n, boo
     bool ok = true;
 #pragma unroll 1
     for (int s = 1; s < NP; s <<= 1) {
-        T lp[L];                                   // own factor, kept for phase B
+        T w[K][K];                                 // w[b] = L^-1 (column b of U), published in phase B
+        T t[K][K];                                 // t[a] = L_{i+s}^-1 (row a of U), used again in phase B
         if (active) {
-            T l[K * K];
+            T l[K * K], lp[L];
 #pragma unroll
             for (int c = 0; c < K * K; ++c) l[c] = d[c];
             ok = chol_inplace<T, K>(l) && ok;
@@ -87,7 +77,7 @@ __device__ bool oee_solve_rows(T d[K * K], T u[K * K], T r[K], int i, int n, boo
             for (int a = 0; a < K; ++a)
 #pragma unroll
                 for (int b = 0; b <= a; ++b) lp[tri<K>(a, b)] = l[a * K + b];
-            T w[K][K], wr[K];                      // w[b] = L^-1 (column b of U), wr = L^-1 R
+            T wr[K];                               // L^-1 R
 #pragma unroll
             for (int b = 0; b < K; ++b) {
 #pragma unroll
@@ -117,12 +107,12 @@ __device__ bool oee_solve_rows(T d[K * K], T u[K * K], T r[K], int i, int n, boo
             }
         }
         block_sync<(NP < 64 ? 64 : NP)>();
-        if (active && i + s < n) {
+        const bool has_e = active && i + s < n;
+        if (has_e) {
             const int j = i + s;
             T wj[K];
 #pragma unroll
             for (int c = 0; c < K; ++c) wj[c] = sw[c * NP + j];
-            T t[K][K];                             // t[a] = L_j^-1 (row a of U_i)
 #pragma unroll
             for (int a = 0; a < K; ++a) {
 #pragma unroll
@@ -156,33 +146,24 @@ __device__ bool oee_solve_rows(T d[K * K], T u[K * K], T r[K], int i, int n, boo
         block_sync<(NP < 64 ? 64 : NP)>();
         if (active) {
 #pragma unroll
-            for (int b = 0; b < K; ++b) {
-                T x[K];
+            for (int b = 0; b < K; ++b)
 #pragma unroll
-                for (int c = 0; c < K; ++c) x[c] = u[c * K + b];
-                packed_fwd<T, K>(lp, 1, x);
-                packed_bwd<T, K>(lp, x);
-#pragma unroll
-                for (int c = 0; c < K; ++c) sv[(c * K + b) * NP + i] = x[c];
-            }
+                for (int c = 0; c < K; ++c) sv[(b * K + c) * NP + i] = w[b][c];
         }
         block_sync<(NP < 64 ? 64 : NP)>();
-        if (active && i + s < n) {
+        if (has_e) {
             const int j = i + s;
             const bool keep_u = i + 2 * s < n;
-            T vj[K * K];
 #pragma unroll
-            for (int c = 0; c < K * K; ++c) vj[c] = sv[c * NP + j];
+            for (int b = 0; b < K; ++b) {
+                T wb[K];                           // W_{i+s}, column b of U_{i+s}
 #pragma unroll
-            for (int a = 0; a < K; ++a) {
-                T row[K];
+                for (int c = 0; c < K; ++c) wb[c] = sv[(b * K + c) * NP + j];
 #pragma unroll
-                for (int c = 0; c < K; ++c) row[c] = u[a * K + c];
-#pragma unroll
-                for (int b = 0; b < K; ++b) {
+                for (int a = 0; a < K; ++a) {
                     T v = T(0);
 #pragma unroll
-                    for (int c = 0; c < K; ++c) v += row[c] * vj[c * K + b];
+                    for (int c = 0; c < K; ++c) v += t[a][c] * wb[c];
                     u[a * K + b] = keep_u ? -v : T(0);
                 }
             }
@@ -190,7 +171,7 @@ __device__ bool oee_solve_rows(T d[K * K], T u[K * K], T r[K], int i, int n, boo
 #pragma unroll
             for (int c = 0; c < K * K; ++c) u[c] = T(0);
         }
-        block_sync<(NP < 64 ? 64 : NP)>();                           // phase B reads done before the next level's writes
+        block_sync<(NP < 64 ? 64 : NP)>();        // phase B reads done before the next level's writes
     }
     if (active) {
         ok = chol_inplace<T, K>(d) && ok;
