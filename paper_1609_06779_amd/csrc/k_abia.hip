@@ -122,7 +122,7 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
             for (int c = 0; c < 6; ++c) pp[c] = T(0);
         }
         const T td = tau[st] - f[2];
-        const T dinv = T(1) / jh[14];
+        const T dinv = rcp_refined(jh[14]);
         const T u = td - pp[2];
         T h[6];
 #pragma unroll

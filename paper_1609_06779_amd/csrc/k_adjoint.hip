@@ -112,7 +112,7 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
 #pragma unroll
                 for (int c = 0; c < 6; ++c) pp[c] = T(0);
             }
-            const T dinv = T(1) / jh[14];
+            const T dinv = rcp_refined(jh[14]);
             const T u = gqdd[st] - pp[2];
             T h[6];
 #pragma unroll

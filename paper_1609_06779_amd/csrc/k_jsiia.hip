@@ -19,17 +19,6 @@
 
 namespace fdk {
 
-// 1/p to full precision from the hardware estimate and two Newton steps (p > 0, normal).
-__device__ __forceinline__ double rcp_refined(double p) {
-    double r = __builtin_amdgcn_rcp(p);
-    r = __builtin_fma(r, __builtin_fma(-p, r, 1.0), r);
-    return __builtin_fma(r, __builtin_fma(-p, r, 1.0), r);
-}
-__device__ __forceinline__ float rcp_refined(float p) {
-    float r = __builtin_amdgcn_rcpf(p);
-    return __builtin_fmaf(r, __builtin_fmaf(-p, r, 1.0f), r);
-}
-
 // Gauss-Jordan on register rows (NP <= 64: one wavefront holds 64 / NP chains).
 template <typename T, int NP>
 __global__ __launch_bounds__(64) void k_jsiia_gj(ModelView<T> m, ChainMap cm, const T* __restrict__ q,

@@ -100,7 +100,7 @@ __device__ __forceinline__ void composite_force(const LinkLane<T>& k, bool activ
         const T m = k.jb.m;
         T rc[3];                       // R c = R h / m
         matvec3(r, k.jb.h, rc);
-        const T invm = T(1) / m;
+        const T invm = rcp_refined(m);
         rc[0] *= invm; rc[1] *= invm; rc[2] *= invm;
         T cs[3] = {rc[0] + k.g.p[0], rc[1] + k.g.p[1], rc[2] + k.g.p[2]};
         const T* s = k.jb.ib;

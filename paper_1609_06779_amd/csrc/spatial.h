@@ -184,6 +184,29 @@ template <typename T> __device__ __forceinline__ void inertia_to_mat6(const Iner
 
 // In-place lower Cholesky of a K x K SPD matrix stored row-major in a[K*K];
 // only the lower triangle is read and written. Returns false on a non-positive pivot.
+// 1/p and 1/sqrt(p) to full precision for p > 0 (normal): the hardware
+// estimate refined by Newton steps, in place of the division and square-root
+// expansions. For p <= 0 the result is meaningless; callers check p > 0.
+__device__ __forceinline__ double rcp_refined(double p) {
+    double r = __builtin_amdgcn_rcp(p);
+    r = __builtin_fma(r, __builtin_fma(-p, r, 1.0), r);
+    return __builtin_fma(r, __builtin_fma(-p, r, 1.0), r);
+}
+__device__ __forceinline__ float rcp_refined(float p) {
+    float r = __builtin_amdgcn_rcpf(p);
+    return __builtin_fmaf(r, __builtin_fmaf(-p, r, 1.0f), r);
+}
+// y <- y + (y / 2)(1 - p y^2)
+__device__ __forceinline__ double rsqrt_refined(double p) {
+    double y = __builtin_amdgcn_rsq(p);
+    y = __builtin_fma(0.5 * y, __builtin_fma(-p * y, y, 1.0), y);
+    return __builtin_fma(0.5 * y, __builtin_fma(-p * y, y, 1.0), y);
+}
+__device__ __forceinline__ float rsqrt_refined(float p) {
+    float y = __builtin_amdgcn_rsqf(p);
+    return __builtin_fmaf(0.5f * y, __builtin_fmaf(-p * y, y, 1.0f), y);
+}
+
 template <typename T, int K> __device__ __forceinline__ bool chol_inplace(T a[K * K]) {
     bool ok = true;
 #pragma unroll
@@ -192,8 +215,7 @@ template <typename T, int K> __device__ __forceinline__ bool chol_inplace(T a[K 
 #pragma unroll
         for (int k = 0; k < j; ++k) d -= a[j * K + k] * a[j * K + k];
         ok = ok && (d > T(0));
-        T l = sqrt(d);
-        T r = T(1) / l;
+        const T r = rsqrt_refined(d);           // 1 / L_jj
         a[j * K + j] = r;                       // keep the reciprocal of the pivot
 #pragma unroll
         for (int i = j + 1; i < K; ++i) {
