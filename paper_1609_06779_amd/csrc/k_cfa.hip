@@ -19,17 +19,19 @@ namespace fdk {
 
 __device__ __forceinline__ constexpr int wsel(int a) { return a < 2 ? a : a + 1; }   // W_i coordinates
 
-// Up to 64 links: two wavefronts per SIMD (the register cap costs a small
+// Two wavefronts per SIMD (the register cap costs a small
 // spill; latency hiding between the two wins, measured 14-17 % on MI355X).
 template <typename T, int NP>
-__global__ __launch_bounds__(Geo<NP>::threads, NP <= 64 ? 2 : 1) void k_cfa(ModelView<T> m, ChainMap cm, const T* __restrict__ q,
+__global__ __launch_bounds__(Geo<NP>::threads, 2) void k_cfa(ModelView<T> m, ChainMap cm, const T* __restrict__ q,
                                                            const T* __restrict__ qd, const T* __restrict__ tau,
                                                            T* __restrict__ qdd, int* __restrict__ status) {
-    // one array: the cross-wavefront scan exchange (NP > 64 only), then the OEE slots
-    constexpr int XB = NP > 64 ? 12 * NP : 0;
-    __shared__ T lds_all[XB + Geo<NP>::chains * NP * OeeSlot<5>::size];
+    // The cross-wavefront scan exchange (NP > 64 only) and the OEE slots share
+    // one array: the scans before the OEE and after it end with a barrier, and
+    // so does every OEE level.
+    constexpr int OS = Geo<NP>::chains * NP * OeeSlot<5>::size;
+    __shared__ T lds_all[(NP > 64 && 12 * NP > OS) ? 12 * NP : OS];
     T* xbuf = lds_all;
-    T* oslot = lds_all + XB;
+    T* oslot = lds_all;
     const int grp = threadIdx.x / NP, li = threadIdx.x % NP;
     const int b = blockIdx.x * Geo<NP>::chains + grp;
     ChainInfo ci{0, 0, 0, 0, 0};

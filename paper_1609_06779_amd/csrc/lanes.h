@@ -327,13 +327,35 @@ __device__ __forceinline__ Pose<T> scan_pose(Pose<T> x, int li, T* lds) {
 #undef FDK_POSE_STEP
         return x;
     } else {
+        // each wavefront scans its 64 lanes, then takes the product of the
+        // earlier wavefronts' totals (lane 63 of each) from LDS
+        constexpr int WAVES = NP / 64;
+        x = scan_pose<64>(x, li & 63, lds);
+        const int w = li >> 6;
+        if ((li & 63) == 63 && w + 1 < WAVES) {
 #pragma unroll
-        for (int s = 1; s < NP; s <<= 1) {
-            Pose<T> o;
-            shift_up<NP>(x.r, o.r, 9, s, lds);
-            shift_up<NP>(x.p, o.p, 3, s, lds);
-            if (li >= s) x = pose_mul(o, x);
+            for (int c = 0; c < 9; ++c) lds[12 * w + c] = x.r[c];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) lds[12 * w + 9 + c] = x.p[c];
         }
+        __syncthreads();
+        if (w > 0) {
+            Pose<T> o;
+#pragma unroll
+            for (int c = 0; c < 9; ++c) o.r[c] = lds[c];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) o.p[c] = lds[9 + c];
+            for (int k = 1; k < w; ++k) {
+                Pose<T> t;
+#pragma unroll
+                for (int c = 0; c < 9; ++c) t.r[c] = lds[12 * k + c];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) t.p[c] = lds[12 * k + 9 + c];
+                o = pose_mul(o, t);
+            }
+            x = pose_mul(o, x);
+        }
+        __syncthreads();
         return x;
     }
 }
@@ -362,15 +384,20 @@ __device__ __forceinline__ void scan_add(T* x, int li, T* lds) {
         if constexpr (NP > 32) FDK_ADD_STEP(dpp::ROW_BCAST31, 0xc, (lane & 32) != 0)
 #undef FDK_ADD_STEP
     } else {
+        // each wavefront sums its 64 lanes, then adds the earlier wavefronts' totals
+        constexpr int WAVES = NP / 64;
+        scan_add<64, K>(x, li & 63, lds);
+        const int w = li >> 6;
+        if ((li & 63) == 63 && w + 1 < WAVES) {
 #pragma unroll
-        for (int s = 1; s < NP; s <<= 1) {
-            T o[K];
-            shift_up<NP>(x, o, K, s, lds);
-            if (li >= s) {
-#pragma unroll
-                for (int c = 0; c < K; ++c) x[c] += o[c];
-            }
+            for (int c = 0; c < K; ++c) lds[K * w + c] = x[c];
         }
+        __syncthreads();
+        for (int k = 0; k < w; ++k) {
+#pragma unroll
+            for (int c = 0; c < K; ++c) x[c] += lds[K * k + c];
+        }
+        __syncthreads();
     }
 }
 
@@ -413,15 +440,21 @@ __device__ __forceinline__ void scan_add_rev(T* x, int li, T* lds) {
             }
         }
     } else {
+        // each wavefront sums its 64 lanes from the back, then adds the later
+        // wavefronts' totals (lane 0 of each)
+        constexpr int WAVES = NP / 64;
+        scan_add_rev<64, K>(x, li & 63, lds);
+        const int w = li >> 6;
+        if ((li & 63) == 0 && w > 0) {
 #pragma unroll
-        for (int s = 1; s < NP; s <<= 1) {
-            T o[K];
-            shift_down<NP>(x, o, K, s, lds);
-            if (li + s < NP) {
-#pragma unroll
-                for (int c = 0; c < K; ++c) x[c] += o[c];
-            }
+            for (int c = 0; c < K; ++c) lds[K * w + c] = x[c];
         }
+        __syncthreads();
+        for (int k = w + 1; k < WAVES; ++k) {
+#pragma unroll
+            for (int c = 0; c < K; ++c) x[c] += lds[K * k + c];
+        }
+        __syncthreads();
     }
 }
 
