@@ -1,4 +1,4 @@
-"""CPU oracle for batched forward dynamics of serial chains.
+"""CPU oracle for batched forward dynamics of serial chains (and branched trees).
 
 TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
 CPU-baseline leg may call it; the library's product path never does. It shares
@@ -29,6 +29,7 @@ _lib = None
 
 _d = ctypes.POINTER(ctypes.c_double)
 _i64 = ctypes.POINTER(ctypes.c_int64)
+_i32 = ctypes.POINTER(ctypes.c_int32)
 
 
 def build(force: bool = False) -> str:
@@ -48,7 +49,7 @@ def _load():
     if _lib is None:
         build()
         lib = ctypes.CDLL(_LIB)
-        model = [_d] * 7
+        model = [_d] * 7 + [_i32]
         lib.oracle_rnea_batch.argtypes = [ctypes.c_int, _i64, _i64] + model + [_d, _d, _d, ctypes.c_int, _d, ctypes.c_int]
         lib.oracle_crba_batch.argtypes = [ctypes.c_int, _i64, _i64] + model + [_d, _i64, _d, ctypes.c_int]
         lib.oracle_fd_batch.argtypes = [ctypes.c_int, _i64, _i64] + model + [_d, _d, _d, _d, ctypes.c_int]
@@ -88,10 +89,13 @@ class _Model:
         self.com = _c(robots.com)
         self.inertia = _c(robots.inertia)
         self.gravity = _c(robots.gravity)
+        par = getattr(robots, "parent", None)
+        self.parent = None if par is None else _c(par, np.int32)
 
     def args(self):
         return [_p(self.axis), _p(self.home_rot), _p(self.offset), _p(self.mass), _p(self.com),
-                _p(self.inertia), _p(self.gravity)]
+                _p(self.inertia), _p(self.gravity),
+                None if self.parent is None else self.parent.ctypes.data_as(_i32)]
 
 
 def _offsets(robots, offsets):

@@ -68,13 +68,15 @@ class Chain:
         self.com = robots.com[sl]
         self.inertia = robots.inertia[sl]
         self.gravity = np.asarray(robots.gravity, dtype=np.float64)
+        par = getattr(robots, "parent", None)
+        self.parent = np.arange(n) - 1 if par is None else np.asarray(par[sl], dtype=np.int64)
 
     def pose(self, i, q):
-        """T_{i-1,i} = (Rhome_i Rot(axis_i, q_i), offset_i)."""
+        """T_{p(i),i} = (Rhome_i Rot(axis_i, q_i), offset_i), p(i) = i - 1 on a serial chain."""
         return self.home[i] @ rot(self.axis[i], q), self.offset[i]
 
     def ad_link(self, i, q):
-        """Ad_i = Ad(T_{i-1,i}^-1): the (i, i-1) block of Gamma."""
+        """Ad_i = Ad(T_{p(i),i}^-1): the (i, p(i)) block of Gamma."""
         r, p = self.pose(i, q)
         return ad_pose(r.T, -r.T @ p)
 
@@ -83,14 +85,19 @@ class Chain:
 
 
 def global_matrices(ch: Chain, q):
-    """Gamma (6n x 6n, block lower), S (6n x n), J (6n x 6n) of eq. (EOM-full)."""
+    """Gamma (6n x 6n, block lower), S (6n x n), J (6n x 6n) of eq. (EOM-full).
+
+    On a serial chain Gamma's blocks sit at (i, i - 1); on a tree at (i, p(i)),
+    the parent of link i (the paper treats chains only; this is the tree reading).
+    """
     n = ch.n
     gam = np.zeros((6 * n, 6 * n))
     s = np.zeros((6 * n, n))
     j = np.zeros((6 * n, 6 * n))
     for i in range(n):
-        if i > 0:
-            gam[6 * i:6 * i + 6, 6 * (i - 1):6 * i] = ch.ad_link(i, q[i])
+        p = ch.parent[i]
+        if p >= 0:
+            gam[6 * i:6 * i + 6, 6 * p:6 * p + 6] = ch.ad_link(i, q[i])
         s[6 * i:6 * i + 6, i] = ch.screw(i)
         j[6 * i:6 * i + 6, 6 * i:6 * i + 6] = inertia6(ch.mass[i], ch.com[i], ch.inertia[i])
     return gam, s, j
@@ -117,9 +124,10 @@ def bias_torque(ch: Chain, q, qd, qdd=None, gravity=True):
     for i in range(n):
         vi = v[6 * i:6 * i + 6]
         rhs[6 * i:6 * i + 6] += ad_twist(vi) @ (ch.screw(i) * qd[i])
-    if gravity:
+    if gravity:                        # the base acceleration enters every link hung from the base
         a0 = np.concatenate([np.zeros(3), -ch.gravity])
-        rhs[0:6] += ch.ad_link(0, q[0]) @ a0
+        for i in np.flatnonzero(ch.parent < 0):
+            rhs[6 * i:6 * i + 6] += ch.ad_link(i, q[i]) @ a0
     a = np.linalg.solve(ig, rhs)
     f = j @ a
     for i in range(n):
@@ -240,31 +248,32 @@ def jsiia_qdd(ch: Chain, q, tau_delta):
 def abia_qdd(ch: Chain, q, tau_delta):
     """ABIA (Sec. II-C): articulated-body inertias by the nonlinear backward
     recursion, then the two linear (bi-diagonal) recursions, applied to
-    tau_delta with zero velocity and no gravity. Returns qdd = M^-1 tau_delta."""
+    tau_delta with zero velocity and no gravity. Returns qdd = M^-1 tau_delta.
+    On a tree every link passes its terms to its parent p(i), where the
+    children's terms add up (p(i) = i - 1 on a serial chain)."""
     n = ch.n
+    par = ch.parent
     ad = [ch.ad_link(i, q[i]) for i in range(n)]
-    jb = [inertia6(ch.mass[i], ch.com[i], ch.inertia[i]) for i in range(n)]
     s = [ch.screw(i) for i in range(n)]
-    jhat = [None] * n
+    jhat = [inertia6(ch.mass[i], ch.com[i], ch.inertia[i]) for i in range(n)]
+    p = [np.zeros(6) for _ in range(n)]  # bias wrench from the children of link i
     h = [None] * n
     dd = np.zeros(n)
     u = np.zeros(n)
-    jhat[n - 1] = jb[n - 1].copy()
-    p = np.zeros(6)                      # bias wrench from the children of link i
     for i in range(n - 1, -1, -1):
         h[i] = jhat[i] @ s[i]
         dd[i] = s[i] @ h[i]
         pi = jhat[i] - np.outer(h[i], h[i]) / dd[i]
-        u[i] = tau_delta[i] - s[i] @ p
-        if i > 0:
-            jhat[i - 1] = jb[i - 1] + ad[i].T @ pi @ ad[i]
-            p = ad[i].T @ (p + h[i] * u[i] / dd[i])
+        u[i] = tau_delta[i] - s[i] @ p[i]
+        if par[i] >= 0:
+            jhat[par[i]] = jhat[par[i]] + ad[i].T @ pi @ ad[i]
+            p[par[i]] = p[par[i]] + ad[i].T @ (p[i] + h[i] * u[i] / dd[i])
     qdd = np.zeros(n)
-    a = np.zeros(6)
+    acc = [None] * n
     for i in range(n):
-        a = ad[i] @ a
+        a = ad[i] @ acc[par[i]] if par[i] >= 0 else np.zeros(6)
         qdd[i] = (u[i] - h[i] @ a) / dd[i]
-        a = a + s[i] * qdd[i]
+        acc[i] = a + s[i] * qdd[i]
     return qdd
 
 

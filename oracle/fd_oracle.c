@@ -1,5 +1,6 @@
 /*
- * fd_oracle.c -- plain, slow CPU oracle for forward dynamics of serial chains.
+ * fd_oracle.c -- plain, slow CPU oracle for forward dynamics of serial chains
+ * (and of branched trees).
  *
  * TEST INFRASTRUCTURE ONLY. Nothing in the library's product path may link,
  * load or call this file: only the tests, the smoke check and the benchmark's
@@ -33,6 +34,11 @@
  *   A_i  = Ad_i A_{i-1} + S_i qdd_i + ad_{V_i}(S_i qd_i)
  *   F_i  = Ad_{i+1}^T F_{i+1} + J_i A_i - ad_{V_i}^T (J_i V_i)
  *   tau_i = S_i^T F_i
+ *
+ * Branched robots (trees; the paper treats serial chains only). Link i hangs
+ * from link p(i) < i, or from the base, and its pose is taken in p(i)'s frame:
+ * Gamma has the block Ad_i at (i, p(i)) instead of (i, i - 1). Then i - 1
+ * above reads p(i), and F_i sums Ad_c^T F_c over all children c of i.
  *
  * Everything is written with explicit 6x6 matrices so that it can be checked
  * against the formulas by eye; speed is not a goal.
@@ -81,12 +87,12 @@ int oracle_rnea_batch(int batch, const int64_t *offsets, const int64_t *model_st
         int n = (int)(offsets[b + 1] - offsets[b]);
         if (n <= 0) continue;
         chain_t c = chain_at(&ma, MSTART(b), n);
-        vec6 *wv = malloc(sizeof(vec6) * n), *wf = malloc(sizeof(vec6) * n);
+        vec6 *wv = malloc(sizeof(vec6) * n), *wc = malloc(sizeof(vec6) * n), *wf = malloc(sizeof(vec6) * n);
         mat6 *wa = malloc(sizeof(mat6) * n);
-        if (!wv || !wf || !wa) { bad++; free(wv); free(wf); free(wa); continue; }
+        if (!wv || !wc || !wf || !wa) { bad++; free(wv); free(wc); free(wf); free(wa); continue; }
         int64_t o = offsets[b];
-        rnea_chain(&c, q + o, qd + o, qdd ? qdd + o : NULL, with_gravity, tau + o, wv, wf, wa);
-        free(wv); free(wf); free(wa);
+        rnea_chain(&c, q + o, qd + o, qdd ? qdd + o : NULL, with_gravity, tau + o, wv, wc, wf, wa);
+        free(wv); free(wc); free(wf); free(wa);
     }
     return bad ? -1 : 0;
 }
@@ -125,13 +131,13 @@ int oracle_fd_batch(int batch, const int64_t *offsets, const int64_t *model_star
         if (n <= 0) continue;
         int64_t o = offsets[b];
         chain_t c = chain_at(&ma, MSTART(b), n);
-        vec6 *wv = malloc(sizeof(vec6) * n), *wf = malloc(sizeof(vec6) * n);
+        vec6 *wv = malloc(sizeof(vec6) * n), *wc = malloc(sizeof(vec6) * n), *wf = malloc(sizeof(vec6) * n);
         mat6 *wa = malloc(sizeof(mat6) * n), *wi = malloc(sizeof(mat6) * n);
         double *m = malloc(sizeof(double) * n * n), *bias = malloc(sizeof(double) * n);
-        if (!wv || !wf || !wa || !wi || !m || !bias) {
+        if (!wv || !wc || !wf || !wa || !wi || !m || !bias) {
             bad++;
         } else {
-            rnea_chain(&c, q + o, qd + o, NULL, 1, bias, wv, wf, wa);
+            rnea_chain(&c, q + o, qd + o, NULL, 1, bias, wv, wc, wf, wa);
             for (int i = 0; i < n; ++i) bias[i] = tau[o + i] - bias[i];
             crba_chain(&c, q + o, m, wa, wi);
             if (cholesky_solve(n, m, bias, qdd + o) != 0) {
@@ -139,7 +145,7 @@ int oracle_fd_batch(int batch, const int64_t *offsets, const int64_t *model_star
                 for (int i = 0; i < n; ++i) qdd[o + i] = NAN;
             }
         }
-        free(wv); free(wf); free(wa); free(wi); free(m); free(bias);
+        free(wv); free(wc); free(wf); free(wa); free(wi); free(m); free(bias);
     }
     return bad;
 }
@@ -177,22 +183,24 @@ int oracle_energy_batch(int batch, const int64_t *offsets, const int64_t *model_
         int64_t o = offsets[b];
         chain_t c = chain_at(&ma, MSTART(b), n);
         double *rot = malloc(sizeof(double) * 9 * n), *pos = malloc(sizeof(double) * 3 * n);
-        if (!rot || !pos) { bad++; free(rot); free(pos); continue; }
+        vec6 *vl = malloc(sizeof(vec6) * n);
+        if (!rot || !pos || !vl) { bad++; free(rot); free(pos); free(vl); continue; }
         fk_chain(&c, q + o, rot, pos);
         double ke = 0, pe = 0;
-        vec6 vprev = {{0, 0, 0, 0, 0, 0}};
+        vec6 vbase = {{0, 0, 0, 0, 0, 0}};
         for (int i = 0; i < n; ++i) {
             double r[3][3], p[3];
             link_pose(&c, i, q[o + i], r, p);
             mat6 ad = ad_pose_inv(r, p);
             vec6 s = joint_screw(&c, i);
             vec6 sqd = vec6_scale(&s, qd[o + i]);
-            vec6 t = mat6_vec(&ad, &vprev);
+            int par = parent_of(&c, i);
+            vec6 t = mat6_vec(&ad, par >= 0 ? &vl[par] : &vbase);
             vec6 v = vec6_add(&t, &sqd);
             mat6 j = spatial_inertia(&c, i);
             vec6 jv = mat6_vec(&j, &v);
             ke += 0.5 * vec6_dot(&v, &jv);
-            vprev = v;
+            vl[i] = v;
             const double *cc = &c.com[3 * i];
             double xc[3];
             for (int a = 0; a < 3; ++a)
@@ -202,7 +210,7 @@ int oracle_energy_batch(int batch, const int64_t *offsets, const int64_t *model_
         }
         kinetic[b] = ke;
         potential[b] = pe;
-        free(rot); free(pos);
+        free(rot); free(pos); free(vl);
     }
     return bad ? -1 : 0;
 }

@@ -42,9 +42,9 @@ int oracle_fd_jvp_batch(int batch, const int64_t *offsets, const int64_t *model_
         chain_t c = chain_at(&ma, MSTART(b), n);
         REAL *xq = malloc(sizeof(REAL) * n), *xqd = malloc(sizeof(REAL) * n), *xt = malloc(sizeof(REAL) * n);
         REAL *bias = malloc(sizeof(REAL) * n), *x = malloc(sizeof(REAL) * n), *m = malloc(sizeof(REAL) * n * n);
-        vec6 *wv = malloc(sizeof(vec6) * n), *wf = malloc(sizeof(vec6) * n);
+        vec6 *wv = malloc(sizeof(vec6) * n), *wc = malloc(sizeof(vec6) * n), *wf = malloc(sizeof(vec6) * n);
         mat6 *wa = malloc(sizeof(mat6) * n), *wi = malloc(sizeof(mat6) * n);
-        if (!xq || !xqd || !xt || !bias || !x || !m || !wv || !wf || !wa || !wi) {
+        if (!xq || !xqd || !xt || !bias || !x || !m || !wv || !wc || !wf || !wa || !wi) {
             bad++;
         } else {
             for (int i = 0; i < n; ++i) {
@@ -52,7 +52,7 @@ int oracle_fd_jvp_batch(int batch, const int64_t *offsets, const int64_t *model_
                 xqd[i] = qd[o + i] + I * CX_STEP * dqd[o + i];
                 xt[i] = tau[o + i] + I * CX_STEP * dtau[o + i];
             }
-            rnea_chain(&c, xq, xqd, NULL, 1, bias, wv, wf, wa);
+            rnea_chain(&c, xq, xqd, NULL, 1, bias, wv, wc, wf, wa);
             for (int i = 0; i < n; ++i) bias[i] = xt[i] - bias[i];
             crba_chain(&c, xq, m, wa, wi);
             if (cholesky_solve(n, m, bias, x) != 0) {
@@ -65,7 +65,7 @@ int oracle_fd_jvp_batch(int batch, const int64_t *offsets, const int64_t *model_
                 }
             }
         }
-        free(xq); free(xqd); free(xt); free(bias); free(x); free(m); free(wv); free(wf); free(wa); free(wi);
+        free(xq); free(xqd); free(xt); free(bias); free(x); free(m); free(wv); free(wc); free(wf); free(wa); free(wi);
     }
     return bad;
 }
@@ -85,9 +85,9 @@ int oracle_rnea_jvp_batch(int batch, const int64_t *offsets, const int64_t *mode
         chain_t c = chain_at(&ma, MSTART(b), n);
         REAL *xq = malloc(sizeof(REAL) * n), *xqd = malloc(sizeof(REAL) * n), *xa = malloc(sizeof(REAL) * n);
         REAL *t = malloc(sizeof(REAL) * n);
-        vec6 *wv = malloc(sizeof(vec6) * n), *wf = malloc(sizeof(vec6) * n);
+        vec6 *wv = malloc(sizeof(vec6) * n), *wc = malloc(sizeof(vec6) * n), *wf = malloc(sizeof(vec6) * n);
         mat6 *wa = malloc(sizeof(mat6) * n);
-        if (!xq || !xqd || !xa || !t || !wv || !wf || !wa) {
+        if (!xq || !xqd || !xa || !t || !wv || !wc || !wf || !wa) {
             bad++;
         } else {
             for (int i = 0; i < n; ++i) {
@@ -95,10 +95,10 @@ int oracle_rnea_jvp_batch(int batch, const int64_t *offsets, const int64_t *mode
                 xqd[i] = qd[o + i] + I * CX_STEP * dqd[o + i];
                 xa[i] = qdd[o + i] + I * CX_STEP * dqdd[o + i];
             }
-            rnea_chain(&c, xq, xqd, xa, with_gravity, t, wv, wf, wa);
+            rnea_chain(&c, xq, xqd, xa, with_gravity, t, wv, wc, wf, wa);
             for (int i = 0; i < n; ++i) dtau[o + i] = cimag(t[i]) / CX_STEP;
         }
-        free(xq); free(xqd); free(xa); free(t); free(wv); free(wf); free(wa);
+        free(xq); free(xqd); free(xa); free(t); free(wv); free(wc); free(wf); free(wa);
     }
     return bad ? -1 : 0;
 }

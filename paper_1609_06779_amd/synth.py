@@ -19,6 +19,13 @@ The paper initialises robot parameters (twists) and joint inputs at random
 * gravity (0, 0, -9.81) in the base frame;
 * state: q ~ U[-pi, pi], qd ~ U[-1, 1], tau ~ N(0, 1).
 
+Branched robots (trees) add a parent index per link (``make_tree_parents``):
+links are numbered in depth-first preorder, so every parent precedes its
+children and every subtree is a contiguous run of links. Link i extends the
+previous link with probability ``p_extend``, else it hangs from a uniformly
+drawn link of the current root-to-link path (or from the base). The per-link
+parameters are drawn as above, with frame i-1 read as the parent's frame.
+
 All per-link arrays are packed chain after chain (``offsets`` gives each
 chain's first link), the layout the library and the oracle both take.
 """
@@ -35,6 +42,7 @@ GRAVITY = (0.0, 0.0, -9.81)
 _STREAM_MODEL = 0
 _STREAM_STATE = 1
 _STREAM_LENGTHS = 2
+_STREAM_TOPOLOGY = 3
 
 
 def _rng(seed: int, cfg: int, stream: int, extra: int = 0) -> np.random.Generator:
@@ -82,6 +90,7 @@ class Robots:
     com: np.ndarray              # [N, 3] centre of mass in frame i
     inertia: np.ndarray          # [N, 6] about the COM: xx yy zz xy xz yz
     gravity: np.ndarray = field(default_factory=lambda: np.array(GRAVITY))
+    parent: np.ndarray | None = None  # [N] int32 parent of link i within its robot, -1 = base; None = serial
 
     @property
     def offsets(self) -> np.ndarray:
@@ -99,7 +108,14 @@ class Robots:
             n_links=self.n_links[robot_ids].astype(np.int32),
             axis=self.axis[idx], home_rot=self.home_rot[idx], offset=self.offset[idx],
             mass=self.mass[idx], com=self.com[idx], inertia=self.inertia[idx],
-            gravity=self.gravity.copy())
+            gravity=self.gravity.copy(), parent=None if self.parent is None else self.parent[idx])
+
+    def parents(self) -> np.ndarray:
+        """Parent of every link within its robot (-1 = base), also for serial robots."""
+        if self.parent is not None:
+            return np.asarray(self.parent, dtype=np.int32)
+        off = self.offsets
+        return (np.arange(self.total_links, dtype=np.int64) - np.repeat(off[:-1], self.n_links) - 1).astype(np.int32)
 
     def astype_rounded(self, dtype) -> "Robots":
         """The same robots with every parameter rounded through ``dtype`` (kept as float64)."""
@@ -107,7 +123,8 @@ class Robots:
             return np.asarray(a, dtype=dtype).astype(np.float64)
         return Robots(n_links=self.n_links.copy(), axis=r(self.axis), home_rot=r(self.home_rot),
                       offset=r(self.offset), mass=r(self.mass), com=r(self.com),
-                      inertia=r(self.inertia), gravity=r(self.gravity))
+                      inertia=r(self.inertia), gravity=r(self.gravity),
+                      parent=None if self.parent is None else self.parent.copy())
 
 
 def make_robots(n_links, seed: int = ROOT_SEED, cfg: int = 0, random_home: bool = False) -> Robots:
@@ -132,6 +149,38 @@ def make_robots(n_links, seed: int = ROOT_SEED, cfg: int = 0, random_home: bool 
         home = np.tile(np.eye(3).reshape(1, 9), (total, 1))
     return Robots(n_links=n_links, axis=axis, home_rot=home, offset=offset, mass=mass,
                   com=com, inertia=inertia)
+
+
+def make_tree_parents(n_links, p_extend: float = 0.85, seed: int = ROOT_SEED, cfg: int = 0) -> np.ndarray:
+    """Parent of every link (-1 = base) of one random tree per entry of ``n_links``,
+    numbered in depth-first preorder (see the module docstring)."""
+    n_links = np.asarray(n_links, dtype=np.int32)
+    rng = _rng(seed, cfg, _STREAM_TOPOLOGY)
+    total = int(np.sum(n_links, dtype=np.int64))
+    u = rng.random(total)
+    pick = rng.random(total)
+    out = np.empty(total, np.int32)
+    k = 0
+    for n in n_links:
+        path = [-1]                               # the base, then the current root-to-link path
+        for i in range(int(n)):
+            if i > 0 and u[k] < p_extend:
+                p = i - 1
+            else:
+                p = path[int(pick[k] * len(path))]
+            del path[path.index(p) + 1:]
+            path.append(i)
+            out[k] = p
+            k += 1
+    return out
+
+
+def make_tree_robots(n_links, p_extend: float = 0.85, seed: int = ROOT_SEED, cfg: int = 0,
+                     random_home: bool = False) -> Robots:
+    """Random branched robots: ``make_robots`` parameters plus ``make_tree_parents`` topology."""
+    rb = make_robots(n_links, seed=seed, cfg=cfg, random_home=random_home)
+    rb.parent = make_tree_parents(n_links, p_extend=p_extend, seed=seed, cfg=cfg)
+    return rb
 
 
 def make_state(n_links, seed: int = ROOT_SEED, cfg: int = 0, rep: int = 0):
@@ -161,6 +210,7 @@ WORKLOADS = {
     "uniform-n32-b65536": dict(batch=65536, n=32, cfg=2),
     "uniform-n64-b65536": dict(batch=65536, n=64, cfg=2),
     "uniform-n128-b65536": dict(batch=65536, n=128, cfg=2),
+    "tree-n64-b65536": dict(batch=65536, n=64, cfg=5, p_extend=0.85),
 }
 
 
