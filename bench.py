@@ -158,7 +158,11 @@ def summarize_trace(trace_dir: str, workload: str, commands, summary_cmd: str, b
     if bench_log:
         for line in open(bench_log):
             if line.startswith("{"):
-                events = {a: v["ms_per_launch"] * 1e3 for a, v in json.loads(line).get("per_algo", {}).items()}
+                rec = json.loads(line)
+                events = {a: v["ms_per_launch"] * 1e3 for a, v in rec.get("per_algo", {}).items()}
+                trees = rec.get("trees", {})
+                if not events and len(trees) == 1:      # a run of one tree workload alone
+                    events = {"abia": next(iter(trees.values()))["ms_per_launch"] * 1e3}
 
     files = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
     if not files:
@@ -301,6 +305,72 @@ def ragged_leg(dtype: str, batch: int = 100000, lo: int = 4, hi: int = 256, reps
             "plain_ragged_ms": ms_plain, "per_length_launches": len(groups), "per_length_ms": ms_split}
 
 
+def copy_calibration(dev):
+    """Device copies of COPY_CALIB_BYTES: the known-size reference for the HBM counters."""
+    import torch
+
+    src = torch.empty(COPY_CALIB_BYTES, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+TREE_WORKLOADS = ("tree-shared-n64-b65536", "tree-n64-b65536")
+
+
+def tree_leg(dtype: str, reps: int = 10, keys=TREE_WORKLOADS):
+    """Branched robots, one articulated-body launch over 65536 trees of 64 links
+    (depth-first numbered; each link extends the previous one with probability
+    0.85, else hangs from a random link of the current path). Two topology
+    mixes: one topology shared by every robot (each with its own parameters),
+    and a random topology per robot (lanes of a wavefront branch at different
+    links, the worst case for divergence)."""
+    import torch
+
+    from paper_1609_06779_amd import fd, synth
+
+    dev = torch.device("cuda:0")
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    esz = 8 if dtype == "f64" else 4
+    out = {}
+    for key in keys:
+        w = synth.WORKLOADS[key]
+        batch, n = w["batch"], w["n"]
+        lengths = synth.uniform_lengths(batch, n)
+        rb = synth.make_tree_robots(lengths, p_extend=w["p_extend"], cfg=w["cfg"],
+                                    shared_topology=w.get("shared_topology", False))
+        if dtype == "f32":
+            rb = rb.astype_rounded(np.float32)
+        q, qd, tau = synth.make_state(lengths, cfg=w["cfg"])
+        model = fd.Model(rb, dtype, device=dev)
+        tq, tqd, ttau = (torch.from_numpy(a).to(dev, tdt) for a in (q, qd, tau))
+        res = torch.empty_like(tq)
+        ws = model.workspace(batch, "abia")
+        stream = torch.cuda.current_stream()
+        model.forward(tq, tqd, ttau, batch=batch, algo="abia", out=res, workspace=ws, stream=stream)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            model.forward(tq, tqd, ttau, batch=batch, algo="abia", out=res, workspace=ws, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        assert torch.isfinite(res).all().item(), f"{key}: tree ABIA produced non-finite qdd"
+        par = rb.parents().reshape(batch, n)
+        branch_points = float(np.mean([(np.bincount(p[p >= 0], minlength=n) > 1).sum() for p in par[:1024]]))
+        algo_bytes = batch * n * ((4 + 22) * esz + 4)       # state, the model's 22 fields and one tree code
+        out[key] = {"ms_per_launch": ms, "solves_per_s": batch / (ms * 1e-3),
+                    "branch_points_per_tree": branch_points, "algorithmic_bytes": algo_bytes,
+                    "algorithmic_gb_per_s": algo_bytes / (ms * 1e-3) / 1e9}
+        model.close()
+        del model, tq, tqd, ttau, res, ws
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -314,6 +384,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
+    ap.add_argument("--no-tree", action="store_true")
+    ap.add_argument("--only-trees", action="store_true", help="run the branched-robot leg alone")
+    ap.add_argument("--tree-workloads", default=",".join(TREE_WORKLOADS))
+    ap.add_argument("--workload", help="with --trace-summary or --pmc-summary: the workload name to file under")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a 256 MiB device copy, the known-size reference for HBM counters")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -324,21 +398,32 @@ def main():
                     help="summarise a rocprofv3 --kernel-trace --stats run into profiles/ and exit (no GPU use)")
     ap.add_argument("--bench-log", help="with --trace-summary: output of the profiled bench.py run")
     args = ap.parse_args()
+    wl = args.workload or f"fd_forward_n{args.n}_b{args.batch}_{args.dtype}"
+    wl_flag = f" --workload {args.workload}" if args.workload else ""
     if args.trace_summary:
-        print(summarize_trace(args.trace_summary, f"fd_forward_n{args.n}_b{args.batch}_{args.dtype}",
-                              args.pmc_command, f"python bench.py --trace-summary {args.trace_summary} --n {args.n} "
-                              f"--batch {args.batch} --dtype {args.dtype} --bench-log {args.bench_log} "
+        print(summarize_trace(args.trace_summary, wl, args.pmc_command,
+                              f"python bench.py --trace-summary {args.trace_summary} --n {args.n} "
+                              f"--batch {args.batch} --dtype {args.dtype}{wl_flag} --bench-log {args.bench_log} "
                               f"--pmc-command ...", args.bench_log))
         return
     if args.pmc_summary:
-        print(summarize_pmc(*args.pmc_summary, f"fd_forward_n{args.n}_b{args.batch}_{args.dtype}",
-                            args.pmc_command, f"python bench.py --pmc-summary {' '.join(args.pmc_summary)} --n {args.n} "
-                            f"--batch {args.batch} --dtype {args.dtype} --pmc-command ..."))
+        print(summarize_pmc(*args.pmc_summary, wl, args.pmc_command,
+                            f"python bench.py --pmc-summary {' '.join(args.pmc_summary)} --n {args.n} "
+                            f"--batch {args.batch} --dtype {args.dtype}{wl_flag} --pmc-command ..."))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); chains are independent, so a "
               "multi-GPU run would shard the batch with no exchange. Nothing was run.", file=sys.stderr)
         sys.exit(2)
+
+    tree_keys = [k for k in args.tree_workloads.split(",") if k]
+    if args.only_trees:
+        print(f"[bench] tree leg alone: {tree_keys} {args.dtype}", file=sys.stderr, flush=True)
+        if args.copy_calib:
+            import torch
+            copy_calibration(torch.device("cuda:0"))
+        print(json.dumps({"trees": tree_leg(args.dtype, keys=tree_keys), "dtype": args.dtype}), flush=True)
+        return
 
     import torch
 
@@ -368,12 +453,7 @@ def main():
                 events[a][1].record(stream)
 
     if args.copy_calib:
-        src = torch.empty(COPY_CALIB_BYTES, dtype=torch.uint8, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_calibration(dev)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -428,6 +508,9 @@ def main():
     if not args.no_ragged:
         print("[bench] ragged leg", file=sys.stderr, flush=True)
         result["ragged"] = ragged_leg(args.dtype)
+    if not args.no_tree:
+        print("[bench] tree leg", file=sys.stderr, flush=True)
+        result["trees"] = tree_leg(args.dtype, keys=tree_keys)
     if not args.no_serve:
         print("[bench] serving leg", file=sys.stderr, flush=True)
         result["serving"] = serving_leg(args.dtype)

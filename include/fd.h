@@ -18,6 +18,11 @@
  * Conventions. A robot is a serial chain of n revolute joints on a fixed base.
  * Twists are (w; v), wrenches (n; f). Link frame i sits on joint i's axis; its
  * pose in frame i-1 is T_{i-1,i}(q_i) = (Rhome_i Rot(axis_i, q_i), offset_i).
+ * Branched robots (trees, beyond the paper's serial chains) name a parent per
+ * link, and i-1 above reads that parent; only the articulated-body algorithm
+ * takes them (fd_forward with FD_ALGO_ABIA or FD_ALGO_AUTO, and
+ * fd_forward_persistent); the other entry points return FD_ERR_UNSUPPORTED for
+ * a model that holds one.
  * Gravity acts as a base acceleration (the "const." terms of eq. (EOM-full));
  * there is no force at the end effector. SI units, angles in radians.
  *
@@ -72,6 +77,9 @@ typedef struct {
     const double* com;       /* [L][3] centre of mass in frame i */
     const double* inertia;   /* [L][6] SPD inertia about the COM, frame-i axes: xx yy zz xy xz yz */
     double gravity[3];       /* gravitational acceleration in the base frame, e.g. {0, 0, -9.81} */
+    const int32_t* parent;   /* [L] parent of link i within its robot (0-based, < i), -1 = the base;
+                                NULL: every robot is a serial chain (parent i-1). The pose, offset
+                                and home rotation of link i are then taken in its parent's frame. */
 } fd_model_desc_t;
 
 /* A batch of chains (device pointers). */
@@ -89,12 +97,13 @@ typedef struct {
 } fd_batch_t;
 
 /* Upload a robot set in the given precision (FD_F32 rounds every parameter).
- * Validates masses, inertias, axes and rotations; FD_ERR_INVALID_ARG if any is
- * out of range. Synchronous. On success *out owns device memory until fd_destroy. */
+ * Validates masses, inertias, axes, rotations and parents; FD_ERR_INVALID_ARG if
+ * any is out of range. Synchronous. On success *out owns device memory until fd_destroy. */
 fd_status_t fd_init(const fd_model_desc_t* desc, fd_dtype_t dtype, fd_model_t** out);
 void fd_destroy(fd_model_t* model);
 fd_dtype_t fd_model_dtype(const fd_model_t* model);
-/* Longest chain any algorithm of this build takes for the model's precision (JSIIA may be lower). */
+/* Longest chain any algorithm of this build takes for the model's precision (JSIIA may be lower;
+ * 0 for JSIIA and CFA when the model holds a branched robot). */
 int32_t fd_max_links(const fd_model_t* model, fd_algo_t algo);
 
 /* Bytes of workspace fd_forward needs for this batch and algorithm (0 if none). */

@@ -29,6 +29,7 @@ class ModelDesc(ctypes.Structure):
         ("com", ctypes.POINTER(ctypes.c_double)),
         ("inertia", ctypes.POINTER(ctypes.c_double)),
         ("gravity", ctypes.c_double * 3),
+        ("parent", ctypes.POINTER(ctypes.c_int32)),
     ]
 
 

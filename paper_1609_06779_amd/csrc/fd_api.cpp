@@ -27,6 +27,8 @@ struct fd_model {
     int32_t* d_n_links = nullptr;
     int32_t* d_slot = nullptr;        // [num_robots] column of each robot in d_il
     int32_t* d_slot_robot = nullptr;  // [num_robots] robot of each column
+    bool tree = false;                // some robot is branched (a link's parent is not link i-1)
+    int32_t* d_tree = nullptr;        // [nmax][num_robots] tree codes (see lanes.h), null without branches
 };
 
 namespace {
@@ -74,6 +76,7 @@ template <typename T> fdk::ModelView<T> view(const fd_model* m) {
     v.il = static_cast<const T*>(m->d_il);
     v.il_fstride = (int64_t)m->nmax * m->num_robots;
     v.slot = m->d_slot;
+    v.tree = m->d_tree;
     return v;
 }
 
@@ -144,8 +147,9 @@ int log2_bucket(int batch) {
     return k;
 }
 
-fd_algo_t pick_algo(fd_dtype_t dtype, int nmax, int batch) {
-    const std::vector<int8_t>& t = g_auto[dtype == FD_F64 ? 0 : 1];
+fd_algo_t pick_algo(const fd_model* m, int nmax, int batch) {
+    if (m->tree) return FD_ALGO_ABIA;   // the only algorithm built for branched robots
+    const std::vector<int8_t>& t = g_auto[m->dtype == FD_F64 ? 0 : 1];
     if (!t.empty() && nmax >= 1 && nmax <= kMaxLinks) return (fd_algo_t)t[nmax * 21 + log2_bucket(batch)];
     // built-in rule: one lane per chain wins once the batch fills the GPU
     return FD_ALGO_ABIA;
@@ -162,15 +166,16 @@ fd_status_t forward_t(const fd_model* m, const BatchPlan& p, const void* q, cons
     const int np = pow2_lanes(p.nmax);
     switch (algo) {
         case FD_ALGO_ABIA: {
-            size_t need = fdk::abia_workspace_elems(p.cm.batch, p.nmax) * sizeof(T);
+            size_t need = fdk::abia_workspace_elems(p.cm.batch, p.nmax, m->tree) * sizeof(T);
             if (!ws || ws_bytes < need) return FD_ERR_WORKSPACE;
             return from_hip(fdk::launch_abia<T>(v, p.cm, p.nmax, tq, tqd, tt, out, static_cast<T*>(ws),
                                                 stream_model(m, p.cm.batch, p.nmax), st));
         }
         case FD_ALGO_JSIIA:
-            if (np > fdk::jsiia_max_np<T>()) return FD_ERR_UNSUPPORTED;
+            if (m->tree || np > fdk::jsiia_max_np<T>()) return FD_ERR_UNSUPPORTED;
             return from_hip(fdk::launch_jsiia<T>(np, v, p.cm, tq, tqd, tt, out, nullptr, st));
         case FD_ALGO_CFA:
+            if (m->tree) return FD_ERR_UNSUPPORTED;
             return from_hip(fdk::launch_cfa<T>(np, v, p.cm, tq, tqd, tt, out, nullptr, st));
         default:
             return FD_ERR_INVALID_ARG;
@@ -194,12 +199,34 @@ fd_status_t fd_init(const fd_model_desc_t* d, fd_dtype_t dtype, fd_model_t** out
     }
     static const double kEye[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
     std::vector<double> raw;
-    std::vector<uint8_t> first;
+    std::vector<int64_t> parent_link;
+    std::vector<int32_t> code;
     try {
         raw.resize((size_t)total * 25);
-        first.resize((size_t)total);
+        parent_link.resize((size_t)total);
+        code.assign((size_t)total, 0);
     } catch (const std::bad_alloc&) {
         return FD_ERR_OUT_OF_MEMORY;
+    }
+    // topology: parent links and the tree codes of the lane-per-chain kernel
+    bool tree = false;
+    for (int64_t r = 0, s0 = 0; r < d->num_robots; s0 += d->n_links[r], ++r) {
+        const int n = d->n_links[r];
+        for (int i = 0; i < n; ++i) {
+            const int p = d->parent ? d->parent[s0 + i] : i - 1;
+            if (p < -1 || p >= i) return FD_ERR_INVALID_ARG;
+            parent_link[s0 + i] = p >= 0 ? s0 + p : -1;
+            code[s0 + i] = (p + 1) | (p >= 0 && p == i - 1 ? fdk::TREE_CHAIN : 0);
+            tree = tree || p != i - 1;
+        }
+        std::vector<uint8_t> reached(n, 0);
+        for (int i = n - 1; i >= 0; --i) {   // children before parents, as in the backward sweep
+            const int p = parent_link[s0 + i] >= 0 ? (int)(parent_link[s0 + i] - s0) : -1;
+            if (p < 0 || p == i - 1) continue;
+            code[s0 + p] |= fdk::TREE_BRANCH;
+            if (!reached[p]) code[s0 + i] |= fdk::TREE_FIRST;
+            reached[p] = 1;
+        }
     }
     int64_t l = 0;
     for (int r = 0; r < d->num_robots; ++r) {
@@ -217,7 +244,6 @@ fd_status_t fd_init(const fd_model_desc_t* d, fd_dtype_t dtype, fd_model_t** out
             w[15] = d->mass[l];
             std::memcpy(w + 16, d->com + 3 * l, 3 * sizeof(double));
             std::memcpy(w + 19, d->inertia + 6 * l, 6 * sizeof(double));
-            first[l] = i == 0;
         }
     }
     fd_model* m = new (std::nothrow) fd_model;
@@ -238,6 +264,7 @@ fd_status_t fd_init(const fd_model_desc_t* d, fd_dtype_t dtype, fd_model_t** out
     }
     m->nmax = mx;
     m->uniform = uni;
+    m->tree = tree;
     for (int k = 0; k < 3; ++k) m->g[k] = d->gravity[k];
     // interleaved columns: robots by decreasing length, ties in robot order, so a
     // model of equal lengths keeps its order and 64 consecutive columns hold
@@ -259,10 +286,16 @@ fd_status_t fd_init(const fd_model_desc_t* d, fd_dtype_t dtype, fd_model_t** out
         s += d->n_links[r];
     }
     const int64_t il_elems = (int64_t)fdk::MF_IL_COUNT * mx * d->num_robots;
+    std::vector<int32_t> tree_il;
+    if (tree) {
+        tree_il.assign((size_t)mx * d->num_robots, 0);
+        for (int r = 0; r < d->num_robots; ++r)
+            for (int i = 0; i < d->n_links[r]; ++i) tree_il[(size_t)i * d->num_robots + slot[r]] = code[starts[r] + i];
+    }
     int32_t* d_ri = nullptr;
     const size_t esz = dtype == FD_F64 ? sizeof(double) : sizeof(float);
     double* d_raw = nullptr;
-    uint8_t* d_first = nullptr;
+    int64_t* d_parent = nullptr;
     fd_status_t st = FD_OK;
     hipError_t e = hipSuccess;
     if ((e = hipMalloc(&m->d_fields, esz * fdk::MF_COUNT * total)) != hipSuccess ||
@@ -271,7 +304,8 @@ fd_status_t fd_init(const fd_model_desc_t* d, fd_dtype_t dtype, fd_model_t** out
         (e = hipMalloc(&m->d_slot, sizeof(int32_t) * d->num_robots)) != hipSuccess ||
         (e = hipMalloc(&m->d_slot_robot, sizeof(int32_t) * d->num_robots)) != hipSuccess ||
         (e = hipMalloc(&d_raw, raw.size() * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc(&d_first, first.size())) != hipSuccess ||
+        (e = hipMalloc(&d_parent, sizeof(int64_t) * total)) != hipSuccess ||
+        (tree && (e = hipMalloc(&m->d_tree, sizeof(int32_t) * tree_il.size())) != hipSuccess) ||
         (e = hipMalloc(&m->d_il, esz * il_elems)) != hipSuccess ||
         (e = hipMalloc(&d_ri, sizeof(int32_t) * 2 * total)) != hipSuccess) {
         st = e == hipErrorOutOfMemory ? FD_ERR_OUT_OF_MEMORY : FD_ERR_DEVICE;
@@ -283,18 +317,20 @@ fd_status_t fd_init(const fd_model_desc_t* d, fd_dtype_t dtype, fd_model_t** out
             hipMemcpy(m->d_slot_robot, slot_robot.data(), sizeof(int32_t) * d->num_robots, hipMemcpyHostToDevice) !=
                 hipSuccess ||
             hipMemcpy(d_raw, raw.data(), raw.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(d_first, first.data(), first.size(), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(d_parent, parent_link.data(), sizeof(int64_t) * total, hipMemcpyHostToDevice) != hipSuccess ||
+            (tree && hipMemcpy(m->d_tree, tree_il.data(), sizeof(int32_t) * tree_il.size(), hipMemcpyHostToDevice) !=
+                         hipSuccess) ||
             hipMemcpy(d_ri, column_of.data(), sizeof(int32_t) * total, hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(d_ri + total, index_of.data(), sizeof(int32_t) * total, hipMemcpyHostToDevice) != hipSuccess ||
             hipMemset(m->d_il, 0, esz * il_elems) != hipSuccess ||
-            fdk::launch_model_init(total, d_raw, d_first, m->d_fields, dtype == FD_F32, nullptr) != hipSuccess ||
+            fdk::launch_model_init(total, d_raw, d_parent, m->d_fields, dtype == FD_F32, nullptr) != hipSuccess ||
             fdk::launch_model_interleave(total, d_ri, d_ri + total, d->num_robots, (int64_t)mx * d->num_robots,
                                          m->d_fields, m->d_il, dtype == FD_F32, nullptr) != hipSuccess ||
             hipDeviceSynchronize() != hipSuccess)
             st = FD_ERR_DEVICE;
     }
     if (d_raw) (void)hipFree(d_raw);
-    if (d_first) (void)hipFree(d_first);
+    if (d_parent) (void)hipFree(d_parent);
     if (d_ri) (void)hipFree(d_ri);
     if (st != FD_OK) {
         fd_destroy(m);
@@ -312,6 +348,7 @@ void fd_destroy(fd_model_t* m) {
     if (m->d_n_links) (void)hipFree(m->d_n_links);
     if (m->d_slot) (void)hipFree(m->d_slot);
     if (m->d_slot_robot) (void)hipFree(m->d_slot_robot);
+    if (m->d_tree) (void)hipFree(m->d_tree);
     delete m;
 }
 
@@ -319,6 +356,7 @@ fd_dtype_t fd_model_dtype(const fd_model_t* m) { return m ? m->dtype : FD_F64; }
 
 int32_t fd_max_links(const fd_model_t* m, fd_algo_t algo) {
     if (!m) return 0;
+    if (m->tree && (algo == FD_ALGO_JSIIA || algo == FD_ALGO_CFA)) return 0;
     if (algo == FD_ALGO_JSIIA) return m->dtype == FD_F64 ? fdk::jsiia_max_np<double>() : fdk::jsiia_max_np<float>();
     return kMaxLinks;
 }
@@ -328,9 +366,9 @@ fd_status_t fd_workspace_size(const fd_model_t* m, const fd_batch_t* b, fd_algo_
     BatchPlan p;
     fd_status_t s = plan_batch(m, b, &p);
     if (s != FD_OK) return s;
-    if (algo == FD_ALGO_AUTO) algo = pick_algo(m->dtype, p.nmax, b->batch);
+    if (algo == FD_ALGO_AUTO) algo = pick_algo(m, p.nmax, b->batch);
     const size_t esz = m->dtype == FD_F64 ? sizeof(double) : sizeof(float);
-    *bytes = algo == FD_ALGO_ABIA ? fdk::abia_workspace_elems(b->batch, p.nmax) * esz : 0;
+    *bytes = algo == FD_ALGO_ABIA ? fdk::abia_workspace_elems(b->batch, p.nmax, m->tree) * esz : 0;
     return FD_OK;
 }
 
@@ -342,7 +380,7 @@ fd_status_t fd_forward(const fd_model_t* m, const fd_batch_t* b, const void* q, 
     if (algo < FD_ALGO_ABIA || algo > FD_ALGO_AUTO) return FD_ERR_INVALID_ARG;
     if (b->batch == 0) return FD_OK;
     if (!q || !qd || !tau || !qdd) return FD_ERR_INVALID_ARG;
-    if (algo == FD_ALGO_AUTO) algo = pick_algo(m->dtype, p.nmax, b->batch);
+    if (algo == FD_ALGO_AUTO) algo = pick_algo(m, p.nmax, b->batch);
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     if (m->dtype == FD_F64) return forward_t<double>(m, p, q, qd, tau, qdd, algo, ws, ws_bytes, st);
     return forward_t<float>(m, p, q, qd, tau, qdd, algo, ws, ws_bytes, st);
@@ -366,7 +404,7 @@ fd_status_t fd_persistent_workspace_size(const fd_model_t* m, const fd_batch_t* 
     if (s != FD_OK) return s;
     const size_t esz = m->dtype == FD_F64 ? sizeof(double) : sizeof(float);
     const int g = persistent_grid(m->dtype, grid);
-    *bytes = align256(fdk::persistent_plan_bytes(b->batch)) + fdk::abia_persistent_workspace_elems(g, p.nmax) * esz;
+    *bytes = align256(fdk::persistent_plan_bytes(b->batch)) + fdk::abia_persistent_workspace_elems(g, p.nmax, m->tree) * esz;
     return FD_OK;
 }
 
@@ -382,7 +420,8 @@ fd_status_t fd_forward_persistent(const fd_model_t* m, const fd_batch_t* b, cons
     const size_t esz = m->dtype == FD_F64 ? sizeof(double) : sizeof(float);
     const int g = persistent_grid(m->dtype, grid);
     const size_t plan = align256(fdk::persistent_plan_bytes(b->batch));
-    if (!ws || ws_bytes < plan + fdk::abia_persistent_workspace_elems(g, p.nmax) * esz) return FD_ERR_WORKSPACE;
+    if (!ws || ws_bytes < plan + fdk::abia_persistent_workspace_elems(g, p.nmax, m->tree) * esz)
+        return FD_ERR_WORKSPACE;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     int32_t* planp = static_cast<int32_t*>(ws);
     void* abws = static_cast<char*>(ws) + plan;
@@ -401,6 +440,7 @@ fd_status_t fd_backward_workspace_size(const fd_model_t* m, const fd_batch_t* b,
     BatchPlan p;
     fd_status_t s = plan_batch(m, b, &p);
     if (s != FD_OK) return s;
+    if (m->tree) return FD_ERR_UNSUPPORTED;
     const size_t esz = m->dtype == FD_F64 ? sizeof(double) : sizeof(float);
     *bytes = fdk::vjp_workspace_elems(b->batch, p.nmax) * esz;
     return FD_OK;
@@ -412,6 +452,7 @@ fd_status_t fd_backward(const fd_model_t* m, const fd_batch_t* b, const void* q,
     BatchPlan p;
     fd_status_t s = plan_batch(m, b, &p);
     if (s != FD_OK) return s;
+    if (m->tree) return FD_ERR_UNSUPPORTED;
     if (b->batch == 0) return FD_OK;
     if (!q || !qd || !qdd || !gqdd || !gq || !gqd || !gtau) return FD_ERR_INVALID_ARG;
     const size_t esz = m->dtype == FD_F64 ? sizeof(double) : sizeof(float);
@@ -457,6 +498,7 @@ fd_status_t fd_inverse(const fd_model_t* m, const fd_batch_t* b, const void* q, 
     BatchPlan p;
     fd_status_t s = plan_batch(m, b, &p);
     if (s != FD_OK) return s;
+    if (m->tree) return FD_ERR_UNSUPPORTED;
     if (b->batch == 0) return FD_OK;
     if (!q || !qd || !tau) return FD_ERR_INVALID_ARG;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
@@ -472,6 +514,7 @@ fd_status_t fd_joint_inertia(const fd_model_t* m, const fd_batch_t* b, const voi
     BatchPlan p;
     fd_status_t s = plan_batch(m, b, &p);
     if (s != FD_OK) return s;
+    if (m->tree) return FD_ERR_UNSUPPORTED;
     if (b->offsets != nullptr) return FD_ERR_INVALID_ARG;
     if (b->batch == 0) return FD_OK;
     if (!q || !m_out) return FD_ERR_INVALID_ARG;

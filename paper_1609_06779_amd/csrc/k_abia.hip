@@ -15,6 +15,17 @@
 //  3. forward: the second linear recursion
 //        a_i = Ad_i a_{i-1} + S_i qdd_i,  qdd_i = (u_i - h_i^T Ad_i a_{i-1}) / D_i,
 // which together apply M^-1 to tau_delta (zero velocity, no gravity).
+//
+// Branched robots (trees; the paper treats serial chains): link i takes its
+// parent p(i)'s velocity and accelerations instead of link i-1's, and hands
+// its backward-sweep terms (F, p and Jh - h h^T / D, moved into p(i)'s frame)
+// to p(i), where the terms of all children add up. A child whose parent is
+// i - 1 still passes them in registers; only branch points go through the
+// workspace: in sweep 1 a branch point stores its velocity and bias
+// acceleration for its other children, in sweep 2 those children sum their
+// terms into its accumulator (the highest-numbered child writes, the others
+// add: children are swept before their parent), and in sweep 3 it stores its
+// acceleration. The model's tree codes say which case each link is.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -23,10 +34,20 @@
 namespace fdk {
 
 constexpr int ABIA_WS_FIELDS = 7;   // sweep 1: f (6); sweep 2 overwrites: h / D (6), u / D (1)
+// Trees add a branch-point record after those 7 fields: sweep 1 velocity (6)
+// and bias acceleration (6); sweep 2 accumulator of the children's F (6), p (6)
+// and Jh - h h^T / D (21, upper triangle by rows); sweep 3 acceleration (6).
+constexpr int ABIA_WB = ABIA_WS_FIELDS;
+constexpr int ABIA_TREE_WS_FIELDS = ABIA_WS_FIELDS + 33;
 
-size_t abia_workspace_elems(int batch, int nmax) {
+template <bool TREE> constexpr int abia_fields() { return TREE ? ABIA_TREE_WS_FIELDS : ABIA_WS_FIELDS; }
+// Branch-point records are read back soon after they are written, so they
+// keep the default cache policy even when the rest of the workspace streams.
+constexpr bool ABIA_BRANCH_NT = false;
+
+size_t abia_workspace_elems(int batch, int nmax, bool tree) {
     size_t blocks = (size_t)(batch + 63) / 64;
-    return blocks * (size_t)nmax * ABIA_WS_FIELDS * 64;
+    return blocks * (size_t)nmax * (tree ? ABIA_TREE_WS_FIELDS : ABIA_WS_FIELDS) * 64;
 }
 
 // Model reads go through the robot-interleaved copy: lanes hold consecutive
@@ -55,10 +76,10 @@ template <typename T> __device__ __forceinline__ void congruence_to_parent(const
     for (int r = 0; r < 6; ++r) wrench_to_parent(t, w + 6 * r, y + 6 * r);
 }
 
-// One chain on one lane. wsb: this lane's workspace column, field f of link i
-// at wsb[(i * ABIA_WS_FIELDS + f) * 64]. NT: model and workspace streamed with
-// non-temporal accesses (see ModelView::at_il).
-template <bool NT, typename T>
+// One chain (or tree) on one lane. wsb: this lane's workspace column, field f
+// of link i at wsb[(i * abia_fields<TREE>() + f) * 64]. NT: model and
+// workspace streamed with non-temporal accesses (see ModelView::at_il).
+template <bool NT, bool TREE, typename T>
 __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInfo& ci, const T* __restrict__ q,
                                            const T* __restrict__ qd, const T* __restrict__ tau,
                                            T* __restrict__ qdd, T* __restrict__ wsb) {
@@ -67,7 +88,7 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
         return;
     }
     const int n = ci.n;
-    auto wsp = [&](int i, int f) -> T* { return &wsb[((size_t)i * ABIA_WS_FIELDS + f) * 64]; };
+    auto wsp = [&](int i, int f) -> T* { return &wsb[((size_t)i * abia_fields<TREE>() + f) * 64]; };
 
     // sweep 1
     T v[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
@@ -75,6 +96,18 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
 #pragma unroll 2   // loads of two links in flight
     for (int i = 0; i < n; ++i) {
         const int64_t st = ci.state0 + i;
+        int32_t code = 0;
+        if constexpr (TREE) {
+            code = m.template tree_il<NT>(i, ci.slot);
+            if (!(code & TREE_CHAIN)) {                // the parent's terms, not link i-1's
+                const int p = tree_parent(code);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    v[c] = p < 0 ? T(0) : ld_ws<NT && ABIA_BRANCH_NT>(wsp(p, ABIA_WB + c));
+                    a[c] = p < 0 ? (c < 3 ? T(0) : -m.g[c - 3]) : ld_ws<NT && ABIA_BRANCH_NT>(wsp(p, ABIA_WB + 6 + c));
+                }
+            }
+        }
         const Pose<T> tl = link_pose_at<NT>(m, i, ci.slot, q[st]);
         const T qdi = qd[st];
         T t[6];
@@ -92,6 +125,15 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
         link_force(m.template inertia_il<NT>(i, ci.slot), v, a, f);
 #pragma unroll
         for (int c = 0; c < 6; ++c) st_ws<NT>(f[c], wsp(i, c));
+        if constexpr (TREE) {
+            if (code & TREE_BRANCH) {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    st_ws<NT && ABIA_BRANCH_NT>(v[c], wsp(i, ABIA_WB + c));
+                    st_ws<NT && ABIA_BRANCH_NT>(a[c], wsp(i, ABIA_WB + 6 + c));
+                }
+            }
+        }
     }
 
     // sweep 2
@@ -101,6 +143,7 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
 #pragma unroll
     for (int c = 0; c < 36; ++c) pi[c] = T(0);
     Pose<T> tn = pose_identity<T>();                   // T_{i,i+1}
+    bool carry = false;                                // trees: registers hold link i+1's terms for link i
 #pragma unroll 2   // loads of two links in flight
     for (int i = n - 1; i >= 0; --i) {
         const int64_t st = ci.state0 + i;
@@ -108,7 +151,8 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
 #pragma unroll
         for (int c = 0; c < 6; ++c) f[c] = ld_ws<NT>(wsp(i, c));
         inertia_to_mat6(m.template inertia_il<NT>(i, ci.slot), jh);
-        if (i + 1 < n) {
+        const int32_t code = TREE ? m.template tree_il<NT>(i, ci.slot) : 0;
+        if (TREE ? carry : i + 1 < n) {
             wrench_to_parent(tn, fc, fp);
             wrench_to_parent(tn, pc, pp);
             T y[36];
@@ -120,6 +164,24 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
         } else {
 #pragma unroll
             for (int c = 0; c < 6; ++c) pp[c] = T(0);
+        }
+        if constexpr (TREE) {
+            if (code & TREE_BRANCH) {                  // the other children's terms, summed
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    f[c] += ld_ws<NT && ABIA_BRANCH_NT>(wsp(i, ABIA_WB + c));
+                    pp[c] += ld_ws<NT && ABIA_BRANCH_NT>(wsp(i, ABIA_WB + 6 + c));
+                }
+                int k = ABIA_WB + 12;
+#pragma unroll
+                for (int r = 0; r < 6; ++r)
+#pragma unroll
+                    for (int c = r; c < 6; ++c, ++k) {
+                        const T y = ld_ws<NT && ABIA_BRANCH_NT>(wsp(i, k));
+                        jh[6 * r + c] += y;
+                        if (c != r) jh[6 * c + r] += y;
+                    }
+            }
         }
         const T td = tau[st] - f[2];
         const T dinv = rcp_refined(jh[14]);
@@ -140,6 +202,36 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
             fc[c] = f[c];
         }
         tn = link_pose_at<NT>(m, i, ci.slot, q[st]);
+        if constexpr (TREE) {
+            carry = (code & TREE_CHAIN) != 0;
+            const int p = tree_parent(code);
+            if (!carry && p >= 0) {                    // hand the terms to a branch point now
+                const bool first = (code & TREE_FIRST) != 0;
+                T x[6];
+                wrench_to_parent(tn, fc, x);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    T* d = wsp(p, ABIA_WB + c);
+                    st_ws<NT && ABIA_BRANCH_NT>(first ? x[c] : x[c] + ld_ws<NT && ABIA_BRANCH_NT>(d), d);
+                }
+                wrench_to_parent(tn, pc, x);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    T* d = wsp(p, ABIA_WB + 6 + c);
+                    st_ws<NT && ABIA_BRANCH_NT>(first ? x[c] : x[c] + ld_ws<NT && ABIA_BRANCH_NT>(d), d);
+                }
+                T y[36];
+                congruence_to_parent(tn, pi, y);
+                int k = ABIA_WB + 12;
+#pragma unroll
+                for (int r = 0; r < 6; ++r)
+#pragma unroll
+                    for (int c = r; c < 6; ++c, ++k) {
+                        T* d = wsp(p, k);
+                        st_ws<NT && ABIA_BRANCH_NT>(first ? y[6 * r + c] : y[6 * r + c] + ld_ws<NT && ABIA_BRANCH_NT>(d), d);
+                    }
+            }
+        }
     }
 
     // sweep 3
@@ -147,6 +239,15 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
 #pragma unroll 2   // loads of two links in flight
     for (int i = 0; i < n; ++i) {
         const int64_t st = ci.state0 + i;
+        int32_t code = 0;
+        if constexpr (TREE) {
+            code = m.template tree_il<NT>(i, ci.slot);
+            if (!(code & TREE_CHAIN)) {
+                const int p = tree_parent(code);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) acc[c] = p < 0 ? T(0) : ld_ws<NT && ABIA_BRANCH_NT>(wsp(p, ABIA_WB + c));
+            }
+        }
         const Pose<T> tl = link_pose_at<NT>(m, i, ci.slot, q[st]);
         T t[6];
         ad_inv_apply(tl, acc, t);
@@ -157,10 +258,16 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
 #pragma unroll
         for (int c = 0; c < 6; ++c) acc[c] = t[c];
         qdd[st] = x;
+        if constexpr (TREE) {
+            if (code & TREE_BRANCH) {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) st_ws<NT && ABIA_BRANCH_NT>(acc[c], wsp(i, ABIA_WB + c));
+            }
+        }
     }
 }
 
-template <typename T, bool NT>
+template <typename T, bool NT, bool TREE>
 __global__ __launch_bounds__(64) void k_abia(ModelView<T> m, ChainMap cm, int nmax, const T* __restrict__ q,
                                              const T* __restrict__ qd, const T* __restrict__ tau,
                                              T* __restrict__ qdd, T* __restrict__ ws) {
@@ -168,7 +275,8 @@ __global__ __launch_bounds__(64) void k_abia(ModelView<T> m, ChainMap cm, int nm
     const int b = blockIdx.x * 64 + lane;
     if (b >= cm.batch) return;
     // workspace: [block][link][field][lane]
-    abia_chain<NT>(m, chain_info(m, cm, b), q, qd, tau, qdd, ws + (size_t)blockIdx.x * nmax * ABIA_WS_FIELDS * 64 + lane);
+    abia_chain<NT, TREE>(m, chain_info(m, cm, b), q, qd, tau, qdd,
+                         ws + (size_t)blockIdx.x * nmax * abia_fields<TREE>() * 64 + lane);
 }
 
 // Persistent form for ragged batches: each wavefront takes 64-entry tiles of
@@ -177,7 +285,7 @@ __global__ __launch_bounds__(64) void k_abia(ModelView<T> m, ChainMap cm, int nm
 // lengths and the longest tiles go first. Entries at or past the batch are
 // skipped. Every wavefront leaves once a tile index runs past the list, so
 // the grid always drains.
-template <typename T, bool NT>
+template <typename T, bool NT, bool TREE>
 __global__ __launch_bounds__(64) void k_abia_persistent(ModelView<T> m, ChainMap cm, int nmax,
                                                         const int32_t* __restrict__ order, int32_t count,
                                                         int32_t* counter, const T* __restrict__ q,
@@ -185,7 +293,7 @@ __global__ __launch_bounds__(64) void k_abia_persistent(ModelView<T> m, ChainMap
                                                         T* __restrict__ qdd, T* __restrict__ ws) {
     __shared__ int tile_s;
     const int lane = threadIdx.x;
-    T* wsb = ws + (size_t)blockIdx.x * nmax * ABIA_WS_FIELDS * 64 + lane;
+    T* wsb = ws + (size_t)blockIdx.x * nmax * abia_fields<TREE>() * 64 + lane;
     for (;;) {
         if (lane == 0) tile_s = atomicAdd(counter, 1);
         __syncthreads();
@@ -194,7 +302,7 @@ __global__ __launch_bounds__(64) void k_abia_persistent(ModelView<T> m, ChainMap
         if ((int64_t)tile * 64 >= count) break;
         const int k = tile * 64 + lane;
         const int b = k < count ? (order ? order[k] : k) : cm.batch;
-        if (b < cm.batch) abia_chain<NT>(m, chain_info(m, cm, b), q, qd, tau, qdd, wsb);
+        if (b < cm.batch) abia_chain<NT, TREE>(m, chain_info(m, cm, b), q, qd, tau, qdd, wsb);
     }
 }
 
@@ -245,7 +353,9 @@ size_t persistent_plan_bytes(int batch) {
     return sizeof(int32_t) * ((size_t)batch + 2 * PLAN_BINS + 64);
 }
 
-size_t abia_persistent_workspace_elems(int grid, int nmax) { return (size_t)grid * nmax * ABIA_WS_FIELDS * 64; }
+size_t abia_persistent_workspace_elems(int grid, int nmax, bool tree) {
+    return (size_t)grid * nmax * (tree ? ABIA_TREE_WS_FIELDS : ABIA_WS_FIELDS) * 64;
+}
 
 // Three orders: with robot ids, the planning kernels sort the batch's chains
 // by decreasing length on the device; without, chain b is robot b, whose
@@ -274,12 +384,17 @@ hipError_t launch_abia_persistent(const ModelView<T>& m, const ChainMap& cm, int
         tiles = slot_robot;
         count = m.num_robots;
     }
-    if (stream_model)
-        hipLaunchKernelGGL((k_abia_persistent<T, true>), dim3(grid), dim3(64), 0, st, m, cm, nmax, tiles, count,
-                           counter, q, qd, tau, qdd, ws);
-    else
-        hipLaunchKernelGGL((k_abia_persistent<T, false>), dim3(grid), dim3(64), 0, st, m, cm, nmax, tiles, count,
-                           counter, q, qd, tau, qdd, ws);
+#define FDK_ABIA_PERSISTENT(NT, TREE)                                                                   \
+    hipLaunchKernelGGL((k_abia_persistent<T, NT, TREE>), dim3(grid), dim3(64), 0, st, m, cm, nmax, tiles, count, \
+                       counter, q, qd, tau, qdd, ws)
+    if (m.tree) {
+        if (stream_model) FDK_ABIA_PERSISTENT(true, true);
+        else FDK_ABIA_PERSISTENT(false, true);
+    } else {
+        if (stream_model) FDK_ABIA_PERSISTENT(true, false);
+        else FDK_ABIA_PERSISTENT(false, false);
+    }
+#undef FDK_ABIA_PERSISTENT
     return hipGetLastError();
 }
 
@@ -288,10 +403,13 @@ hipError_t launch_abia(const ModelView<T>& m, const ChainMap& cm, int nmax, cons
                        T* qdd, T* ws, bool stream_model, hipStream_t st) {
     if (cm.batch <= 0) return hipSuccess;
     const dim3 grid((cm.batch + 63) / 64);
-    if (stream_model)
-        hipLaunchKernelGGL((k_abia<T, true>), grid, dim3(64), 0, st, m, cm, nmax, q, qd, tau, qdd, ws);
-    else
-        hipLaunchKernelGGL((k_abia<T, false>), grid, dim3(64), 0, st, m, cm, nmax, q, qd, tau, qdd, ws);
+    if (m.tree) {
+        if (stream_model) hipLaunchKernelGGL((k_abia<T, true, true>), grid, dim3(64), 0, st, m, cm, nmax, q, qd, tau, qdd, ws);
+        else hipLaunchKernelGGL((k_abia<T, false, true>), grid, dim3(64), 0, st, m, cm, nmax, q, qd, tau, qdd, ws);
+    } else {
+        if (stream_model) hipLaunchKernelGGL((k_abia<T, true, false>), grid, dim3(64), 0, st, m, cm, nmax, q, qd, tau, qdd, ws);
+        else hipLaunchKernelGGL((k_abia<T, false, false>), grid, dim3(64), 0, st, m, cm, nmax, q, qd, tau, qdd, ws);
+    }
     return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@
 // coordinate directions. Joint coordinates, and therefore qdd, are unchanged:
 //   Rhome'_i = C_{i-1}^T Rhome_i C_i,  p'_i = C_{i-1}^T p_i,
 //   c'_i = C_i^T c_i,  Ic'_i = C_i^T Ic_i C_i,  C_0 = I (base frame kept).
+// On a tree, i-1 reads the parent p(i) (C = I for the base).
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -34,14 +35,15 @@ __device__ void canon_frame(const double* ax, double c[9]) {
 }
 
 template <typename T>
-__global__ void k_model_init(int64_t nl, const double* __restrict__ raw, const uint8_t* __restrict__ first,
+__global__ void k_model_init(int64_t nl, const double* __restrict__ raw, const int64_t* __restrict__ parent_link,
                              T* __restrict__ out) {
     int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= nl) return;
     const double* rl = raw + l * RAW_N;
     double ci[9], cp[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
     canon_frame(rl + RAW_AXIS, ci);
-    if (!first[l]) canon_frame(raw + (l - 1) * RAW_N + RAW_AXIS, cp);
+    const int64_t pl = parent_link[l];
+    if (pl >= 0) canon_frame(raw + pl * RAW_N + RAW_AXIS, cp);
     const double* rh = rl + RAW_HOME;
     // R' = Cp^T Rh Ci
     double t[9], rp[9];
@@ -115,14 +117,14 @@ hipError_t launch_model_interleave(int64_t nl, const int32_t* column, const int3
     return hipGetLastError();
 }
 
-hipError_t launch_model_init(int64_t nl, const double* raw, const uint8_t* first, void* out, int as_float,
+hipError_t launch_model_init(int64_t nl, const double* raw, const int64_t* parent_link, void* out, int as_float,
                              hipStream_t st) {
     if (nl <= 0) return hipSuccess;
     dim3 block(128), grid((unsigned)((nl + 127) / 128));
     if (as_float)
-        hipLaunchKernelGGL(k_model_init<float>, grid, block, 0, st, nl, raw, first, (float*)out);
+        hipLaunchKernelGGL(k_model_init<float>, grid, block, 0, st, nl, raw, parent_link, (float*)out);
     else
-        hipLaunchKernelGGL(k_model_init<double>, grid, block, 0, st, nl, raw, first, (double*)out);
+        hipLaunchKernelGGL(k_model_init<double>, grid, block, 0, st, nl, raw, parent_link, (double*)out);
     return hipGetLastError();
 }
 

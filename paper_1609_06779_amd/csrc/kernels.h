@@ -38,11 +38,11 @@ template <typename T> int jsiia_max_np();
 template <typename T>
 hipError_t launch_abia(const ModelView<T>& m, const ChainMap& cm, int nmax, const T* q, const T* qd,
                        const T* tau, T* qdd, T* ws, bool stream_model, hipStream_t st);
-size_t abia_workspace_elems(int batch, int nmax);
+size_t abia_workspace_elems(int batch, int nmax, bool tree);
 // ragged batches: one persistent launch over chains sorted by decreasing length
 // (slot_robot: robot of each interleaved column, used when cm has no robot ids)
 size_t persistent_plan_bytes(int batch);
-size_t abia_persistent_workspace_elems(int grid, int nmax);
+size_t abia_persistent_workspace_elems(int grid, int nmax, bool tree);
 template <typename T>
 hipError_t launch_abia_persistent(const ModelView<T>& m, const ChainMap& cm, int nmax, int grid, const T* q,
                                   const T* qd, const T* tau, T* qdd, T* ws, int32_t* plan,
@@ -67,7 +67,8 @@ hipError_t launch_btd6(int np, int segs, const int64_t* offsets, const T* d, con
                        T* x, int* status, hipStream_t st);
 
 // model upload: canonical joint frames from raw per-link parameters (fp64 in)
-hipError_t launch_model_init(int64_t nlinks, const double* raw, const uint8_t* first, void* out,
+// parent_link: the parent's link index in the same arrays, or -1 (the base)
+hipError_t launch_model_init(int64_t nlinks, const double* raw, const int64_t* parent_link, void* out,
                              int as_float, hipStream_t st);
 hipError_t launch_model_interleave(int64_t nlinks, const int32_t* column, const int32_t* index, int32_t num_robots,
                                    int64_t fstride, const void* soa, void* il, int as_float, hipStream_t st);

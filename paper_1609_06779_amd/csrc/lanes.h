@@ -80,6 +80,19 @@ template <typename T> __device__ __forceinline__ void inv_inertia_to_child(const
     o[9] = p[9];
 }
 
+// Branched robots (trees): link i hangs from link p(i) < i of its robot, or
+// from the base. Per link and robot column, an int32 code (interleaved like
+// `il`, [i * num_robots + column]) tells the lane-per-chain kernel where its
+// parent's terms are:
+//   bits 0..15   p(i) + 1 (0: the base);
+//   TREE_CHAIN   p(i) = i - 1: the parent's terms are still in registers;
+//   TREE_BRANCH  i has a child other than i + 1: its terms go through the
+//                workspace for that child;
+//   TREE_FIRST   the highest-numbered such child of p(i): the first to reach
+//                p(i)'s accumulator in the backward sweep, so it writes it.
+constexpr int32_t TREE_CHAIN = 1 << 16, TREE_BRANCH = 1 << 17, TREE_FIRST = 1 << 18;
+__device__ __forceinline__ int tree_parent(int32_t code) { return (code & 0xffff) - 1; }
+
 template <typename T> struct ModelView {
     const T* base;
     int64_t stride;               // total links of the model
@@ -96,6 +109,7 @@ template <typename T> struct ModelView {
     const T* il;
     int64_t il_fstride;
     const int32_t* slot;
+    const int32_t* tree;          // tree codes, or null when every robot is a serial chain
 
     __device__ __forceinline__ T at(int f, int64_t l) const { return base[f * stride + l]; }
     // NT: a non-temporal load, for launches whose model and workspace outgrow
@@ -103,6 +117,11 @@ template <typename T> struct ModelView {
     // push out the chain state the lane-per-chain kernels reuse across links.
     template <bool NT = false> __device__ __forceinline__ T at_il(int f, int i, int c) const {
         const T* p = &il[f * il_fstride + (int64_t)i * num_robots + c];
+        if constexpr (NT) return __builtin_nontemporal_load(p);
+        else return *p;
+    }
+    template <bool NT = false> __device__ __forceinline__ int32_t tree_il(int i, int c) const {
+        const int32_t* p = &tree[(int64_t)i * num_robots + c];
         if constexpr (NT) return __builtin_nontemporal_load(p);
         else return *p;
     }

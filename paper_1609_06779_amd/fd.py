@@ -56,7 +56,9 @@ class Model:
     """A robot set uploaded to the GPU in one precision ('f64' or 'f32').
 
     ``robots`` needs the per-link arrays n_links, axis, home_rot, offset, mass,
-    com, inertia and a gravity 3-vector (packed robot after robot).
+    com, inertia and a gravity 3-vector (packed robot after robot); an optional
+    ``parent`` array (parent of each link within its robot, -1 = base) makes
+    the robots branched. Branched models run the articulated-body algorithm only.
     """
 
     def __init__(self, robots, dtype: str = "f64", device=None):
@@ -70,6 +72,10 @@ class Model:
         self.n_links = _c(robots.n_links, np.int32)
         self._keep = dict(axis=_c(robots.axis), home=_c(robots.home_rot), off=_c(robots.offset),
                           mass=_c(robots.mass), com=_c(robots.com), inertia=_c(robots.inertia))
+        par = getattr(robots, "parent", None)
+        self._keep["parent"] = None if par is None else _c(par, np.int32)
+        starts = np.repeat(np.cumsum(self.n_links, dtype=np.int64) - self.n_links, self.n_links)
+        self.branched = par is not None and bool(np.any(np.asarray(par) != np.arange(len(par)) - starts - 1))
         d = _lib.ModelDesc()
         dp = ctypes.POINTER(ctypes.c_double)
         d.num_robots = len(self.n_links)
@@ -80,6 +86,8 @@ class Model:
         d.mass = self._keep["mass"].ctypes.data_as(dp)
         d.com = self._keep["com"].ctypes.data_as(dp)
         d.inertia = self._keep["inertia"].ctypes.data_as(dp)
+        if self._keep["parent"] is not None:
+            d.parent = self._keep["parent"].ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         for k in range(3):
             d.gravity[k] = float(robots.gravity[k])
         handle = ctypes.c_void_p()

@@ -188,6 +188,8 @@ class GpuExecutor(Executor):
         self.streams = [torch.cuda.Stream(device=model.device) for _ in range(streams)]   # default priority
         self.turn = 0
         self.esz = 8 if model.dtype == "f64" else 4
+        # ABIA workspace values per link and lane: 7, plus a 33-value branch-point record on trees
+        self.abia_fields = 40 if getattr(model, "branched", False) else 7
 
     def _groups(self, reqs):
         groups = collections.OrderedDict()
@@ -204,7 +206,7 @@ class GpuExecutor(Executor):
             chains = sum(r.chains for r in grp)
             links = sum(r.chains * r.n for r in grp)
             nmax = max(r.n for r in grp)
-            ws = ((chains + 63) // 64) * nmax * 7 * 64 * self.esz if algo == "abia" else 0
+            ws = ((chains + 63) // 64) * nmax * self.abia_fields * 64 * self.esz if algo == "abia" else 0
             total += 4 * links * self.esz + 12 * chains + 8 + ws
         return total
 

@@ -176,10 +176,19 @@ def make_tree_parents(n_links, p_extend: float = 0.85, seed: int = ROOT_SEED, cf
 
 
 def make_tree_robots(n_links, p_extend: float = 0.85, seed: int = ROOT_SEED, cfg: int = 0,
-                     random_home: bool = False) -> Robots:
-    """Random branched robots: ``make_robots`` parameters plus ``make_tree_parents`` topology."""
+                     random_home: bool = False, shared_topology: bool = False) -> Robots:
+    """Random branched robots: ``make_robots`` parameters plus ``make_tree_parents``
+    topology (one topology drawn once and given to every robot when
+    ``shared_topology``; the robots must then have equal lengths)."""
     rb = make_robots(n_links, seed=seed, cfg=cfg, random_home=random_home)
-    rb.parent = make_tree_parents(n_links, p_extend=p_extend, seed=seed, cfg=cfg)
+    n_links = np.asarray(n_links, dtype=np.int32)
+    if shared_topology:
+        if len(n_links) and np.any(n_links != n_links[0]):
+            raise ValueError("a shared topology needs robots of equal length")
+        one = make_tree_parents(n_links[:1], p_extend=p_extend, seed=seed, cfg=cfg)
+        rb.parent = np.tile(one, len(n_links))
+    else:
+        rb.parent = make_tree_parents(n_links, p_extend=p_extend, seed=seed, cfg=cfg)
     return rb
 
 
@@ -211,6 +220,7 @@ WORKLOADS = {
     "uniform-n64-b65536": dict(batch=65536, n=64, cfg=2),
     "uniform-n128-b65536": dict(batch=65536, n=128, cfg=2),
     "tree-n64-b65536": dict(batch=65536, n=64, cfg=5, p_extend=0.85),
+    "tree-shared-n64-b65536": dict(batch=65536, n=64, cfg=5, p_extend=0.85, shared_topology=True),
 }
 
 

@@ -83,6 +83,20 @@ def test_init_rejects_invalid_models(lib, mutate):
     assert not out.value
 
 
+@pytest.mark.parametrize("parents", [[0, 0, 1], [-1, 1, 0], [-1, 0, -2], [-1, 0, 3]])
+def test_init_rejects_invalid_parents(lib, parents):
+    """A parent must be an earlier link of the same robot, or the base (-1)."""
+    rb = synth.make_robots([3, 2], seed=5)
+    keep = []
+    d, arrs = _desc(rb, keep)
+    par = np.array(parents + [-1, 0], np.int32)
+    keep.append(par)
+    d.parent = par.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    out = ctypes.c_void_p()
+    assert lib.fd_init(ctypes.byref(d), 0, ctypes.byref(out)) == _lib.FD_ERR_INVALID_ARG
+    assert not out.value
+
+
 def test_null_arguments(lib):
     out = ctypes.c_void_p()
     assert lib.fd_init(None, 0, ctypes.byref(out)) == _lib.FD_ERR_INVALID_ARG
