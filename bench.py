@@ -162,7 +162,8 @@ def summarize_trace(trace_dir: str, workload: str, commands, summary_cmd: str, b
                 events = {a: v["ms_per_launch"] * 1e3 for a, v in rec.get("per_algo", {}).items()}
                 trees = rec.get("trees", {})
                 if not events and len(trees) == 1:      # a run of one tree workload alone
-                    events = {"abia": next(iter(trees.values()))["ms_per_launch"] * 1e3}
+                    events = {a: v["ms_per_launch"] * 1e3 for a, v in next(iter(trees.values())).items()
+                              if isinstance(v, dict)}
 
     files = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
     if not files:
@@ -321,7 +322,7 @@ TREE_WORKLOADS = ("tree-shared-n64-b65536", "tree-n64-b65536")
 
 
 def tree_leg(dtype: str, reps: int = 10, keys=TREE_WORKLOADS):
-    """Branched robots, one articulated-body launch over 65536 trees of 64 links
+    """Branched robots, one launch (ABIA, then JSIIA) over 65536 trees of 64 links
     (depth-first numbered; each link extends the previous one with probability
     0.85, else hangs from a random link of the current path). Two topology
     mixes: one topology shared by every robot (each with its own parameters),
@@ -347,26 +348,31 @@ def tree_leg(dtype: str, reps: int = 10, keys=TREE_WORKLOADS):
         model = fd.Model(rb, dtype, device=dev)
         tq, tqd, ttau = (torch.from_numpy(a).to(dev, tdt) for a in (q, qd, tau))
         res = torch.empty_like(tq)
-        ws = model.workspace(batch, "abia")
         stream = torch.cuda.current_stream()
-        model.forward(tq, tqd, ttau, batch=batch, algo="abia", out=res, workspace=ws, stream=stream)
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        for _ in range(reps):
-            model.forward(tq, tqd, ttau, batch=batch, algo="abia", out=res, workspace=ws, stream=stream)
-        b.record(stream)
-        torch.cuda.synchronize()
-        ms = a.elapsed_time(b) / reps
-        assert torch.isfinite(res).all().item(), f"{key}: tree ABIA produced non-finite qdd"
         par = rb.parents().reshape(batch, n)
         branch_points = float(np.mean([(np.bincount(p[p >= 0], minlength=n) > 1).sum() for p in par[:1024]]))
         algo_bytes = batch * n * ((4 + 22) * esz + 4)       # state, the model's 22 fields and one tree code
-        out[key] = {"ms_per_launch": ms, "solves_per_s": batch / (ms * 1e-3),
-                    "branch_points_per_tree": branch_points, "algorithmic_bytes": algo_bytes,
-                    "algorithmic_gb_per_s": algo_bytes / (ms * 1e-3) / 1e9}
+        entry = {"branch_points_per_tree": branch_points}
+        for algo in ("abia", "jsiia"):
+            ws = model.workspace(batch, algo)
+            model.forward(tq, tqd, ttau, batch=batch, algo=algo, out=res, workspace=ws, stream=stream)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                model.forward(tq, tqd, ttau, batch=batch, algo=algo, out=res, workspace=ws, stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / reps
+            assert torch.isfinite(res).all().item(), f"{key}: tree {algo} produced non-finite qdd"
+            entry[algo] = {"ms_per_launch": ms, "solves_per_s": batch / (ms * 1e-3)}
+            if algo == "abia":
+                entry[algo].update({"algorithmic_bytes": algo_bytes,
+                                    "algorithmic_gb_per_s": algo_bytes / (ms * 1e-3) / 1e9})
+            del ws
+        out[key] = entry
         model.close()
-        del model, tq, tqd, ttau, res, ws
+        del model, tq, tqd, ttau, res
         torch.cuda.empty_cache()
     return out
 

@@ -19,10 +19,13 @@
  * Twists are (w; v), wrenches (n; f). Link frame i sits on joint i's axis; its
  * pose in frame i-1 is T_{i-1,i}(q_i) = (Rhome_i Rot(axis_i, q_i), offset_i).
  * Branched robots (trees, beyond the paper's serial chains) name a parent per
- * link, and i-1 above reads that parent; only the articulated-body algorithm
- * takes them (fd_forward with FD_ALGO_ABIA or FD_ALGO_AUTO, and
- * fd_forward_persistent); the other entry points return FD_ERR_UNSUPPORTED for
- * a model that holds one.
+ * link, and i-1 above reads that parent. The articulated-body algorithm takes
+ * any numbering with parents before children (fd_forward with FD_ALGO_ABIA,
+ * fd_forward_persistent). The lane-per-link paths (FD_ALGO_JSIIA, fd_inverse,
+ * fd_joint_inertia) need the links of each robot numbered depth-first, so
+ * that every subtree is a run of consecutive links. The CFA and fd_backward
+ * take serial chains only. A path that does not take the model returns
+ * FD_ERR_UNSUPPORTED; FD_ALGO_AUTO picks one that does.
  * Gravity acts as a base acceleration (the "const." terms of eq. (EOM-full));
  * there is no force at the end effector. SI units, angles in radians.
  *
@@ -103,7 +106,7 @@ fd_status_t fd_init(const fd_model_desc_t* desc, fd_dtype_t dtype, fd_model_t** 
 void fd_destroy(fd_model_t* model);
 fd_dtype_t fd_model_dtype(const fd_model_t* model);
 /* Longest chain any algorithm of this build takes for the model's precision (JSIIA may be lower;
- * 0 for JSIIA and CFA when the model holds a branched robot). */
+ * 0 for an algorithm that does not take the model's branched robots). */
 int32_t fd_max_links(const fd_model_t* model, fd_algo_t algo);
 
 /* Bytes of workspace fd_forward needs for this batch and algorithm (0 if none). */

@@ -28,6 +28,7 @@ struct fd_model {
     int32_t* d_slot = nullptr;        // [num_robots] column of each robot in d_il
     int32_t* d_slot_robot = nullptr;  // [num_robots] robot of each column
     bool tree = false;                // some robot is branched (a link's parent is not link i-1)
+    bool depth_first = true;          // every robot's links are numbered depth-first (subtrees are runs)
     int32_t* d_tree = nullptr;        // [nmax][num_robots] tree codes (see lanes.h), null without branches
 };
 
@@ -148,11 +149,13 @@ int log2_bucket(int batch) {
 }
 
 fd_algo_t pick_algo(const fd_model* m, int nmax, int batch) {
-    if (m->tree) return FD_ALGO_ABIA;   // the only algorithm built for branched robots
     const std::vector<int8_t>& t = g_auto[m->dtype == FD_F64 ? 0 : 1];
-    if (!t.empty() && nmax >= 1 && nmax <= kMaxLinks) return (fd_algo_t)t[nmax * 21 + log2_bucket(batch)];
     // built-in rule: one lane per chain wins once the batch fills the GPU
-    return FD_ALGO_ABIA;
+    fd_algo_t a = FD_ALGO_ABIA;
+    if (!t.empty() && nmax >= 1 && nmax <= kMaxLinks) a = (fd_algo_t)t[nmax * 21 + log2_bucket(batch)];
+    // branched robots: the CFA is built for serial chains, JSIIA for depth-first numbering
+    if (m->tree && (a == FD_ALGO_CFA || (a == FD_ALGO_JSIIA && !m->depth_first))) a = FD_ALGO_ABIA;
+    return a;
 }
 
 template <typename T>
@@ -172,7 +175,7 @@ fd_status_t forward_t(const fd_model* m, const BatchPlan& p, const void* q, cons
                                                 stream_model(m, p.cm.batch, p.nmax), st));
         }
         case FD_ALGO_JSIIA:
-            if (m->tree || np > fdk::jsiia_max_np<T>()) return FD_ERR_UNSUPPORTED;
+            if ((m->tree && !m->depth_first) || np > fdk::jsiia_max_np<T>()) return FD_ERR_UNSUPPORTED;
             return from_hip(fdk::launch_jsiia<T>(np, v, p.cm, tq, tqd, tt, out, nullptr, st));
         case FD_ALGO_CFA:
             if (m->tree) return FD_ERR_UNSUPPORTED;
@@ -208,20 +211,28 @@ fd_status_t fd_init(const fd_model_desc_t* d, fd_dtype_t dtype, fd_model_t** out
     } catch (const std::bad_alloc&) {
         return FD_ERR_OUT_OF_MEMORY;
     }
-    // topology: parent links and the tree codes of the lane-per-chain kernel
-    bool tree = false;
+    // topology: parent links and the tree codes (lanes.h)
+    bool tree = false, depth_first = true;
     for (int64_t r = 0, s0 = 0; r < d->num_robots; s0 += d->n_links[r], ++r) {
         const int n = d->n_links[r];
+        std::vector<int> par(n), size(n, 1);
         for (int i = 0; i < n; ++i) {
             const int p = d->parent ? d->parent[s0 + i] : i - 1;
             if (p < -1 || p >= i) return FD_ERR_INVALID_ARG;
+            par[i] = p;
             parent_link[s0 + i] = p >= 0 ? s0 + p : -1;
-            code[s0 + i] = (p + 1) | (p >= 0 && p == i - 1 ? fdk::TREE_CHAIN : 0);
             tree = tree || p != i - 1;
+            // depth-first numbering: the parent of i is i - 1 or one of its ancestors
+            int k = i - 1;
+            while (k >= 0 && k != p) k = par[k];
+            depth_first = depth_first && k == p;
         }
+        for (int i = n - 1; i >= 1; --i)
+            if (par[i] >= 0) size[par[i]] += size[i];
         std::vector<uint8_t> reached(n, 0);
         for (int i = n - 1; i >= 0; --i) {   // children before parents, as in the backward sweep
-            const int p = parent_link[s0 + i] >= 0 ? (int)(parent_link[s0 + i] - s0) : -1;
+            const int p = par[i];
+            code[s0 + i] |= (p + 1) | ((i + size[i]) << 9) | (p >= 0 && p == i - 1 ? fdk::TREE_CHAIN : 0);
             if (p < 0 || p == i - 1) continue;
             code[s0 + p] |= fdk::TREE_BRANCH;
             if (!reached[p]) code[s0 + i] |= fdk::TREE_FIRST;
@@ -265,6 +276,7 @@ fd_status_t fd_init(const fd_model_desc_t* d, fd_dtype_t dtype, fd_model_t** out
     m->nmax = mx;
     m->uniform = uni;
     m->tree = tree;
+    m->depth_first = depth_first;
     for (int k = 0; k < 3; ++k) m->g[k] = d->gravity[k];
     // interleaved columns: robots by decreasing length, ties in robot order, so a
     // model of equal lengths keeps its order and 64 consecutive columns hold
@@ -356,7 +368,7 @@ fd_dtype_t fd_model_dtype(const fd_model_t* m) { return m ? m->dtype : FD_F64; }
 
 int32_t fd_max_links(const fd_model_t* m, fd_algo_t algo) {
     if (!m) return 0;
-    if (m->tree && (algo == FD_ALGO_JSIIA || algo == FD_ALGO_CFA)) return 0;
+    if (m->tree && (algo == FD_ALGO_CFA || (algo == FD_ALGO_JSIIA && !m->depth_first))) return 0;
     if (algo == FD_ALGO_JSIIA) return m->dtype == FD_F64 ? fdk::jsiia_max_np<double>() : fdk::jsiia_max_np<float>();
     return kMaxLinks;
 }
@@ -498,7 +510,7 @@ fd_status_t fd_inverse(const fd_model_t* m, const fd_batch_t* b, const void* q, 
     BatchPlan p;
     fd_status_t s = plan_batch(m, b, &p);
     if (s != FD_OK) return s;
-    if (m->tree) return FD_ERR_UNSUPPORTED;
+    if (m->tree && !m->depth_first) return FD_ERR_UNSUPPORTED;
     if (b->batch == 0) return FD_OK;
     if (!q || !qd || !tau) return FD_ERR_INVALID_ARG;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
@@ -514,7 +526,7 @@ fd_status_t fd_joint_inertia(const fd_model_t* m, const fd_batch_t* b, const voi
     BatchPlan p;
     fd_status_t s = plan_batch(m, b, &p);
     if (s != FD_OK) return s;
-    if (m->tree) return FD_ERR_UNSUPPORTED;
+    if (m->tree && !m->depth_first) return FD_ERR_UNSUPPORTED;
     if (b->offsets != nullptr) return FD_ERR_INVALID_ARG;
     if (b->batch == 0) return FD_OK;
     if (!q || !m_out) return FD_ERR_INVALID_ARG;

@@ -20,7 +20,9 @@
 namespace fdk {
 
 // Gauss-Jordan on register rows (NP <= 64: one wavefront holds 64 / NP chains).
-template <typename T, int NP>
+// TREE: branched robots numbered depth-first; M_ik is zero for links on
+// different branches (neither is an ancestor of the other).
+template <typename T, int NP, bool TREE>
 __global__ __launch_bounds__(64) void k_jsiia_gj(ModelView<T> m, ChainMap cm, const T* __restrict__ q,
                                                   const T* __restrict__ qd, const T* __restrict__ tau,
                                                   T* __restrict__ qdd, int* __restrict__ status) {
@@ -38,17 +40,21 @@ __global__ __launch_bounds__(64) void k_jsiia_gj(ModelView<T> m, ChainMap cm, co
     const int64_t link = ci.link0 + li;
     T qi = active ? q[st] : T(0), qdi = active ? qd[st] : T(0), ti = active ? tau[st] : T(0);
 
+    const int32_t code = TREE && active ? m.tree_il(li, ci.slot) : 0;
     LinkLane<T> k;
-    const T tb = rnea_lane<T, NP>(m, link, active, qi, qdi, T(0), true, li, nullptr, k);
+    const T tb = rnea_lane<T, NP, TREE>(m, link, active, qi, qdi, T(0), true, li, nullptr, k, code);
     T y = active ? ti - tb : T(0);
     T f[6];
-    composite_force<T, NP>(k, active, li, nullptr, f);
+    composite_force<T, NP, TREE>(k, active, li, nullptr, f, code);
     T* my = sf + grp * NP * 12;
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
         my[c * NP + li] = k.s[c];
         my[(6 + c) * NP + li] = f[c];
     }
+    // trees: the links coupled to li are its ancestors (bits) and its subtree (below end)
+    const uint32_t anc_bits = TREE ? tree_ancestors<NP>(active ? tree_parent(code) : -1, li) : 0u;
+    const int end = TREE && active ? tree_end(code) : NP;
     block_sync<64>();
     // row li of M: M_ik = s_min(i,k) . F_max(i,k); padding rows/columns are the identity
     T row[NP];
@@ -61,6 +67,10 @@ __global__ __launch_bounds__(64) void k_jsiia_gj(ModelView<T> m, ChainMap cm, co
             up += k.s[c] * my[(6 + c) * NP + kk];
         }
         T v = kk <= li ? lo : up;
+        if constexpr (TREE) {
+            const bool related = kk <= li ? ((anc_bits >> kk) & 1u) != 0 : kk < end;
+            v = related ? v : T(0);
+        }
         row[kk] = (active && kk < n) ? v : (kk == li ? T(1) : T(0));
     }
     T diag = T(1);
@@ -103,7 +113,7 @@ __global__ __launch_bounds__(64) void k_jsiia_gj(ModelView<T> m, ChainMap cm, co
 //  * back substitution L^T x = D^-1 b by blocks of G rows (below).
 // Blocks outside the trailing part are skipped at compile time. The inverse
 // dynamics before it runs lane per link on all TH = G * G lanes.
-template <typename T, int NP>
+template <typename T, int NP, bool TREE>
 __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> m, ChainMap cm,
                                                                     const T* __restrict__ q,
                                                                     const T* __restrict__ qd,
@@ -113,7 +123,8 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> 
     constexpr int TH = G * G;
     static_assert(TH >= NP, "the lane grid must cover one lane per link");
     __shared__ T xbuf[TH > 64 ? 10 * TH : 1];   // cross-wavefront scan exchange
-    __shared__ T sf[NP * 13];                   // s (6), F (6), tau_delta per link
+    constexpr int SF = TREE ? 14 : 13;
+    __shared__ T sf[NP * SF];                   // s (6), F (6), tau_delta, subtree end (trees) per link
     __shared__ T col[2][NP + 2];                // column j (zero at rows <= j), b_j, m_jj
     const int li = threadIdx.x;
     ChainInfo ci{0, 0, 0, 0, 0};
@@ -123,10 +134,11 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> 
     const int64_t st = ci.state0 + li;
     T qi = active ? q[st] : T(0), qdi = active ? qd[st] : T(0), ti = active ? tau[st] : T(0);
 
+    const int32_t code = TREE && active ? m.tree_il(li, ci.slot) : 0;
     LinkLane<T> k;
-    const T tb = rnea_lane<T, TH>(m, ci.link0 + li, active, qi, qdi, T(0), true, li, xbuf, k);
+    const T tb = rnea_lane<T, TH, TREE>(m, ci.link0 + li, active, qi, qdi, T(0), true, li, xbuf, k, code);
     T f6[6];
-    composite_force<T, TH>(k, active, li, xbuf, f6);
+    composite_force<T, TH, TREE>(k, active, li, xbuf, f6, code);
     if (li < NP) {
 #pragma unroll
         for (int e = 0; e < 6; ++e) {
@@ -134,6 +146,7 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> 
             sf[(6 + e) * NP + li] = f6[e];
         }
         sf[12 * NP + li] = active ? ti - tb : T(0);
+        if constexpr (TREE) sf[13 * NP + li] = T(tree_end(code));
     }
     block_sync<TH>();
 
@@ -153,6 +166,7 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> 
             T v = T(0);
 #pragma unroll
             for (int e = 0; e < 6; ++e) v += sf[e * NP + kk] * fi[e];   // k <= i: s_k . F_i
+            if constexpr (TREE) v = i < int(sf[13 * NP + kk]) ? v : T(0);   // k an ancestor of i
             mb[a * (a + 1) / 2 + bb] = (i < n && kk < n) ? v : (i == kk ? T(1) : T(0));
         }
     }
@@ -253,12 +267,20 @@ template <typename T>
 hipError_t launch_jsiia(int np, const ModelView<T>& m, const ChainMap& cm, const T* q, const T* qd, const T* tau,
                         T* qdd, int* status, hipStream_t st) {
     if (cm.batch <= 0) return hipSuccess;
-#define GJ(P)                                                                                        \
-    hipLaunchKernelGGL((k_jsiia_gj<T, P>), dim3((cm.batch + Geo<P>::chains - 1) / Geo<P>::chains),  \
-                       dim3(64), 0, st, m, cm, q, qd, tau, qdd, status)
-#define GJ2D(P)                                                                                      \
-    hipLaunchKernelGGL((k_jsiia_ldl<T, P>), dim3(cm.batch), dim3((P / 8) * (P / 8)), 0, st, m, cm, q, qd, tau, \
-                       qdd, status)
+#define GJ(P)                                                                                            \
+    if (m.tree)                                                                                          \
+        hipLaunchKernelGGL((k_jsiia_gj<T, P, true>), dim3((cm.batch + Geo<P>::chains - 1) / Geo<P>::chains), \
+                           dim3(64), 0, st, m, cm, q, qd, tau, qdd, status);                            \
+    else                                                                                                 \
+        hipLaunchKernelGGL((k_jsiia_gj<T, P, false>), dim3((cm.batch + Geo<P>::chains - 1) / Geo<P>::chains), \
+                           dim3(64), 0, st, m, cm, q, qd, tau, qdd, status)
+#define GJ2D(P)                                                                                          \
+    if (m.tree)                                                                                          \
+        hipLaunchKernelGGL((k_jsiia_ldl<T, P, true>), dim3(cm.batch), dim3((P / 8) * (P / 8)), 0, st, m, cm, q, \
+                           qd, tau, qdd, status);                                                        \
+    else                                                                                                 \
+        hipLaunchKernelGGL((k_jsiia_ldl<T, P, false>), dim3(cm.batch), dim3((P / 8) * (P / 8)), 0, st, m, cm, q, \
+                           qd, tau, qdd, status)
     switch (np) {
         case 8: GJ(8); break;
         case 16: GJ(16); break;

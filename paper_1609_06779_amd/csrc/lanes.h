@@ -82,16 +82,20 @@ template <typename T> __device__ __forceinline__ void inv_inertia_to_child(const
 
 // Branched robots (trees): link i hangs from link p(i) < i of its robot, or
 // from the base. Per link and robot column, an int32 code (interleaved like
-// `il`, [i * num_robots + column]) tells the lane-per-chain kernel where its
-// parent's terms are:
-//   bits 0..15   p(i) + 1 (0: the base);
-//   TREE_CHAIN   p(i) = i - 1: the parent's terms are still in registers;
+// `il`, [i * num_robots + column]) describes the link's place in the tree:
+//   bits 0..8    p(i) + 1 (0: the base);
+//   bits 9..17   one past the last link of i's subtree, when the robot's
+//                links are numbered depth-first (its subtree is then the run
+//                i .. end - 1; the lane-per-link kernels need that order);
+//   TREE_CHAIN   p(i) = i - 1: the lane-per-chain kernel still has the
+//                parent's terms in registers;
 //   TREE_BRANCH  i has a child other than i + 1: its terms go through the
 //                workspace for that child;
 //   TREE_FIRST   the highest-numbered such child of p(i): the first to reach
 //                p(i)'s accumulator in the backward sweep, so it writes it.
-constexpr int32_t TREE_CHAIN = 1 << 16, TREE_BRANCH = 1 << 17, TREE_FIRST = 1 << 18;
-__device__ __forceinline__ int tree_parent(int32_t code) { return (code & 0xffff) - 1; }
+constexpr int32_t TREE_CHAIN = 1 << 24, TREE_BRANCH = 1 << 25, TREE_FIRST = 1 << 26;
+__host__ __device__ __forceinline__ int tree_parent(int32_t code) { return (code & 0x1ff) - 1; }
+__host__ __device__ __forceinline__ int tree_end(int32_t code) { return (code >> 9) & 0x1ff; }
 
 template <typename T> struct ModelView {
     const T* base;
@@ -474,6 +478,126 @@ __device__ __forceinline__ void scan_add_rev(T* x, int li, T* lds) {
             for (int c = 0; c < K; ++c) x[c] += lds[K * k + c];
         }
         __syncthreads();
+    }
+}
+
+// ---------------- tree scans (branched robots, links in depth-first order) ----------------
+// The chain scans above combine lane li with lane li - s. On a tree the
+// prefix of link i runs over its root path instead, and the suffix over its
+// subtree. Root-path scans use pointer jumping: every lane keeps the
+// combination over the links from its current pointer (exclusive) down to
+// itself, then takes its pointer's combination and its pointer's pointer, so
+// after log2(NP) rounds every pointer has reached the base. Subtree sums, with
+// depth-first numbering, are differences of the group's suffix sums.
+
+// Lane src of this lane's group reads into out; src outside [0, NP) reads the
+// lane's own values. NP <= 64: ds_bpermute inside the wavefront; larger
+// groups go through LDS (lds: at least W * NP values). All lanes of the group
+// must call it.
+namespace xlane {
+__device__ __forceinline__ double bperm(double v, int addr) {
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float bperm(float v, int addr) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+__device__ __forceinline__ int bperm(int v, int addr) { return __builtin_amdgcn_ds_bpermute(addr, v); }
+}  // namespace xlane
+
+template <int NP, int W, typename T>
+__device__ __forceinline__ void group_gather(const T* v, T* out, int src, int li, T* lds) {
+    const bool ok = src >= 0 && src < NP;
+    if constexpr (NP <= 64) {
+        const int lane = threadIdx.x & 63;
+        const int addr = 4 * (ok ? (lane & ~(NP - 1)) + src : lane);
+#pragma unroll
+        for (int w = 0; w < W; ++w) out[w] = xlane::bperm(v[w], addr);
+    } else {
+        __syncthreads();                       // earlier readers of lds are done
+#pragma unroll
+        for (int w = 0; w < W; ++w) lds[w * NP + li] = v[w];
+        __syncthreads();
+        const int s = ok ? src : li;
+#pragma unroll
+        for (int w = 0; w < W; ++w) out[w] = lds[w * NP + s];
+    }
+}
+
+// Base-frame pose of every link: the product of the joint poses along its
+// root path (par: the lane of the link's parent, -1 for the base).
+template <int NP, typename T>
+__device__ __forceinline__ Pose<T> tree_scan_pose(Pose<T> x, int par, int li, T* lds) {
+    int anc = par;
+#pragma unroll 1   // rolled: the rounds need no compile-time index, and unrolled they crowd registers
+    for (int s = 1; s < NP; s <<= 1) {
+        Pose<T> o;
+        T pa[4] = {x.p[0], x.p[1], x.p[2], T(anc)}, po[4];
+        group_gather<NP, 9>(x.r, o.r, anc, li, lds);
+        group_gather<NP, 4>(pa, po, anc, li, lds);
+        if (anc >= 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) o.p[c] = po[c];
+            x = pose_mul(o, x);
+            anc = int(po[3]);
+        }
+    }
+    return x;
+}
+
+// Sum of K-vectors over every link's root path (inclusive).
+template <int NP, int K, typename T>
+__device__ __forceinline__ void tree_scan_add(T* x, int par, int li, T* lds) {
+    int anc = par;
+#pragma unroll 1
+    for (int s = 1; s < NP; s <<= 1) {
+        T v[K + 1], o[K + 1];
+#pragma unroll
+        for (int c = 0; c < K; ++c) v[c] = x[c];
+        v[K] = T(anc);
+        group_gather<NP, K + 1>(v, o, anc, li, lds);
+        if (anc >= 0) {
+#pragma unroll
+            for (int c = 0; c < K; ++c) x[c] += o[c];
+            anc = int(o[K]);
+        }
+    }
+}
+
+// Bit k set for every link k on the root path of li (li included), for groups
+// of at most 32 lanes: pointer jumping with OR, as above.
+template <int NP>
+__device__ __forceinline__ uint32_t tree_ancestors(int par, int li) {
+    static_assert(NP <= 32, "one bit per link of the group");
+    uint32_t bits = 1u << li;
+    int anc = par;
+    const int lane = threadIdx.x & 63;
+#pragma unroll 1
+    for (int s = 1; s < NP; s <<= 1) {
+        const int addr = 4 * (anc >= 0 ? (lane & ~(NP - 1)) + anc : lane);
+        const uint32_t ob = (uint32_t)xlane::bperm((int)bits, addr);
+        const int oa = xlane::bperm(anc, addr);
+        if (anc >= 0) {
+            bits |= ob;
+            anc = oa;
+        }
+    }
+    return bits;
+}
+
+// Sum of K-vectors over every link's subtree, links end - 1 .. li in
+// depth-first order: the suffix sum at li minus the suffix sum at end (zero
+// past the group; lanes past the chain hold zeros). The difference carries an
+// absolute error of a few units of roundoff of the suffix sum at li.
+template <int NP, int K, typename T>
+__device__ __forceinline__ void subtree_sum(T* x, int end, int li, T* lds) {
+    scan_add_rev<NP, K>(x, li, lds);
+    T o[K];
+    group_gather<NP, K>(x, o, end, li, lds);
+    if (end >= 0 && end < NP) {
+#pragma unroll
+        for (int c = 0; c < K; ++c) x[c] -= o[c];
     }
 }
 

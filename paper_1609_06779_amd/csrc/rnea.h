@@ -14,6 +14,11 @@
 // with s_i = Ad(G_i) e3 the joint screw in the base frame and (v_k, a_k) the
 // body-frame twist and acceleration. A_0 = (0; -g) puts gravity in as a base
 // acceleration (the "const." terms of eq. (EOM-full)).
+//
+// TREE: branched robots numbered depth-first (code: the link's tree code, see
+// lanes.h). The same sums run over each link's root path (k <= i above reads
+// "k on the path from the base to i") and its subtree (k >= i reads "k in the
+// subtree of i"), by the tree scans of lanes.h.
 #pragma once
 #include "lanes.h"
 
@@ -28,9 +33,11 @@ template <typename T> struct LinkLane {
 };
 
 // Returns tau_i = ID(q, qd, qdd)_i for active lanes. All lanes of the group must call it.
-template <typename T, int NP>
+template <typename T, int NP, bool TREE = false>
 __device__ __forceinline__ T rnea_lane(const ModelView<T>& m, int64_t link, bool active, T q, T qd,
-                                       T qdd, bool gravity, int li, T* xbuf, LinkLane<T>& k) {
+                                       T qdd, bool gravity, int li, T* xbuf, LinkLane<T>& k, int32_t code = 0) {
+    const int par = TREE && active ? tree_parent(code) : -1;
+    const int end = TREE && active ? tree_end(code) : NP;
     k.tl = pose_identity<T>();
     k.jb.m = T(0);
 #pragma unroll
@@ -46,7 +53,8 @@ __device__ __forceinline__ T rnea_lane(const ModelView<T>& m, int64_t link, bool
         qd = T(0);
         qdd = T(0);
     }
-    k.g = scan_pose<NP>(k.tl, li, xbuf);
+    if constexpr (TREE) k.g = tree_scan_pose<NP>(k.tl, par, li, xbuf);
+    else k.g = scan_pose<NP>(k.tl, li, xbuf);
     // s = Ad(G) e3 = (z; p x z), z = third column of R
     const T z[3] = {k.g.r[2], k.g.r[5], k.g.r[8]};
     T pz[3];
@@ -57,13 +65,15 @@ __device__ __forceinline__ T rnea_lane(const ModelView<T>& m, int64_t link, bool
     T sqd[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) { sqd[c] = k.s[c] * qd; k.v[c] = sqd[c]; }
-    scan_add<NP, 6>(k.v, li, xbuf);
+    if constexpr (TREE) tree_scan_add<NP, 6>(k.v, par, li, xbuf);
+    else scan_add<NP, 6>(k.v, li, xbuf);
 
     T a[6];
     ad_twist(k.v, sqd, a);
 #pragma unroll
     for (int c = 0; c < 6; ++c) a[c] += k.s[c] * qdd;
-    scan_add<NP, 6>(a, li, xbuf);
+    if constexpr (TREE) tree_scan_add<NP, 6>(a, par, li, xbuf);
+    else scan_add<NP, 6>(a, li, xbuf);
     if (gravity) {
         a[3] -= m.g[0];
         a[4] -= m.g[1];
@@ -79,7 +89,8 @@ __device__ __forceinline__ T rnea_lane(const ModelView<T>& m, int64_t link, bool
 #pragma unroll
         for (int c = 0; c < 6; ++c) fs[c] = T(0);
     }
-    scan_add_rev<NP, 6>(fs, li, xbuf);
+    if constexpr (TREE) subtree_sum<NP, 6>(fs, end, li, xbuf);
+    else scan_add_rev<NP, 6>(fs, li, xbuf);
     T tau = T(0);
 #pragma unroll
     for (int c = 0; c < 6; ++c) tau += k.s[c] * fs[c];
@@ -91,8 +102,11 @@ __device__ __forceinline__ T rnea_lane(const ModelView<T>& m, int64_t link, bool
 // with qdd = e_i, qd = 0 and no gravity, whose force recursion sums
 // J_k V^s_k = J_k s_i over k >= i (Sec. II-C), so
 //   M_ik = s_max(i,k)^T Ic_max(i,k) s_min(i,k).
-template <typename T, int NP>
-__device__ __forceinline__ void composite_force(const LinkLane<T>& k, bool active, int li, T* xbuf, T f[6]) {
+// TREE: the composite inertia of i's subtree; M_ik is that product when one
+// of i, k is an ancestor of the other, else zero (the caller masks it).
+template <typename T, int NP, bool TREE = false>
+__device__ __forceinline__ void composite_force(const LinkLane<T>& k, bool active, int li, T* xbuf, T f[6],
+                                                int32_t code = 0) {
     // base-frame inertia of the link: m, h^s = m (R c + p), Ibar^s = R Ibar R^T + m([Rc]^2 - [c^s]^2)
     T ic[10];
     if (active) {
@@ -130,7 +144,8 @@ __device__ __forceinline__ void composite_force(const LinkLane<T>& k, bool activ
 #pragma unroll
         for (int c = 0; c < 10; ++c) ic[c] = T(0);
     }
-    scan_add_rev<NP, 10>(ic, li, xbuf);
+    if constexpr (TREE) subtree_sum<NP, 10>(ic, active ? tree_end(code) : NP, li, xbuf);
+    else scan_add_rev<NP, 10>(ic, li, xbuf);
     Inertia<T> cj;
     cj.m = ic[0];
 #pragma unroll

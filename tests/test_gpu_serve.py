@@ -104,9 +104,10 @@ def test_rounds_with_several_algorithms_match_the_oracle(dev, mode):
         assert np.all(err <= bar), (r.rid, r.algo, r.n, (err / bar).max())
 
 
-def test_serving_branched_robots_runs_the_tree_kernel(dev):
-    """A model of branched robots: every request goes to the articulated-body
-    kernel whatever the tuned table says, and matches the oracle."""
+def test_serving_branched_robots_runs_the_tree_kernels(dev):
+    """A model of branched robots: requests the tuned table gives to the CFA
+    (serial chains only) go to the articulated-body kernel instead; every
+    request matches the oracle."""
     from paper_1609_06779_amd import fd, serve
 
     lengths = synth.ragged_lengths(16, 7, 120, seed=3, cfg=5)
@@ -117,12 +118,12 @@ def test_serving_branched_robots_runs_the_tree_kernel(dev):
     ex = serve.GpuExecutor(model, lengths, algo="auto", streams=2)
     stats = serve.Scheduler(ex, budget_bytes=64 << 20, max_inflight=2, idle=serve.spin_idle).run(reqs)
     assert stats.completed == 24 and stats.rejected == 0
-    assert {r.algo for r in reqs} == {"abia"}
+    assert "abia" in {r.algo for r in reqs} and {r.algo for r in reqs} <= {"abia", "jsiia"}
     for r in reqs[::3]:
         pick = np.unique(np.minimum([0, r.chains // 2, r.chains - 1], r.chains - 1))
         sub = robots.take(np.full(len(pick), r.robot))
         idx = np.concatenate([np.arange(r.n * b, r.n * b + r.n) for b in pick])
         q, qd, tau = (x.numpy()[idx] for x in (r.q, r.qd, r.tau))
         err = oracle.relative_error(r.out.numpy()[idx], oracle.fd(sub, q, qd, tau), sub.offsets)
-        bar = _bar("abia", sub, q, sub.offsets)
+        bar = _bar(r.algo, sub, q, sub.offsets)
         assert np.all(err <= bar), (r.rid, (err / bar).max())

@@ -1,11 +1,13 @@
-"""GPU parity on branched robots (trees): the articulated-body kernel's tree
-variant, through the C-ABI, against the oracle.
+"""GPU parity on branched robots (trees), through the C-ABI, against the oracle:
+the articulated-body kernel's tree variant (any parent order), and the
+lane-per-link kernels on trees numbered depth-first (JSIIA, inverse dynamics,
+the joint-space inertia), whose scans run over root paths and subtrees.
 
 A tree hangs link i from a parent p(i) < i (the paper treats serial chains).
-The bar is the one of the serial-chain parity tests for ABIA: a forward error
-of 1e-10 (FP64) or 1e-4 (FP32) where conditioning allows, else
-16 cond_2(M) u per chain, and a normwise backward error of at most 64 u.
-FP32 runs round robots and states to FP32 first.
+The bars are those of the serial-chain parity tests: a forward error of 1e-10
+(FP64) or 1e-4 (FP32) where conditioning allows, else 16 cond_2(M) u per chain;
+for ABIA also a normwise backward error of at most 64 u. FP32 runs round robots
+and states to FP32 first.
 """
 import numpy as np
 import pytest
@@ -48,7 +50,7 @@ def _t(a, dtype, dev):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64 if dtype == "f64" else np.float32)).to(dev)
 
 
-def _check(got, rb, q, qd, tau, off, dtype, what):
+def _check(got, rb, q, qd, tau, off, dtype, what, backward=True):
     ref = oracle.fd(rb, q, qd, tau, offsets=off)
     err = oracle.relative_error(got, ref, off)
     ms = oracle.crba(rb, q, offsets=off)
@@ -57,6 +59,8 @@ def _check(got, rb, q, qd, tau, off, dtype, what):
         bar = np.maximum(bar, COND_FACTOR * np.array([np.linalg.cond(m) for m in ms]) * U[dtype])
     bad = np.nonzero(~(err <= bar))[0]
     assert len(bad) == 0, f"{what}: {len(bad)} trees over the bar, worst {err.max():.3e} (tree {bad[:5]})"
+    if not backward:
+        return
     bias = oracle.rnea(rb, q, qd, offsets=off)
     for b, m in enumerate(ms):
         sl = slice(off[b], off[b + 1])
@@ -85,8 +89,8 @@ def test_tree_forward_uniform(fdm, dev, dtype, n):
     assert m.branched or n <= 2
     got = _forward(m, rb, q, qd, tau, dtype, dev)
     _check(got, rb, q, qd, tau, rb.offsets, dtype, f"tree n={n} {dtype}")
-    if m.branched:                                       # AUTO takes ABIA on a branched model
-        np.testing.assert_array_equal(_forward(m, rb, q, qd, tau, dtype, dev, algo="auto"), got)
+    auto = _forward(m, rb, q, qd, tau, dtype, dev, algo="auto")   # never the CFA on a branched model
+    _check(auto, rb, q, qd, tau, rb.offsets, dtype, f"tree n={n} {dtype} auto", backward=False)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -180,6 +184,7 @@ def test_explicit_serial_parents_take_the_chain_kernel(fdm, dev):
 
 
 def test_tree_model_rejects_the_chain_only_entry_points(fdm, dev):
+    """The CFA and the reverse mode are built for serial chains only."""
     from paper_1609_06779_amd import _lib
 
     lengths = [8] * 4
@@ -187,18 +192,117 @@ def test_tree_model_rejects_the_chain_only_entry_points(fdm, dev):
     m = fdm.Model(rb, "f64", device=dev)
     assert m.branched
     args = (_t(q, "f64", dev), _t(qd, "f64", dev), _t(tau, "f64", dev))
-    for algo in ("jsiia", "cfa"):
-        assert m.max_links(algo) == 0
-        with pytest.raises(_lib.FdError) as e:
-            m.forward(*args, batch=4, algo=algo)
-        assert e.value.status == _lib.FD_ERR_UNSUPPORTED
-    assert m.max_links("abia") == 256
-    for call in (lambda: m.inverse(args[0], args[1], None, batch=4),
-                 lambda: m.joint_inertia(args[0], batch=4, n=8),
-                 lambda: m.backward(args[0], args[1], args[2], args[2], batch=4)):
+    assert m.max_links("cfa") == 0
+    with pytest.raises(_lib.FdError) as e:
+        m.forward(*args, batch=4, algo="cfa")
+    assert e.value.status == _lib.FD_ERR_UNSUPPORTED
+    with pytest.raises(_lib.FdError) as e:
+        m.backward(args[0], args[1], args[2], args[2], batch=4)
+    assert e.value.status == _lib.FD_ERR_UNSUPPORTED
+    assert m.max_links("abia") == 256 and m.max_links("jsiia") == 128
+
+
+def _not_depth_first(n, count):
+    """Trees whose links are numbered parent-first but not depth-first: link i
+    hangs from link i - 2 (two interleaved branches from the base)."""
+    rb = synth.make_robots([n] * count, seed=21, cfg=5, random_home=True)
+    rb.parent = np.tile(np.arange(n, dtype=np.int32) - 2, count)
+    rb.parent[rb.parent < 0] = -1
+    return rb
+
+
+def test_parent_first_order_that_is_not_depth_first(fdm, dev):
+    """ABIA takes any parent-first numbering; the lane-per-link kernels need
+    depth-first numbering and say so."""
+    from paper_1609_06779_amd import _lib
+
+    n, count = 20, 64
+    rb = _not_depth_first(n, count)
+    q, qd, tau = synth.make_state([n] * count, seed=21, cfg=5)
+    m = fdm.Model(rb, "f64", device=dev)
+    got = _forward(m, rb, q, qd, tau, "f64", dev)
+    _check(got, rb, q, qd, tau, rb.offsets, "f64", "interleaved branches")
+    assert m.max_links("jsiia") == 0
+    args = (_t(q, "f64", dev), _t(qd, "f64", dev), _t(tau, "f64", dev))
+    for call in (lambda: m.forward(*args, batch=count, algo="jsiia"),
+                 lambda: m.inverse(args[0], args[1], None, batch=count),
+                 lambda: m.joint_inertia(args[0], batch=count, n=n)):
         with pytest.raises(_lib.FdError) as e:
             call()
         assert e.value.status == _lib.FD_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n", [1, 5, 8, 17, 32, 33, 64, 100, 128])
+def test_jsiia_on_trees(fdm, dev, dtype, n):
+    """JSIIA on trees: M from the subtree composite inertias, zero between
+    branches, then the dense elimination; every lane-group width (8 .. 128)."""
+    lengths = [n] * 40
+    rb, q, qd, tau = _prep(lengths, dtype, seed=200 + n, p_extend=0.7)
+    m = fdm.Model(rb, dtype, device=dev)
+    got = _forward(m, rb, q, qd, tau, dtype, dev, algo="jsiia")
+    _check(got, rb, q, qd, tau, rb.offsets, dtype, f"jsiia tree n={n} {dtype}", backward=False)
+
+
+def test_jsiia_on_trees_ragged_and_shared(fdm, dev):
+    lengths = synth.ragged_lengths(120, 1, 128, seed=22)
+    rb, q, qd, tau = _prep(lengths, "f64", seed=23, p_extend=0.6)
+    m = fdm.Model(rb, "f64", device=dev)
+    got = _forward(m, rb, q, qd, tau, "f64", dev, algo="jsiia", offsets=rb.offsets)
+    _check(got, rb, q, qd, tau, rb.offsets, "f64", "jsiia ragged trees", backward=False)
+    lengths = [64] * 256
+    rb = synth.make_tree_robots(lengths, seed=24, cfg=5, random_home=True, shared_topology=True)
+    q, qd, tau = synth.make_state(lengths, seed=24, cfg=5)
+    m = fdm.Model(rb, "f64", device=dev)
+    got = _forward(m, rb, q, qd, tau, "f64", dev, algo="jsiia")
+    _check(got, rb, q, qd, tau, rb.offsets, "f64", "jsiia shared topology", backward=False)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n", [1, 7, 32, 64, 130, 256])
+def test_inverse_dynamics_on_trees(fdm, dev, dtype, n):
+    batch = 21
+    lengths = [n] * batch
+    rb, q, qd, _ = _prep(lengths, dtype, seed=300 + n, p_extend=0.7)
+    qdd = np.random.default_rng(n).standard_normal(len(q))
+    if dtype == "f32":
+        qdd = qdd.astype(np.float32).astype(np.float64)
+    m = fdm.Model(rb, dtype, device=dev)
+    for gravity in (True, False):
+        ref = oracle.rnea(rb, q, qd, qdd, gravity=gravity)
+        got = m.inverse(_t(q, dtype, dev), _t(qd, dtype, dev), _t(qdd, dtype, dev), batch=batch,
+                        gravity=gravity).cpu().numpy().astype(np.float64)
+        err = oracle.relative_error(got, ref, rb.offsets)
+        bar = 1e-12 if dtype == "f64" else 2e-5           # the serial-chain bar
+        assert err.max() <= bar * max(1.0, n / 8), (gravity, err.max())
+
+
+@pytest.mark.parametrize("n", [1, 5, 16, 64, 128, 256])
+def test_joint_inertia_on_trees(fdm, dev, n):
+    batch = 9
+    lengths = [n] * batch
+    rb, q, _, _ = _prep(lengths, "f64", seed=400 + n, p_extend=0.7)
+    m = fdm.Model(rb, "f64", device=dev)
+    got = m.joint_inertia(_t(q, "f64", dev), batch=batch, n=n).cpu().numpy()
+    ref = oracle.crba(rb, q)
+    for b in range(batch):
+        scale = np.abs(ref[b]).max()
+        assert np.abs(got[b] - ref[b]).max() <= 1e-13 * scale * max(1, n / 8), b
+        np.testing.assert_array_equal(got[b][ref[b] == 0], 0.0)    # no coupling across branches
+
+
+def test_round_trip_on_trees(fdm, dev):
+    """inverse(q, qd, FD(q, qd, tau)) returns tau (ABIA and JSIIA)."""
+    lengths = [48] * 64
+    rb, q, qd, tau = _prep(lengths, "f64", seed=25)
+    m = fdm.Model(rb, "f64", device=dev)
+    tq, tqd, ttau = _t(q, "f64", dev), _t(qd, "f64", dev), _t(tau, "f64", dev)
+    for algo in ("abia", "jsiia"):
+        qdd = m.forward(tq, tqd, ttau, batch=64, algo=algo)
+        back = m.inverse(tq, tqd, qdd, batch=64).cpu().numpy()
+        err = oracle.relative_error(back, tau, rb.offsets)
+        kappa = np.array([np.linalg.cond(x) for x in oracle.crba(rb, q)])
+        assert np.all(err <= np.maximum(1e-10, 64 * kappa * 2.0 ** -53)), (algo, err.max())
 
 
 def test_full_size_tree_n64_b65536_sampled(fdm, dev):
