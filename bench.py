@@ -351,7 +351,7 @@ def tree_leg(dtype: str, reps: int = 10, keys=TREE_WORKLOADS):
         stream = torch.cuda.current_stream()
         par = rb.parents().reshape(batch, n)
         branch_points = float(np.mean([(np.bincount(p[p >= 0], minlength=n) > 1).sum() for p in par[:1024]]))
-        algo_bytes = batch * n * ((4 + 22) * esz + 4)       # state, the model's 22 fields and one tree code
+        algo_bytes = batch * n * ((4 + 17) * esz + 4)       # state, the model's 17 fields and one tree code
         entry = {"branch_points_per_tree": branch_points}
         for algo in ("abia", "jsiia"):
             ws = model.workspace(batch, algo)

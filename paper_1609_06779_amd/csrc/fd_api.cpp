@@ -22,7 +22,7 @@ struct fd_model {
     bool uniform = false;
     double g[3] = {0, 0, 0};
     void* d_fields = nullptr;         // T[MF_COUNT][total_links]
-    void* d_il = nullptr;             // T[MF_IL_COUNT][nmax][num_robots], columns by decreasing length
+    void* d_il = nullptr;             // T[IL_COUNT][nmax][num_robots], columns by decreasing length
     int64_t* d_link_start = nullptr;
     int32_t* d_n_links = nullptr;
     int32_t* d_slot = nullptr;        // [num_robots] column of each robot in d_il
@@ -128,7 +128,7 @@ fd_status_t plan_batch(const fd_model* m, const fd_batch_t* b, BatchPlan* p) {
 constexpr size_t kLastLevelCache = size_t(256) << 20;
 bool stream_model(const fd_model* m, int batch, int nmax) {
     const size_t esz = m->dtype == FD_F64 ? sizeof(double) : sizeof(float);
-    return (size_t)batch * nmax * (fdk::MF_IL_COUNT + 7) * esz > kLastLevelCache;
+    return (size_t)batch * nmax * (fdk::IL_COUNT + 7) * esz > kLastLevelCache;
 }
 
 fd_status_t from_hip(hipError_t e) {
@@ -297,7 +297,7 @@ fd_status_t fd_init(const fd_model_desc_t* d, fd_dtype_t dtype, fd_model_t** out
         }
         s += d->n_links[r];
     }
-    const int64_t il_elems = (int64_t)fdk::MF_IL_COUNT * mx * d->num_robots;
+    const int64_t il_elems = (int64_t)fdk::IL_COUNT * mx * d->num_robots;
     std::vector<int32_t> tree_il;
     if (tree) {
         tree_il.assign((size_t)mx * d->num_robots, 0);

@@ -93,15 +93,48 @@ __global__ void k_model_init(int64_t nl, const double* __restrict__ raw, const i
     put(MF_MINV, 1.0 / m);
 }
 
-// Robot-interleaved copy of the fields the lane-per-chain kernels read: link l
-// (entry `index` of its robot) goes to column `column[l]`.
+// Unit quaternion (w, x, y, z) of a rotation matrix (row-major), by
+// Shepperd's method: the largest of 4w^2, 4x^2, 4y^2, 4z^2 (read off the
+// trace and the diagonal) fixes the divisor, so no step divides by a small
+// number; the result is normalised.
+__device__ void rot_to_quat(const double r[9], double qt[4]) {
+    const double tr = r[0] + r[4] + r[8];
+    double w, x, y, z;
+    if (tr >= r[0] && tr >= r[4] && tr >= r[8]) {
+        const double s = 2.0 * sqrt(1.0 + tr);
+        w = 0.25 * s; x = (r[7] - r[5]) / s; y = (r[2] - r[6]) / s; z = (r[3] - r[1]) / s;
+    } else if (r[0] >= r[4] && r[0] >= r[8]) {
+        const double s = 2.0 * sqrt(1.0 + r[0] - r[4] - r[8]);
+        w = (r[7] - r[5]) / s; x = 0.25 * s; y = (r[1] + r[3]) / s; z = (r[2] + r[6]) / s;
+    } else if (r[4] >= r[8]) {
+        const double s = 2.0 * sqrt(1.0 + r[4] - r[0] - r[8]);
+        w = (r[2] - r[6]) / s; x = (r[1] + r[3]) / s; y = 0.25 * s; z = (r[5] + r[7]) / s;
+    } else {
+        const double s = 2.0 * sqrt(1.0 + r[8] - r[0] - r[4]);
+        w = (r[3] - r[1]) / s; x = (r[2] + r[6]) / s; y = (r[5] + r[7]) / s; z = 0.25 * s;
+    }
+    const double nrm = sqrt(w * w + x * x + y * y + z * z);
+    qt[0] = w / nrm; qt[1] = x / nrm; qt[2] = y / nrm; qt[3] = z / nrm;
+}
+
+// Robot-interleaved copy of the fields the lane-per-chain kernels read
+// (InterleavedField): link l (entry `index` of its robot) goes to column
+// `column[l]`; its home rotation (the model's canonical-frame matrix, in the
+// model's precision) becomes a quaternion, computed in FP64.
 template <typename T>
 __global__ void k_model_interleave(int64_t nl, const int32_t* __restrict__ column, const int32_t* __restrict__ index,
                                    int32_t num_robots, int64_t fstride, const T* __restrict__ soa, T* __restrict__ il) {
     int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= nl) return;
     const int64_t dst = (int64_t)index[l] * num_robots + column[l];
-    for (int f = 0; f < MF_IL_COUNT; ++f) il[f * fstride + dst] = soa[f * nl + l];
+    double r[9], qt[4];
+    for (int k = 0; k < 9; ++k) r[k] = (double)soa[(MF_ROT + k) * nl + l];
+    rot_to_quat(r, qt);
+    for (int k = 0; k < 4; ++k) il[(IL_QUAT + k) * fstride + dst] = (T)qt[k];
+    for (int k = 0; k < 3; ++k) il[(IL_POS + k) * fstride + dst] = soa[(MF_POS + k) * nl + l];
+    il[IL_MASS * fstride + dst] = soa[MF_MASS * nl + l];
+    for (int k = 0; k < 3; ++k) il[(IL_H + k) * fstride + dst] = soa[(MF_H + k) * nl + l];
+    for (int k = 0; k < 6; ++k) il[(IL_IB + k) * fstride + dst] = soa[(MF_IB + k) * nl + l];
 }
 
 hipError_t launch_model_interleave(int64_t nl, const int32_t* column, const int32_t* index, int32_t num_robots,

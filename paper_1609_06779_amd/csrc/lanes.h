@@ -27,9 +27,30 @@ enum ModelField {
     MF_ICINV = 22,  // 6: Ic^-1
     MF_COM = 28,    // 3: c
     MF_MINV = 31,   // 1: 1/m
-    MF_COUNT = 32,
-    MF_IL_COUNT = 22   // fields MF_ROT .. MF_IB also kept robot-interleaved
+    MF_COUNT = 32
 };
+// The robot-interleaved copy read by the lane-per-chain kernels holds the
+// home rotation as a unit quaternion (4 values instead of 9: those kernels
+// stream the model from HBM once per sweep), then the origin and the inertia.
+enum InterleavedField {
+    IL_QUAT = 0,    // 4: w x y z of Rhome
+    IL_POS = 4,     // 3
+    IL_MASS = 7,    // 1
+    IL_H = 8,       // 3
+    IL_IB = 11,     // 6
+    IL_COUNT = 17
+};
+
+// Rotation matrix (row-major) of a unit quaternion (w, x, y, z).
+template <typename T> __device__ __forceinline__ void quat_to_rot(const T qt[4], T r[9]) {
+    const T w = qt[0], x = qt[1], y = qt[2], z = qt[3];
+    const T x2 = x + x, y2 = y + y, z2 = z + z;
+    const T xx = x * x2, yy = y * y2, zz = z * z2, xy = x * y2, xz = x * z2, yz = y * z2;
+    const T wx = w * x2, wy = w * y2, wz = w * z2;
+    r[0] = T(1) - (yy + zz); r[1] = xy - wz;            r[2] = xz + wy;
+    r[3] = xy + wz;            r[4] = T(1) - (xx + zz); r[5] = yz - wx;
+    r[6] = xz - wy;            r[7] = yz + wx;            r[8] = T(1) - (xx + yy);
+}
 
 // J^-1 = [[Ic^-1, -Ic^-1 [c]], [[c] Ic^-1, 1/m - [c] Ic^-1 [c]]] (row-major 6x6)
 // from p = (Ic^-1 as xx yy zz xy xz yz, c, 1/m): the inverse of the spatial
@@ -104,7 +125,7 @@ template <typename T> struct ModelView {
     const int32_t* n_links;       // [num_robots]
     int32_t num_robots;
     T g[3];                       // gravity, base frame
-    // Robot-interleaved copy of the first MF_IL_COUNT fields: field f of link i
+    // Robot-interleaved copy (InterleavedField): field f of link i
     // of the robot in column c at il[f * il_fstride + i * num_robots + c]
     // (il_fstride = longest robot x num_robots), so that lanes holding
     // consecutive columns read consecutive addresses. Columns hold the robots
@@ -130,18 +151,20 @@ template <typename T> struct ModelView {
         else return *p;
     }
     template <bool NT = false> __device__ __forceinline__ void home_il(int i, int c, T rh[9], T p[3]) const {
+        T qt[4];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) rh[k] = at_il<NT>(MF_ROT + k, i, c);
+        for (int k = 0; k < 4; ++k) qt[k] = at_il<NT>(IL_QUAT + k, i, c);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) p[k] = at_il<NT>(MF_POS + k, i, c);
+        for (int k = 0; k < 3; ++k) p[k] = at_il<NT>(IL_POS + k, i, c);
+        quat_to_rot(qt, rh);
     }
     template <bool NT = false> __device__ __forceinline__ Inertia<T> inertia_il(int i, int c) const {
         Inertia<T> j;
-        j.m = at_il<NT>(MF_MASS, i, c);
+        j.m = at_il<NT>(IL_MASS, i, c);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) j.h[k] = at_il<NT>(MF_H + k, i, c);
+        for (int k = 0; k < 3; ++k) j.h[k] = at_il<NT>(IL_H + k, i, c);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) j.ib[k] = at_il<NT>(MF_IB + k, i, c);
+        for (int k = 0; k < 6; ++k) j.ib[k] = at_il<NT>(IL_IB + k, i, c);
         return j;
     }
 
