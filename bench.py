@@ -210,10 +210,14 @@ def cpu_baseline(rb, q, qd, tau, chains: int, min_s: float = 10.0, max_s: float 
                       f"plain CRBA + RNEA + Cholesky, all host threads, {dt:.1f} s wall"}
 
 
-def serving_leg(dtype: str, requests: int = 10000):
+def serving_leg(dtype: str, requests: int = 30000):
     """Continuous batching over 32 resident robots (n ~ U{7..200}), requests of
-    1..4096 chains (log-uniform), Poisson arrivals at 50% and 80% of the
-    measured saturation rate; latency is arrival to result in host memory."""
+    1..4096 chains (log-uniform), Poisson arrivals at 50%, 70% and 80% of the
+    saturation rate (all requests present at once); latency is arrival to
+    result in host memory. Launches at a finite rate are smaller than at
+    saturation, so 80% sits close to the sustainable rate, where p99 is set by
+    queueing behind bursts; 3e4 requests per point give about 300 samples past
+    the 99th percentile."""
     import torch
 
     from paper_1609_06779_amd import fd, serve, synth
@@ -238,7 +242,7 @@ def serving_leg(dtype: str, requests: int = 10000):
            "algo": "per request, tuned table", "requests_per_load": requests, "budget_bytes": budget,
            "streams": 4, "saturation_solves_per_s": sat.solves_per_s, "saturation_launches": sat.launches,
            "saturation_algo_mix": dict(algos)}
-    for load in (0.5, 0.8):
+    for load in (0.5, 0.7, 0.8):
         qps = load * sat.solves_per_s / mean_chains
         st, _ = run(qps, requests, 3 + int(load * 10))
         out[f"load_{int(load * 100)}pct"] = {"qps": qps, "p50_ms": st.p50 * 1e3, "p99_ms": st.p99 * 1e3,
