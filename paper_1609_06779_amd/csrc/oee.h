@@ -54,6 +54,11 @@ __device__ __forceinline__ void packed_fwd(const T* lf, int np, T x[K]) {
 //     E-part of row i forms T = L_{i+s}^-1 U_i^T, then E_i U_i^T = T^T T and
 //     E_i R_{i+s} = T^T (L^-1 R)_{i+s}.
 //  B. every row publishes W; the E-part sets U_i <- -E_i U_{i+s} = -T^T W_{i+s}.
+// Levels with s >= n change nothing (no row has a partner) and are not run;
+// phase B is skipped at a level with 2 s >= n, where no row keeps a U. Every
+// level still ends with a barrier, so the caller may reuse the slot memory.
+// For groups of more than one wavefront n is the same on every thread (one
+// system per block), so every thread takes the same barriers.
 template <typename T, int K, int NP>
 __device__ bool oee_solve_rows(T d[K * K], T u[K * K], T r[K], int i, int n, bool active, T* slot) {
     using S = OeeSlot<K>;
@@ -65,7 +70,7 @@ __device__ bool oee_solve_rows(T d[K * K], T u[K * K], T r[K], int i, int n, boo
     T* sv = slot;                 // phase B
     bool ok = true;
 #pragma unroll 1
-    for (int s = 1; s < NP; s <<= 1) {
+    for (int s = 1; s < NP && s < n; s <<= 1) {
         T w[K][K];                                 // w[b] = L^-1 (column b of U), published in phase B
         T t[K][K];                                 // t[a] = L_{i+s}^-1 (row a of U), used again in phase B
         if (active) {
@@ -142,6 +147,10 @@ __device__ bool oee_solve_rows(T d[K * K], T u[K * K], T r[K], int i, int n, boo
                 for (int b = 0; b <= a; ++b) d[a * K + b] -= sg[tri<K>(a, b) * NP + p];
                 r[a] -= sq[a * NP + p];
             }
+        }
+        if (2 * s >= n) {                          // last level: no U is kept, phase B has nothing to do
+            block_sync<(NP < 64 ? 64 : NP)>();    // phase A reads done before the slot is reused
+            continue;
         }
         block_sync<(NP < 64 ? 64 : NP)>();
         if (active) {
