@@ -99,6 +99,22 @@ __global__ __launch_bounds__(64) void k_jsiia_gj(ModelView<T> m, ChainMap cm, co
 }
 
 
+// Unknowns of one row block of L^T x = z (rows t = T .. 0 of the block, last
+// first), column by column: lane c of a row group holds z_c, reduced by
+// (1 / d_c) m_tc x_t as each later unknown x_t is found; once every later
+// unknown is in, z_t is x_t, broadcast from lane t to its group. wrow: the
+// block's published rows (row t at wrow[t * ws], its column c at + c); yout
+// takes x_t on the lanes of row group t.
+template <int G, int T, typename R>
+__device__ __forceinline__ void block_back_solve(R& zc, R& yout, const R* wrow, int ws, int c, int r, R rbc) {
+    const R xt = xlane::group_bcast<G, T>(zc);
+    if (r == T) yout = xt;
+    if constexpr (T > 0) {
+        if (c < T) zc -= rbc * wrow[T * ws + c] * xt;
+        block_back_solve<G, T - 1>(zc, yout, wrow, ws, c, r, rbc);
+    }
+}
+
 // Chains of up to 64 or 128 links: M spread over a G x G grid of lanes,
 // G = NP / 8 (one chain per workgroup: 64 lanes for NP = 64, 256 for
 // NP = 128). Lane (r, c) owns the entries (i, k) = (r + G a, c + G b) with
@@ -215,10 +231,10 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> 
     // Back substitution L^T x = D^-1 b in blocks of G rows, last block first.
     // Row block jb is published once (entries m_jk, k <= j, and the block's
     // z = D^-1 b and 1 / d). Lane (r, c) then carries x of the block's row c:
-    // each unknown of the block, and each correction of a row above it, is a
-    // sum over the block's rows, one term per lane of a row group (G
-    // consecutive lanes), summed by dpp::group_sum. The buffer reuses LDS that
-    // is free after the M build.
+    // the block's unknowns come column by column (block_back_solve), and each
+    // correction of a row above the block is a sum over the block's rows, one
+    // term per lane of a row group (G consecutive lanes), summed by
+    // dpp::group_sum. The buffer reuses LDS that is free after the M build.
     constexpr int WS = NP + 1;                              // row stride: one extra entry spreads the rows over the LDS banks
     T* wbuf = TH > 64 ? xbuf : sf;                          // G rows of WS entries, then z (G), 1/d (G)
     static_assert((TH > 64 ? 10 * TH : NP * 13) >= G * WS + 2 * G, "block rows fit the reused buffer");
@@ -236,15 +252,9 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> 
             rb[r] = rd[jb];
         }
         block_sync<TH>();
-        // x_t = z_t - (1 / d_t) sum_{u > t} m_ut x_u within the block
-        T xc = T(0);
-#pragma unroll
-        for (int t = G - 1; t >= 0; --t) {
-            const T part = c > t ? wbuf[c * WS + G * jb + t] * xc : T(0);
-            const T xt = zb[t] - dpp::group_sum<G>(part) * rb[t];
-            xc = c == t ? xt : xc;
-            if (r == t) y[jb] = xt;
-        }
+        // x_t = z_t - (1 / d_t) sum_{u > t} m_ut x_u within the block; lane c ends with x_c
+        T xc = zb[c];
+        block_back_solve<G, G - 1>(xc, y[jb], wbuf + G * jb, WS, c, r, rb[c]);
         // rows k above the block: z_k -= (1 / d_k) sum_t m_tk x_t
 #pragma unroll
         for (int a = 0; a < jb; ++a) y[a] -= dpp::group_sum<G>(wbuf[c * WS + r + G * a] * xc) * rd[a];

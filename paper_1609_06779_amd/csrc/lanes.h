@@ -255,11 +255,15 @@ template <bool NT, typename T> __device__ __forceinline__ void st_ws(T v, T* p) 
     else *p = v;
 }
 
-// Block-wide LDS ordering. A block of one wavefront needs none: its LDS
-// operations complete in program order, so a write is seen by every later
-// read of the same wavefront. Larger blocks need the barrier.
+// Block-wide LDS ordering. Larger blocks need the barrier. A block of one
+// wavefront needs no hardware barrier (its LDS operations complete in program
+// order), but the compiler must still not move LDS accesses across the point
+// where lanes hand data to each other: without a fence it may, for instance,
+// sink a lane's read of another lane's store into a branch taken only by the
+// writers. The wave barrier emits no instruction and pins that order.
 template <int THREADS> __device__ __forceinline__ void block_sync() {
     if constexpr (THREADS > 64) __syncthreads();
+    else __builtin_amdgcn_wave_barrier();
 }
 
 // ---------------- lane-group exchange ----------------
@@ -527,6 +531,22 @@ __device__ __forceinline__ float bperm(float v, int addr) {
     return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
 }
 __device__ __forceinline__ int bperm(int v, int addr) { return __builtin_amdgcn_ds_bpermute(addr, v); }
+
+// Lane T of every group of G consecutive lanes (G = 8 or 16) to all lanes of
+// the group, by ds_swizzle in bit mode: within each 32-lane half, lane l reads
+// lane (l & and_mask) | T, and_mask keeping the group bits.
+template <int G, int T> __device__ __forceinline__ double group_bcast(double v) {
+    static_assert((G == 8 || G == 16) && T >= 0 && T < G, "a lane of a group of 8 or 16");
+    constexpr int pattern = (32 - G) | (T << 5);
+    const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), pattern);
+    const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), pattern);
+    return __hiloint2double(hi, lo);
+}
+template <int G, int T> __device__ __forceinline__ float group_bcast(float v) {
+    static_assert((G == 8 || G == 16) && T >= 0 && T < G, "a lane of a group of 8 or 16");
+    constexpr int pattern = (32 - G) | (T << 5);
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), pattern));
+}
 }  // namespace xlane
 
 template <int NP, int W, typename T>
