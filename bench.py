@@ -322,6 +322,82 @@ def copy_calibration(dev):
     del src, dst
 
 
+def adjoint_leg(dtype: str, reps: int = 10, steps: int = 50):
+    """Reverse mode at 65536 chains of 64 links: the vector-Jacobian product
+    (fd_backward) per launch beside the plain ABIA forward it differentiates,
+    and a checkpointed rollout of `steps` semi-implicit Euler steps (forward,
+    then the backward pass through the recomputed segments) beside `steps`
+    plain forward + Euler steps."""
+    import torch
+
+    from paper_1609_06779_amd import fd, synth
+
+    dev = torch.device("cuda:0")
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    batch, n = 65536, 64
+    lengths = synth.uniform_lengths(batch, n)
+    rb = synth.make_robots(lengths, cfg=2)
+    if dtype == "f32":
+        rb = rb.astype_rounded(np.float32)
+    q, qd, tau = synth.make_state(lengths, cfg=2)
+    model = fd.Model(rb, dtype, device=dev)
+    tq, tqd, ttau = (torch.from_numpy(a).to(dev, tdt) for a in (q, qd, tau))
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, count):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(count):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / count
+
+    ws = model.workspace(batch, "abia")
+    qdd = torch.empty_like(tq)
+    ms_fwd = timed(lambda: model.forward(tq, tqd, ttau, batch=batch, algo="abia", out=qdd, workspace=ws,
+                                         stream=stream), reps)
+    g = torch.from_numpy(np.random.default_rng(5).standard_normal(len(q))).to(dev, tdt)
+    bws = model.backward_workspace(batch)
+    gq, gqd, gt = (torch.empty_like(tq) for _ in range(3))
+    ms_vjp = timed(lambda: model.backward(tq, tqd, qdd, g, batch=batch, grad_q=gq, grad_qd=gqd, grad_tau=gt,
+                                          workspace=bws, stream=stream), reps)
+
+    dt = 1e-3
+    qs, qds = tq.clone(), tqd.clone()
+
+    def plain_steps():
+        for _ in range(steps):
+            model.forward(qs, qds, ttau, batch=batch, algo="abia", out=qdd, workspace=ws, stream=stream)
+            model.euler_step(qs, qds, qdd, dt, q_next=qs, qd_next=qds, stream=stream)
+
+    ms_plain = timed(plain_steps, 1)
+    taus = ttau.unsqueeze(0).repeat(steps, 1)
+    wq, wqd = torch.ones_like(tq), torch.ones_like(tq)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    for rep in range(2):                           # the second pass is timed (allocator warm)
+        q0, qd0 = tq.clone().requires_grad_(True), tqd.clone().requires_grad_(True)
+        tt = taus.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        qT, qdT = fd.rollout(model, q0, qd0, tt, batch=batch, dt=dt, every=10, algo="abia")
+        ev[1].record(stream)
+        ((qT * wq).sum() + (qdT * wqd).sum()).backward()
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        assert torch.isfinite(tt.grad).all().item() and torch.isfinite(q0.grad).all().item()
+    out = {"workload": f"uniform-n{n}-b{batch}", "abia_forward_ms": ms_fwd, "vjp_ms": ms_vjp,
+           "vjp_over_forward": ms_vjp / ms_fwd,
+           "rollout": {"steps": steps, "checkpoint_every": 10, "forward_ms": ev[0].elapsed_time(ev[1]),
+                       "backward_ms": ev[1].elapsed_time(ev[2]), "plain_forward_steps_ms": ms_plain}}
+    model.close()
+    del tq, tqd, ttau, taus, qdd, g, gq, gqd, gt, ws, bws
+    torch.cuda.empty_cache()
+    return out
+
+
 TREE_WORKLOADS = ("tree-shared-n64-b65536", "tree-n64-b65536")
 
 
@@ -395,6 +471,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--no-tree", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--only-trees", action="store_true", help="run the branched-robot leg alone")
     ap.add_argument("--tree-workloads", default=",".join(TREE_WORKLOADS))
     ap.add_argument("--workload", help="with --trace-summary or --pmc-summary: the workload name to file under")
@@ -518,6 +595,9 @@ def main():
     if not args.no_ragged:
         print("[bench] ragged leg", file=sys.stderr, flush=True)
         result["ragged"] = ragged_leg(args.dtype)
+    if not args.no_adjoint:
+        print("[bench] adjoint leg", file=sys.stderr, flush=True)
+        result["adjoint"] = adjoint_leg(args.dtype)
     if not args.no_tree:
         print("[bench] tree leg", file=sys.stderr, flush=True)
         result["trees"] = tree_leg(args.dtype, keys=tree_keys)
