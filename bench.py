@@ -148,6 +148,59 @@ def summarize_pmc(fetch_dir: str, write_dir: str, workload: str, commands, summa
     return path
 
 
+def summarize_flops(p1_dir: str, p2_dir: str, workload: str, commands, summary_cmd: str, bench_log: str,
+                    n: int, batch: int, dtype: str) -> str:
+    """Write profiles/<workload>_valu_flops.md from two rocprofv3 --pmc passes:
+    SQ_INSTS_VALU_FLOPS_FP64 (FP64 flops per wave instruction: 2 per FMA, 1 per
+    add or multiply), then SQ_INSTS_MFMA, SQ_INSTS_VALU and the FP64 FMA / MUL /
+    ADD counts. Executed flops per launch = the flops counter x 64 lanes (masked
+    lanes included); the time per launch is bench.py's HIP-event average from
+    `bench_log` (an unprofiled or trace-only run of the same step)."""
+    import csv
+    import glob
+    import re
+
+    def load(d):
+        vals = collections.defaultdict(lambda: collections.defaultdict(list))
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                vals[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        return vals
+
+    c1, c2 = load(p1_dir), load(p2_dir)
+    events = {}
+    for line in open(bench_log):
+        if line.startswith("{"):
+            events = {a: v["ms_per_launch"] for a, v in json.loads(line).get("per_algo", {}).items()}
+    peak = PEAK_FLOPS[dtype] / 1e12
+    lines = [f"# FP64 VALU work per launch: {workload}", "", "Commands:", "", "```", *commands, summary_cmd, "```", "",
+             "Executed flops = `SQ_INSTS_VALU_FLOPS_FP64` x 64 lanes (it counts 2 per FMA and 1 per add or "
+             "multiply, per wave instruction, so masked lanes are included). The algorithmic count is "
+             "bench.py's `fma_per_solve` x 2 x batch. Times: the HIP-event average per launch of the "
+             "bench log named above (an unprofiled bench.py run of the same workload).", "",
+             "| algorithm | kernel | executed GFLOP / launch | algorithmic GFLOP / launch | ms / launch | "
+             "executed TFLOP/s | frac of peak | MFMA instructions | FP64 share of VALU instructions |",
+             "|---|---|---|---|---|---|---|---|---|"]
+    for algo, pat in KERNEL_PATTERNS:
+        k1 = next((k for k in c1 if re.search(pat, k)), None)
+        k2 = next((k for k in c2 if re.search(pat, k)), None)
+        if not k1 or not k2 or algo not in events:
+            continue
+        mean = lambda d, c: sum(d[c]) / len(d[c])
+        ex = mean(c1[k1], "SQ_INSTS_VALU_FLOPS_FP64") * 64
+        alg = 2.0 * fma_per_solve(algo, n) * batch
+        ms = events[algo]
+        f64 = sum(mean(c2[k2], c) for c in ("SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_ADD_F64"))
+        rate = ex / (ms * 1e-3) / 1e12
+        lines.append(f"| {algo} | `{k1.split('(')[0].replace('void ', '')}` | {ex / 1e9:.2f} | {alg / 1e9:.2f} | "
+                     f"{ms:.3f} | {rate:.1f} | {rate / peak:.2f} | {mean(c2[k2], 'SQ_INSTS_MFMA'):.0f} | "
+                     f"{f64 / mean(c2[k2], 'SQ_INSTS_VALU'):.2f} |")
+    path = os.path.join(ROOT, "profiles", f"{workload}_valu_flops.md")
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return path
+
+
 def summarize_trace(trace_dir: str, workload: str, commands, summary_cmd: str, bench_log=None) -> str:
     """Write profiles/<workload>_kernel_trace.md from a rocprofv3 --kernel-trace --stats run;
     with ``bench_log`` (the profiled bench.py's output) its own HIP-event averages go beside."""
@@ -205,9 +258,17 @@ def cpu_baseline(rb, q, qd, tau, chains: int, min_s: float = 10.0, max_s: float 
         dt = time.perf_counter() - t0
         if dt >= min_s or dt * (passes + 1) / passes > max_s:
             break
-    return {"value": passes * chains / dt, "unit": "solves/s", "cores": oracle.max_threads(), "kind": "oracle",
+    cores = oracle.max_threads()
+    one = min(chains, 4096)                     # one host thread, a smaller slice of the same chains
+    sl = slice(0, one * n)
+    t1 = time.perf_counter()
+    oracle.fd(sub.take(np.arange(one)), q[sl], qd[sl], tau[sl], threads=1)
+    dt1 = time.perf_counter() - t1
+    return {"value": passes * chains / dt, "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "single_thread_value": one / dt1,
             "sample": f"{passes} passes over the first {chains} chains of the same workload (n={n}, FP64), "
-                      f"plain CRBA + RNEA + Cholesky, all host threads, {dt:.1f} s wall"}
+                      f"plain CRBA + RNEA + Cholesky, all host threads, {dt:.1f} s wall; single thread: "
+                      f"the first {one} chains, {dt1:.1f} s"}
 
 
 def serving_leg(dtype: str, requests: int = 30000):
@@ -320,6 +381,108 @@ def copy_calibration(dev):
         dst.copy_(src)
     torch.cuda.synchronize()
     del src, dst
+
+
+def transfer_leg(dtype: str, reps: int = 10):
+    """The headline batch (65536 chains of 64 links) with its state handed over in
+    pinned host memory: copy q, qd, tau in, one ABIA launch, copy qdd out, all on
+    one stream. The library itself takes device buffers; this is the rate a
+    caller holding host arrays sees."""
+    import torch
+
+    from paper_1609_06779_amd import fd, synth
+
+    dev = torch.device("cuda:0")
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    batch, n = 65536, 64
+    lengths = synth.uniform_lengths(batch, n)
+    rb = synth.make_robots(lengths, cfg=2)
+    if dtype == "f32":
+        rb = rb.astype_rounded(np.float32)
+    q, qd, tau = synth.make_state(lengths, cfg=2)
+    model = fd.Model(rb, dtype, device=dev)
+    host = [torch.from_numpy(a).to(tdt).pin_memory() for a in (q, qd, tau)]
+    hout = torch.empty(len(q), dtype=tdt).pin_memory()
+    dq, dqd, dtau = (torch.empty(len(q), dtype=tdt, device=dev) for _ in range(3))
+    out = torch.empty_like(dq)
+    ws = model.workspace(batch, "abia")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        for d, h in zip((dq, dqd, dtau), host):
+            d.copy_(h, non_blocking=True)
+        model.forward(dq, dqd, dtau, batch=batch, algo="abia", out=out, workspace=ws, stream=stream)
+        hout.copy_(out, non_blocking=True)
+
+    step()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        step()
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    model.close()
+    return {"workload": f"uniform-n{n}-b{batch}", "algo": "abia", "ms_per_batch": ms,
+            "solves_per_s": batch / (ms * 1e-3), "bytes_over_pcie": 4 * len(q) * (8 if dtype == "f64" else 4)}
+
+
+def levels_leg(dtype: str, ns=(16, 32, 64, 128), batch: int = 65536, reps: int = 20):
+    """The two building blocks on their own at `batch` systems of n blocks each:
+    the segmented scan of block bi-diagonal 6x6 systems (fd_scan6) and the
+    odd-even elimination solve of SPD block tri-diagonal 6x6 systems
+    (fd_btd_solve6), both with ceil(log2 n) levels. Reports the launch time,
+    the time per level (launch time / levels, loads and stores included) and
+    the algorithmic HBM rate. Inputs: 1024 seeded systems tiled to the batch."""
+    import torch
+
+    from paper_1609_06779_amd import fd, synth
+
+    dev = torch.device("cuda:0")
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    w = 8 if dtype == "f64" else 4
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    out = {}
+    rep = batch // 1024
+    for n in ns:
+        lengths = np.full(1024, n, np.int64)
+        off = torch.from_numpy(synth.offsets_of(np.full(batch, n, np.int64))).to(dev)
+        levels = max(1, math.ceil(math.log2(n)))
+        sb, sc = synth.make_scan_elements(lengths)
+        sb, sc = (torch.from_numpy(x).to(dev, tdt).repeat(rep, *([1] * (x.ndim - 1))) for x in (sb, sc))
+        sx = torch.empty_like(sc)
+        ms_scan = timed(lambda: fd.scan6(sb, sc, off, n, out=sx, stream=stream))
+        d, u, r = synth.make_btd(lengths)
+        d, u, r = (torch.from_numpy(x).to(dev, tdt).repeat(rep, *([1] * (x.ndim - 1))) for x in (d, u, r))
+        x = torch.empty_like(r)
+        st = torch.zeros(1, dtype=torch.int32, device=dev)
+        ms_oee = timed(lambda: fd.btd_solve6(d, u, r, off, n, out=x, status=st, stream=stream))
+        if int(st.item()) != 0:
+            raise RuntimeError(f"btd_solve6 status {int(st.item())} at n={n}")
+        rows = batch * n
+        out[str(n)] = {
+            "levels": levels,
+            "scan_ms": ms_scan, "scan_us_per_level": 1e3 * ms_scan / levels,
+            "scan_gb_s": rows * (36 + 12) * w / (ms_scan * 1e-3) / 1e9,
+            "oee_ms": ms_oee, "oee_us_per_level": 1e3 * ms_oee / levels,
+            "oee_gb_s": rows * (72 + 12) * w / (ms_oee * 1e-3) / 1e9,
+        }
+        del sb, sc, sx, d, u, r, x
+        torch.cuda.empty_cache()
+    return out
 
 
 def adjoint_leg(dtype: str, reps: int = 10, steps: int = 50):
@@ -472,6 +635,10 @@ def main():
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--no-tree", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-transfer", action="store_true")
+    ap.add_argument("--no-levels", action="store_true")
+    ap.add_argument("--only-step", action="store_true",
+                    help="time the step alone: no legs and no CPU baseline (the profiled command)")
     ap.add_argument("--only-trees", action="store_true", help="run the branched-robot leg alone")
     ap.add_argument("--tree-workloads", default=",".join(TREE_WORKLOADS))
     ap.add_argument("--workload", help="with --trace-summary or --pmc-summary: the workload name to file under")
@@ -483,8 +650,13 @@ def main():
                     help="with --pmc-summary or --trace-summary: the profiler command lines to record")
     ap.add_argument("--trace-summary", metavar="TRACE_DIR",
                     help="summarise a rocprofv3 --kernel-trace --stats run into profiles/ and exit (no GPU use)")
-    ap.add_argument("--bench-log", help="with --trace-summary: output of the profiled bench.py run")
+    ap.add_argument("--bench-log", help="with --trace-summary or --flops-summary: output of the profiled bench.py run")
+    ap.add_argument("--flops-summary", nargs=2, metavar=("P1_DIR", "P2_DIR"),
+                    help="summarise the two FP64 VALU counter passes into profiles/ and exit (no GPU use)")
     args = ap.parse_args()
+    if args.only_step:
+        args.no_cpu = args.no_serve = args.no_ragged = args.no_tree = args.no_adjoint = args.no_transfer = True
+        args.no_levels = True
     wl = args.workload or f"fd_forward_n{args.n}_b{args.batch}_{args.dtype}"
     wl_flag = f" --workload {args.workload}" if args.workload else ""
     if args.trace_summary:
@@ -492,6 +664,12 @@ def main():
                               f"python bench.py --trace-summary {args.trace_summary} --n {args.n} "
                               f"--batch {args.batch} --dtype {args.dtype}{wl_flag} --bench-log {args.bench_log} "
                               f"--pmc-command ...", args.bench_log))
+        return
+    if args.flops_summary:
+        print(summarize_flops(*args.flops_summary, wl, args.pmc_command,
+                              f"python bench.py --flops-summary {' '.join(args.flops_summary)} --n {args.n} "
+                              f"--batch {args.batch} --dtype {args.dtype}{wl_flag} --bench-log {args.bench_log} "
+                              f"--pmc-command ...", args.bench_log, args.n, args.batch, args.dtype))
         return
     if args.pmc_summary:
         print(summarize_pmc(*args.pmc_summary, wl, args.pmc_command,
@@ -595,6 +773,12 @@ def main():
     if not args.no_ragged:
         print("[bench] ragged leg", file=sys.stderr, flush=True)
         result["ragged"] = ragged_leg(args.dtype)
+    if not args.no_transfer:
+        print("[bench] transfer leg", file=sys.stderr, flush=True)
+        result["host_transfer"] = transfer_leg(args.dtype)
+    if not args.no_levels:
+        print("[bench] levels leg", file=sys.stderr, flush=True)
+        result["levels"] = levels_leg(args.dtype)
     if not args.no_adjoint:
         print("[bench] adjoint leg", file=sys.stderr, flush=True)
         result["adjoint"] = adjoint_leg(args.dtype)
