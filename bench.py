@@ -558,6 +558,32 @@ def adjoint_leg(dtype: str, reps: int = 10, steps: int = 50):
     model.close()
     del tq, tqd, ttau, taus, qdd, g, gq, gqd, gt, ws, bws
     torch.cuda.empty_cache()
+    # the same VJP on branched robots of the same size (tree workloads of the tree leg)
+    out["trees"] = {}
+    for key in TREE_WORKLOADS:
+        w = synth.WORKLOADS[key]
+        tl = synth.uniform_lengths(w["batch"], w["n"])
+        rb = synth.make_tree_robots(tl, p_extend=w["p_extend"], cfg=w["cfg"],
+                                    shared_topology=w.get("shared_topology", False))
+        if dtype == "f32":
+            rb = rb.astype_rounded(np.float32)
+        q, qd, tau = synth.make_state(tl, cfg=w["cfg"])
+        model = fd.Model(rb, dtype, device=dev)
+        tq, tqd, ttau = (torch.from_numpy(a).to(dev, tdt) for a in (q, qd, tau))
+        ws = model.workspace(w["batch"], "abia")
+        qdd = torch.empty_like(tq)
+        ms_fwd = timed(lambda: model.forward(tq, tqd, ttau, batch=w["batch"], algo="abia", out=qdd, workspace=ws,
+                                             stream=stream), reps)
+        g = torch.from_numpy(np.random.default_rng(5).standard_normal(len(q))).to(dev, tdt)
+        bws = model.backward_workspace(w["batch"])
+        gq, gqd, gt = (torch.empty_like(tq) for _ in range(3))
+        ms_vjp = timed(lambda: model.backward(tq, tqd, qdd, g, batch=w["batch"], grad_q=gq, grad_qd=gqd,
+                                              grad_tau=gt, workspace=bws, stream=stream), reps)
+        assert torch.isfinite(gq).all().item() and torch.isfinite(gt).all().item()
+        out["trees"][key] = {"abia_forward_ms": ms_fwd, "vjp_ms": ms_vjp, "vjp_over_forward": ms_vjp / ms_fwd}
+        model.close()
+        del tq, tqd, ttau, qdd, g, gq, gqd, gt, ws, bws
+        torch.cuda.empty_cache()
     return out
 
 

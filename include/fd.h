@@ -21,10 +21,10 @@
  * Branched robots (trees, beyond the paper's serial chains) name a parent per
  * link, and i-1 above reads that parent. The articulated-body algorithm takes
  * any numbering with parents before children (fd_forward with FD_ALGO_ABIA,
- * fd_forward_persistent). The lane-per-link paths (FD_ALGO_JSIIA, fd_inverse,
- * fd_joint_inertia) need the links of each robot numbered depth-first, so
- * that every subtree is a run of consecutive links. The CFA and fd_backward
- * take serial chains only. A path that does not take the model returns
+ * fd_forward_persistent, fd_backward). The lane-per-link paths (FD_ALGO_JSIIA,
+ * fd_inverse, fd_joint_inertia) need the links of each robot numbered
+ * depth-first, so that every subtree is a run of consecutive links. The CFA
+ * takes serial chains only. A path that does not take the model returns
  * FD_ERR_UNSUPPORTED; FD_ALGO_AUTO picks one that does.
  * Gravity acts as a base acceleration (the "const." terms of eq. (EOM-full));
  * there is no force at the end effector. SI units, angles in radians.

@@ -452,9 +452,8 @@ fd_status_t fd_backward_workspace_size(const fd_model_t* m, const fd_batch_t* b,
     BatchPlan p;
     fd_status_t s = plan_batch(m, b, &p);
     if (s != FD_OK) return s;
-    if (m->tree) return FD_ERR_UNSUPPORTED;
     const size_t esz = m->dtype == FD_F64 ? sizeof(double) : sizeof(float);
-    *bytes = fdk::vjp_workspace_elems(b->batch, p.nmax) * esz;
+    *bytes = fdk::vjp_workspace_elems(b->batch, p.nmax, m->tree) * esz;
     return FD_OK;
 }
 
@@ -464,11 +463,10 @@ fd_status_t fd_backward(const fd_model_t* m, const fd_batch_t* b, const void* q,
     BatchPlan p;
     fd_status_t s = plan_batch(m, b, &p);
     if (s != FD_OK) return s;
-    if (m->tree) return FD_ERR_UNSUPPORTED;
     if (b->batch == 0) return FD_OK;
     if (!q || !qd || !qdd || !gqdd || !gq || !gqd || !gtau) return FD_ERR_INVALID_ARG;
     const size_t esz = m->dtype == FD_F64 ? sizeof(double) : sizeof(float);
-    if (!ws || ws_bytes < fdk::vjp_workspace_elems(b->batch, p.nmax) * esz) return FD_ERR_WORKSPACE;
+    if (!ws || ws_bytes < fdk::vjp_workspace_elems(b->batch, p.nmax, m->tree) * esz) return FD_ERR_WORKSPACE;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     if (m->dtype == FD_F64)
         return from_hip(fdk::launch_fd_vjp<double>(view<double>(m), p.cm, p.nmax, (const double*)q, (const double*)qd,

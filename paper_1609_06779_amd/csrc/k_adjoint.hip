@@ -21,6 +21,14 @@
 //     (dID/dq)^T lambda |_i  = -Vb_i . ad_S V_i - ab_i . ad_S (a_i - ad_{V_i}(S qd_i))
 //                              - (ad_S A_i Fb_{i-1}) . F_i
 // using d A_i / d q_i = -ad_S A_i. One lane per chain, robot-interleaved model.
+//
+// Branched robots (trees): i - 1 reads p(i) in the forward recursions, and the
+// backward ones sum the terms A_c^T (.) of all children c of i, as in the
+// tree form of the ABIA: a child whose parent is i - 1 passes them in
+// registers, any other child adds them into a record of its parent in the
+// workspace (the highest-numbered such child writes it first). The force
+// recursion adds straight into the parent's F field, which holds f_p when the
+// backward sweep starts.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -35,10 +43,16 @@ constexpr int VJP_V = 7;       // V (6)
 constexpr int VJP_A = 13;      // a (6)
 constexpr int VJP_F = 19;      // f -> F -> Fb (6)
 constexpr int VJP_FIELDS = 25;
+// Trees add a branch-point record after those 25 fields, reused phase by phase:
+// A: the children's p terms (6) and Jh - h h^T / D (21, upper triangle by rows);
+// B: the acceleration of the M^-1 g recursion (6); E: the children's ab (6) and vb (6).
+constexpr int VJP_WB = VJP_FIELDS;
+constexpr int VJP_TREE_FIELDS = VJP_FIELDS + 27;
+template <bool TREE> constexpr int vjp_fields() { return TREE ? VJP_TREE_FIELDS : VJP_FIELDS; }
 
-size_t vjp_workspace_elems(int batch, int nmax) {
+size_t vjp_workspace_elems(int batch, int nmax, bool tree) {
     size_t blocks = (size_t)(batch + 63) / 64;
-    return blocks * (size_t)nmax * VJP_FIELDS * 64;
+    return blocks * (size_t)nmax * (tree ? VJP_TREE_FIELDS : VJP_FIELDS) * 64;
 }
 
 template <typename T>
@@ -70,7 +84,10 @@ template <typename T> __device__ __forceinline__ void ad_z(const T x[6], T y[6])
     y[3] = -x[4]; y[4] = x[3]; y[5] = T(0);
 }
 
-template <typename T>
+// Adds x (or stores it, when first) into the workspace entry d.
+template <typename T> __device__ __forceinline__ void add_into(T* d, T x, bool first) { *d = first ? x : *d + x; }
+
+template <typename T, bool TREE>
 __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int nmax, const T* __restrict__ q,
                                                const T* __restrict__ qd, const T* __restrict__ qdd,
                                                const T* __restrict__ gqdd, T* __restrict__ gq,
@@ -88,8 +105,9 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
     }
     const int n = ci.n;
     const int sl = ci.slot;
-    T* wsb = ws + (size_t)blockIdx.x * nmax * VJP_FIELDS * 64 + lane;
-    auto w = [&](int i, int f) -> T& { return wsb[((size_t)i * VJP_FIELDS + f) * 64]; };
+    T* wsb = ws + (size_t)blockIdx.x * nmax * vjp_fields<TREE>() * 64 + lane;
+    auto w = [&](int i, int f) -> T& { return wsb[((size_t)i * vjp_fields<TREE>() + f) * 64]; };
+    auto code_of = [&](int i) -> int32_t { return TREE ? m.template tree_il<false>(i, sl) : 0; };
 
     // A: articulated-body inertias and the p recursion with tau_delta := g
     {
@@ -98,11 +116,13 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
 #pragma unroll
         for (int c = 0; c < 36; ++c) pi[c] = T(0);
         Pose<T> tn = pose_identity<T>();
+        bool carry = false;                            // trees: registers hold link i+1's terms for link i
         for (int i = n - 1; i >= 0; --i) {
             const int64_t st = ci.state0 + i;
+            const int32_t code = code_of(i);
             T jh[36], pp[6];
             inertia_to_mat6(m.inertia_il(i, sl), jh);
-            if (i + 1 < n) {
+            if (TREE ? carry : i + 1 < n) {
                 wrench_to_parent(tn, pc, pp);
                 T y[36];
                 congruence_up(tn, pi, y);
@@ -111,6 +131,21 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
             } else {
 #pragma unroll
                 for (int c = 0; c < 6; ++c) pp[c] = T(0);
+            }
+            if constexpr (TREE) {
+                if (code & TREE_BRANCH) {              // the other children's terms, summed
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) pp[c] += w(i, VJP_WB + c);
+                    int k = VJP_WB + 6;
+#pragma unroll
+                    for (int r = 0; r < 6; ++r)
+#pragma unroll
+                        for (int c = r; c < 6; ++c, ++k) {
+                            const T y = w(i, k);
+                            jh[6 * r + c] += y;
+                            if (c != r) jh[6 * c + r] += y;
+                        }
+                }
             }
             const T dinv = rcp_refined(jh[14]);
             const T u = gqdd[st] - pp[2];
@@ -127,6 +162,23 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
 #pragma unroll
             for (int c = 0; c < 6; ++c) pc[c] = pp[c] + h[c] * u * dinv;
             tn = pose_il(m, i, sl, q[st]);
+            if constexpr (TREE) {
+                carry = (code & TREE_CHAIN) != 0;
+                const int p = tree_parent(code);
+                if (!carry && p >= 0) {                // hand the terms to a branch point now
+                    const bool first = (code & TREE_FIRST) != 0;
+                    T x[6], y[36];
+                    wrench_to_parent(tn, pc, x);
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) add_into(&w(p, VJP_WB + c), x[c], first);
+                    congruence_up(tn, pi, y);
+                    int k = VJP_WB + 6;
+#pragma unroll
+                    for (int r = 0; r < 6; ++r)
+#pragma unroll
+                        for (int c = r; c < 6; ++c, ++k) add_into(&w(p, k), y[6 * r + c], first);
+                }
+            }
         }
     }
     // B: lambda, and the inverse dynamics forward sweep at the given qdd
@@ -136,6 +188,18 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
         T a[6] = {T(0), T(0), T(0), -m.g[0], -m.g[1], -m.g[2]};
         for (int i = 0; i < n; ++i) {
             const int64_t st = ci.state0 + i;
+            const int32_t code = code_of(i);
+            if constexpr (TREE) {
+                if (!(code & TREE_CHAIN)) {            // the parent's terms, not link i-1's
+                    const int p = tree_parent(code);
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) {
+                        acc[c] = p < 0 ? T(0) : w(p, VJP_WB + c);
+                        v[c] = p < 0 ? T(0) : w(p, VJP_V + c);
+                        a[c] = p < 0 ? (c < 3 ? T(0) : -m.g[c - 3]) : w(p, VJP_A + c);
+                    }
+                }
+            }
             const Pose<T> tl = pose_il(m, i, sl, q[st]);
             T t[6];
             ad_inv_apply(tl, acc, t);
@@ -147,6 +211,12 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
             for (int c = 0; c < 6; ++c) acc[c] = t[c];
             w(i, VJP_HD) = lam;
             gtau[st] = accumulate ? gtau[st] + lam : lam;
+            if constexpr (TREE) {
+                if (code & TREE_BRANCH) {
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) w(i, VJP_WB + c) = acc[c];
+                }
+            }
 
             const T qdi = qd[st];
             ad_inv_apply(tl, v, t);
@@ -169,15 +239,16 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
             }
         }
     }
-    // C: force recursion F_i = f_i + A_{i+1}^T F_{i+1}
+    // C: force recursion F_i = f_i + sum over children c of A_c^T F_c
     {
         T fc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
         Pose<T> tn = pose_identity<T>();
+        bool carry = false;
         for (int i = n - 1; i >= 0; --i) {
             T f[6], fp[6];
 #pragma unroll
             for (int c = 0; c < 6; ++c) f[c] = w(i, VJP_F + c);
-            if (i + 1 < n) {
+            if (TREE ? carry : i + 1 < n) {
                 wrench_to_parent(tn, fc, fp);
 #pragma unroll
                 for (int c = 0; c < 6; ++c) f[c] += fp[c];
@@ -188,17 +259,37 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
                 w(i, VJP_F + c) = f[c];
             }
             tn = pose_il(m, i, sl, q[ci.state0 + i]);
+            if constexpr (TREE) {
+                const int32_t code = code_of(i);
+                carry = (code & TREE_CHAIN) != 0;
+                const int p = tree_parent(code);
+                if (!carry && p >= 0) {                // into the parent's f_p (+ its other children's terms)
+                    wrench_to_parent(tn, f, fp);
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) w(p, VJP_F + c) += fp[c];
+                }
+            }
         }
     }
-    // D: Fb_i = lambda_i S + A_i Fb_{i-1}; force term of q_bar
+    // D: Fb_i = lambda_i S + A_i Fb_p(i); force term of q_bar
     {
         T fb[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
         for (int i = 0; i < n; ++i) {
+            bool has_parent = i > 0;
+            if constexpr (TREE) {
+                const int32_t code = code_of(i);
+                const int p = tree_parent(code);
+                has_parent = p >= 0;
+                if (!(code & TREE_CHAIN)) {
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) fb[c] = p < 0 ? T(0) : w(p, VJP_F + c);   // Fb_p, written at p
+                }
+            }
             const Pose<T> tl = pose_il(m, i, sl, q[ci.state0 + i]);
             T t[6], z[6];
-            ad_inv_apply(tl, fb, t);           // A_i Fb_{i-1}
+            ad_inv_apply(tl, fb, t);           // A_i Fb_p(i)
             T qf = T(0);
-            if (i > 0) {
+            if (has_parent) {
                 ad_z(t, z);
 #pragma unroll
                 for (int c = 0; c < 6; ++c) qf -= z[c] * w(i, VJP_F + c);
@@ -217,8 +308,10 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
         T ab[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
         T vb[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
         Pose<T> tn = pose_identity<T>();
+        bool carry = false;
         for (int i = n - 1; i >= 0; --i) {
             const int64_t st = ci.state0 + i;
+            const int32_t code = code_of(i);
             const Inertia<T> j = m.inertia_il(i, sl);
             T fb[6], v[6], a[6];
 #pragma unroll
@@ -228,12 +321,21 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
                 a[c] = w(i, VJP_A + c);
             }
             T na[6], nv[6];
-            if (i + 1 < n) {
+            if (TREE ? carry : i + 1 < n) {
                 wrench_to_parent(tn, ab, na);
                 wrench_to_parent(tn, vb, nv);
             } else {
 #pragma unroll
                 for (int c = 0; c < 6; ++c) na[c] = nv[c] = T(0);
+            }
+            if constexpr (TREE) {
+                if (code & TREE_BRANCH) {              // the other children's terms, summed
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) {
+                        na[c] += w(i, VJP_WB + c);
+                        nv[c] += w(i, VJP_WB + 6 + c);
+                    }
+                }
             }
             T jf[6];
             inertia_apply(j, fb, jf);
@@ -266,6 +368,21 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
             gq[st] = accumulate ? gq[st] - gq_id : -gq_id;
             gqd[st] = accumulate ? gqd[st] - gqd_id : -gqd_id;
             tn = pose_il(m, i, sl, q[st]);
+            if constexpr (TREE) {
+                carry = (code & TREE_CHAIN) != 0;
+                const int p = tree_parent(code);
+                if (!carry && p >= 0) {
+                    const bool first = (code & TREE_FIRST) != 0;
+                    T x[6], y[6];
+                    wrench_to_parent(tn, ab, x);
+                    wrench_to_parent(tn, vb, y);
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) {
+                        add_into(&w(p, VJP_WB + c), x[c], first);
+                        add_into(&w(p, VJP_WB + 6 + c), y[c], first);
+                    }
+                }
+            }
         }
     }
 }
@@ -297,8 +414,12 @@ template <typename T>
 hipError_t launch_fd_vjp(const ModelView<T>& m, const ChainMap& cm, int nmax, const T* q, const T* qd, const T* qdd,
                          const T* gqdd, T* gq, T* gqd, T* gtau, int accumulate, T* ws, hipStream_t st) {
     if (cm.batch <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_fd_vjp<T>), dim3((cm.batch + 63) / 64), dim3(64), 0, st, m, cm, nmax, q, qd, qdd, gqdd, gq,
-                       gqd, gtau, accumulate, ws);
+    if (m.tree)
+        hipLaunchKernelGGL((k_fd_vjp<T, true>), dim3((cm.batch + 63) / 64), dim3(64), 0, st, m, cm, nmax, q, qd, qdd,
+                           gqdd, gq, gqd, gtau, accumulate, ws);
+    else
+        hipLaunchKernelGGL((k_fd_vjp<T, false>), dim3((cm.batch + 63) / 64), dim3(64), 0, st, m, cm, nmax, q, qd,
+                           qdd, gqdd, gq, gqd, gtau, accumulate, ws);
     return hipGetLastError();
 }
 

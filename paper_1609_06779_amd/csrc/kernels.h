@@ -49,7 +49,7 @@ hipError_t launch_abia_persistent(const ModelView<T>& m, const ChainMap& cm, int
                                   const int32_t* slot_robot, bool stream_model, hipStream_t st);
 
 // reverse mode and the rollout step
-size_t vjp_workspace_elems(int batch, int nmax);
+size_t vjp_workspace_elems(int batch, int nmax, bool tree);
 template <typename T>
 hipError_t launch_fd_vjp(const ModelView<T>& m, const ChainMap& cm, int nmax, const T* q, const T* qd, const T* qdd,
                          const T* gqdd, T* gq, T* gqd, T* gtau, int accumulate, T* ws, hipStream_t st);

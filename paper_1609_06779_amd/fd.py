@@ -58,7 +58,7 @@ class Model:
     ``robots`` needs the per-link arrays n_links, axis, home_rot, offset, mass,
     com, inertia and a gravity 3-vector (packed robot after robot); an optional
     ``parent`` array (parent of each link within its robot, -1 = base) makes
-    the robots branched. Branched models run the articulated-body algorithm only.
+    the robots branched. Branched models run every path but the CFA (see the C header).
     """
 
     def __init__(self, robots, dtype: str = "f64", device=None):

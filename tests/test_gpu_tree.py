@@ -184,7 +184,7 @@ def test_explicit_serial_parents_take_the_chain_kernel(fdm, dev):
 
 
 def test_tree_model_rejects_the_chain_only_entry_points(fdm, dev):
-    """The CFA and the reverse mode are built for serial chains only."""
+    """The CFA is built for serial chains only."""
     from paper_1609_06779_amd import _lib
 
     lengths = [8] * 4
@@ -195,9 +195,6 @@ def test_tree_model_rejects_the_chain_only_entry_points(fdm, dev):
     assert m.max_links("cfa") == 0
     with pytest.raises(_lib.FdError) as e:
         m.forward(*args, batch=4, algo="cfa")
-    assert e.value.status == _lib.FD_ERR_UNSUPPORTED
-    with pytest.raises(_lib.FdError) as e:
-        m.backward(args[0], args[1], args[2], args[2], batch=4)
     assert e.value.status == _lib.FD_ERR_UNSUPPORTED
     assert m.max_links("abia") == 256 and m.max_links("jsiia") == 128
 
@@ -324,3 +321,151 @@ def test_full_size_tree_n64_b65536_sampled(fdm, dev):
     sub = rb.take(pick)
     idx = np.concatenate([np.arange(64 * k, 64 * k + 64) for k in pick])
     _check(got[idx], sub, q[idx], qd[idx], tau[idx], sub.offsets, "f64", "tree n64 b65536")
+
+
+# ---------------- reverse mode on trees ----------------
+
+def _chain_sums(x, off):
+    return np.add.reduceat(x, off[:-1])
+
+
+def _tree_set(kind, n, count, seed):
+    if kind == "not_depth_first":
+        rb = _not_depth_first(n, count)
+        q, qd, tau = synth.make_state([n] * count, seed=seed, cfg=5)
+        return rb, q, qd, tau
+    if kind == "shared":
+        rb = synth.make_tree_robots([n] * count, seed=seed, cfg=5, random_home=True, shared_topology=True)
+        q, qd, tau = synth.make_state([n] * count, seed=seed, cfg=5)
+        return rb, q, qd, tau
+    return _prep([n] * count, "f64", seed=seed)
+
+
+@pytest.mark.parametrize("kind", ["random", "shared", "not_depth_first"])
+@pytest.mark.parametrize("n", [2, 5, 16, 64, 100])
+def test_tree_vjp_adjoint_identity(fdm, dev, kind, n):
+    """fd_backward on trees: tau_bar = M^-1 g against the oracle's M, and
+    <VJP(g), v> = <g, JVP(v)> per tree against the oracle's complex-step JVP."""
+    count = 9
+    rb, q, qd, tau = _tree_set(kind, n, count, seed=300 + n)
+    off = rb.offsets
+    m = fdm.Model(rb, "f64", device=dev)
+    tq, tqd, ttau = (_t(a, "f64", dev) for a in (q, qd, tau))
+    qdd = m.forward(tq, tqd, ttau, batch=count, algo="abia")
+    ms = oracle.crba(rb, q)
+    kappa = np.array([np.linalg.cond(x) for x in ms])
+    rng = np.random.default_rng(n)
+    for _ in range(3):
+        g = rng.standard_normal(len(q))
+        gq, gqd, gtau = (x.cpu().numpy() for x in m.backward(tq, tqd, qdd, _t(g, "f64", dev), batch=count))
+        for b in range(count):
+            sl = slice(off[b], off[b + 1])
+            ref = np.linalg.solve(ms[b], g[sl])
+            bar = max(TOL["f64"], COND_FACTOR * kappa[b] * U["f64"])
+            assert np.linalg.norm(gtau[sl] - ref) <= bar * np.linalg.norm(ref), (b, "tau_bar")
+        dq, dqd, dtau = (rng.standard_normal(len(q)) for _ in range(3))
+        _, dqdd = oracle.fd_jvp(rb, q, qd, tau, dq, dqd, dtau)
+        lhs = _chain_sums(g * dqdd, off)
+        rhs = _chain_sums(gq * dq + gqd * dqd + gtau * dtau, off)
+        scale = _chain_sums(np.abs(g * dqdd), off) + _chain_sums(
+            np.abs(gq * dq) + np.abs(gqd * dqd) + np.abs(gtau * dtau), off)
+        bar = np.maximum(1e-11, COND_FACTOR * kappa * U["f64"])
+        assert np.all(np.abs(lhs - rhs) <= bar * scale), (np.abs(lhs - rhs) / scale).max()
+
+
+def test_tree_vjp_of_two_chains_merged_at_the_base(fdm, dev):
+    """Two chains merged into one tree from the base, their links interleaved,
+    give the chains' own gradients (permuted)."""
+    chains = synth.make_robots([3, 4], seed=5, cfg=5, random_home=True)
+    q, qd, tau = synth.make_state([3, 4], seed=5, cfg=5)
+    order = [(0, 0), (1, 0), (1, 1), (0, 1), (1, 2), (0, 2), (1, 3)]
+    off = chains.offsets
+    src = np.array([off[c] + i for c, i in order])
+    pos = {ci: t for t, ci in enumerate(order)}
+    parent = np.array([-1 if i == 0 else pos[(c, i - 1)] for c, i in order], np.int32)
+    tree = synth.Robots(n_links=np.array([7], np.int32), axis=chains.axis[src], home_rot=chains.home_rot[src],
+                        offset=chains.offset[src], mass=chains.mass[src], com=chains.com[src],
+                        inertia=chains.inertia[src], gravity=chains.gravity, parent=parent)
+    mc = fdm.Model(chains, "f64", device=dev)
+    mt = fdm.Model(tree, "f64", device=dev)
+    assert mt.branched
+    g = np.random.default_rng(7).standard_normal(7)
+    a = [_t(x, "f64", dev) for x in (q, qd, tau, g)]
+    toff = torch.from_numpy(np.asarray(off, np.int64)).to(dev)
+    qc = mc.forward(a[0], a[1], a[2], batch=2, algo="abia", offsets=toff)
+    rc = [x.cpu().numpy() for x in mc.backward(a[0], a[1], qc, a[3], batch=2, offsets=toff)]
+    b = [_t(x[src], "f64", dev) for x in (q, qd, tau, g)]
+    qt = mt.forward(b[0], b[1], b[2], batch=1, algo="abia")
+    rt = [x.cpu().numpy() for x in mt.backward(b[0], b[1], qt, b[3], batch=1)]
+    for x, y in zip(rt, rc):
+        np.testing.assert_allclose(x, y[src], rtol=1e-12, atol=1e-12)
+
+
+def _oracle_rollout(rb, q, qd, taus, dt, dq, dqd, dtaus):
+    """(q_T, qd_T) of semi-implicit Euler and their derivatives along a direction."""
+    q, qd, tq, tqd = q.copy(), qd.copy(), dq.copy(), dqd.copy()
+    for t in range(taus.shape[0]):
+        qdd, dqdd = oracle.fd_jvp(rb, q, qd, taus[t], tq, tqd, dtaus[t])
+        tqd = tqd + dt * dqdd
+        tq = tq + dt * tqd
+        qd = qd + dt * qdd
+        q = q + dt * qd
+    return q, qd, tq, tqd
+
+
+def test_tree_rollout_gradient_matches_oracle(fdm, dev):
+    """30 semi-implicit Euler steps on branched robots, dt = 1e-3, checkpoints every
+    10 steps, loss = sum(q_T^2 + qd_T^2): the gradient with respect to q_0, qd_0 and
+    every tau_t along random directions against the oracle's complex-step JVP."""
+    batch, n, steps, dt = 12, 24, 30, 1e-3
+    rb, q0, qd0, _ = _prep([n] * batch, "f64", seed=77)
+    taus = np.random.default_rng(8).standard_normal((steps, len(q0)))
+    off = rb.offsets
+    m = fdm.Model(rb, "f64", device=dev)
+    assert m.branched
+    tq0 = _t(q0, "f64", dev).requires_grad_(True)
+    tqd0 = _t(qd0, "f64", dev).requires_grad_(True)
+    ttaus = _t(taus, "f64", dev).requires_grad_(True)
+    qt, qdt = fdm.rollout(m, tq0, tqd0, ttaus, batch=batch, dt=dt, every=10, algo="abia")
+    ((qt ** 2).sum() + (qdt ** 2).sum()).backward()
+    g0, gd0, gt = tq0.grad.cpu().numpy(), tqd0.grad.cpu().numpy(), ttaus.grad.cpu().numpy()
+    rng = np.random.default_rng(9)
+    for _ in range(8):
+        dq, dqd = rng.standard_normal(len(q0)), rng.standard_normal(len(q0))
+        dtaus = rng.standard_normal(taus.shape)
+        rq, rqd, tq, tqd = _oracle_rollout(rb, q0, qd0, taus, dt, dq, dqd, dtaus)
+        exact = _chain_sums(2 * rq * tq + 2 * rqd * tqd, off)
+        ours = _chain_sums(g0 * dq + gd0 * dqd + (gt * dtaus).sum(axis=0), off)
+        scale = _chain_sums(np.abs(g0 * dq) + np.abs(gd0 * dqd) + np.abs(gt * dtaus).sum(axis=0), off)
+        assert np.all(np.abs(ours - exact) <= 1e-10 * (1 + np.maximum(np.abs(exact), scale))), \
+            np.abs(ours - exact).max()
+    np.testing.assert_allclose(qt.detach().cpu().numpy(), rq, rtol=0, atol=1e-10 * (1 + np.abs(rq).max()))
+
+
+def test_tree_vjp_full_size_sampled(fdm, dev):
+    """65536 random trees of 64 links (the headline shape): sampled trees against
+    the oracle through the adjoint identity, and every gradient finite."""
+    batch, n = 65536, 64
+    lengths = [n] * batch
+    rb = synth.make_tree_robots(lengths, seed=11, cfg=2)
+    q, qd, tau = synth.make_state(lengths, seed=11, cfg=2)
+    m = fdm.Model(rb, "f64", device=dev)
+    tq, tqd, ttau = (_t(a, "f64", dev) for a in (q, qd, tau))
+    qdd = m.forward(tq, tqd, ttau, batch=batch, algo="abia")
+    g = np.random.default_rng(12).standard_normal(len(q))
+    gq, gqd, gtau = (x.cpu().numpy() for x in m.backward(tq, tqd, qdd, _t(g, "f64", dev), batch=batch))
+    assert np.all(np.isfinite(gq)) and np.all(np.isfinite(gqd)) and np.all(np.isfinite(gtau))
+    pick = np.array([0, 1, 4095, 33333, 65535])
+    sub = rb.take(pick)
+    idx = np.concatenate([np.arange(n * b, n * b + n) for b in pick])
+    off = sub.offsets
+    rng = np.random.default_rng(13)
+    dq, dqd, dtau = (rng.standard_normal(len(idx)) for _ in range(3))
+    _, dqdd = oracle.fd_jvp(sub, q[idx], qd[idx], tau[idx], dq, dqd, dtau)
+    lhs = _chain_sums(g[idx] * dqdd, off)
+    rhs = _chain_sums(gq[idx] * dq + gqd[idx] * dqd + gtau[idx] * dtau, off)
+    scale = _chain_sums(np.abs(g[idx] * dqdd), off) + _chain_sums(
+        np.abs(gq[idx] * dq) + np.abs(gqd[idx] * dqd) + np.abs(gtau[idx] * dtau), off)
+    kappa = np.array([np.linalg.cond(x) for x in oracle.crba(sub, q[idx])])
+    bar = np.maximum(1e-11, COND_FACTOR * kappa * U["f64"])
+    assert np.all(np.abs(lhs - rhs) <= bar * scale), (np.abs(lhs - rhs) / scale).max()

@@ -221,3 +221,25 @@ def test_a_tree_of_one_branch_is_the_serial_chain():
     tree = rb.take([0])
     tree.parent = np.arange(9, dtype=np.int32) - 1
     np.testing.assert_array_equal(oracle.fd(tree, q, qd, tau), oracle.fd(rb, q, qd, tau))
+
+
+def test_cfa_system_couples_siblings_on_trees():
+    """On a tree, A = W^T (I - Gamma) J^-1 (I - Gamma)^T W has a nonzero block exactly
+    where two joints share a link: joint and parent joint, and any two siblings
+    (through their common parent's J^-1; the base has none). So the CFA's system
+    is not block tri-diagonal on a tree, nor tree-structured."""
+    n = 7
+    # 0 - 1 - 2, and 3, 4 hang from 1 (siblings of 2); 5 hangs from the base; 6 from 5
+    parent = np.array([-1, 0, 1, 1, 1, -1, 5], np.int32)
+    rb = synth.make_robots([n], seed=8, random_home=True)
+    rb.parent = parent
+    q = synth.make_state([n], seed=8)[0]
+    _, _, _, a, _, _ = dense.cfa_matrices(dense.Chain(rb, 0, n), q)
+    for i in range(n):
+        for k in range(n):
+            block = a[5 * i:5 * i + 5, 5 * k:5 * k + 5]
+            share = i == k or parent[i] == k or parent[k] == i or (parent[i] == parent[k] >= 0)
+            if share:
+                assert np.abs(block).max() > 1e-6, (i, k)
+            else:
+                assert np.abs(block).max() < 1e-12, (i, k)
