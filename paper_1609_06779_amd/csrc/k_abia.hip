@@ -137,6 +137,7 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
     }
 
     // sweep 2
+    // link i+1's terms for link i; trees hold them already moved into frame i
     T fc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};   // F_{i+1} (frame i+1)
     T pc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};   // p_{i+1} + h_{i+1} u_{i+1} / D_{i+1} (frame i+1)
     T pi[36];                                          // Jh_{i+1} - h h^T / D (frame i+1)
@@ -152,7 +153,15 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
         for (int c = 0; c < 6; ++c) f[c] = ld_ws<NT>(wsp(i, c));
         inertia_to_mat6(m.template inertia_il<NT>(i, ci.slot), jh);
         const int32_t code = TREE ? m.template tree_il<NT>(i, ci.slot) : 0;
-        if (TREE ? carry : i + 1 < n) {
+        if (TREE && carry) {                           // terms already in this link's frame
+#pragma unroll
+            for (int c = 0; c < 36; ++c) jh[c] += pi[c];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                f[c] += fc[c];
+                pp[c] = pc[c];
+            }
+        } else if (!TREE && i + 1 < n) {
             wrench_to_parent(tn, fc, fp);
             wrench_to_parent(tn, pc, pp);
             T y[36];
@@ -203,32 +212,37 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
         }
         tn = link_pose_at<NT>(m, i, ci.slot, q[st]);
         if constexpr (TREE) {
+            // Move the terms into the parent's frame here, once per link, on
+            // every lane: the parent takes them from registers (chain step) or
+            // from its record, and only the record update diverges.
+            T x[6], y[36];
+            wrench_to_parent(tn, fc, x);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) fc[c] = x[c];
+            wrench_to_parent(tn, pc, x);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) pc[c] = x[c];
+            congruence_to_parent(tn, pi, y);
+#pragma unroll
+            for (int c = 0; c < 36; ++c) pi[c] = y[c];
             carry = (code & TREE_CHAIN) != 0;
             const int p = tree_parent(code);
             if (!carry && p >= 0) {                    // hand the terms to a branch point now
                 const bool first = (code & TREE_FIRST) != 0;
-                T x[6];
-                wrench_to_parent(tn, fc, x);
 #pragma unroll
                 for (int c = 0; c < 6; ++c) {
                     T* d = wsp(p, ABIA_WB + c);
-                    st_ws<NT && ABIA_BRANCH_NT>(first ? x[c] : x[c] + ld_ws<NT && ABIA_BRANCH_NT>(d), d);
+                    st_ws<NT && ABIA_BRANCH_NT>(first ? fc[c] : fc[c] + ld_ws<NT && ABIA_BRANCH_NT>(d), d);
+                    d = wsp(p, ABIA_WB + 6 + c);
+                    st_ws<NT && ABIA_BRANCH_NT>(first ? pc[c] : pc[c] + ld_ws<NT && ABIA_BRANCH_NT>(d), d);
                 }
-                wrench_to_parent(tn, pc, x);
-#pragma unroll
-                for (int c = 0; c < 6; ++c) {
-                    T* d = wsp(p, ABIA_WB + 6 + c);
-                    st_ws<NT && ABIA_BRANCH_NT>(first ? x[c] : x[c] + ld_ws<NT && ABIA_BRANCH_NT>(d), d);
-                }
-                T y[36];
-                congruence_to_parent(tn, pi, y);
                 int k = ABIA_WB + 12;
 #pragma unroll
                 for (int r = 0; r < 6; ++r)
 #pragma unroll
                     for (int c = r; c < 6; ++c, ++k) {
                         T* d = wsp(p, k);
-                        st_ws<NT && ABIA_BRANCH_NT>(first ? y[6 * r + c] : y[6 * r + c] + ld_ws<NT && ABIA_BRANCH_NT>(d), d);
+                        st_ws<NT && ABIA_BRANCH_NT>(first ? pi[6 * r + c] : pi[6 * r + c] + ld_ws<NT && ABIA_BRANCH_NT>(d), d);
                     }
             }
         }

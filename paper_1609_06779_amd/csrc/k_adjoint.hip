@@ -122,7 +122,12 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
             const int32_t code = code_of(i);
             T jh[36], pp[6];
             inertia_to_mat6(m.inertia_il(i, sl), jh);
-            if (TREE ? carry : i + 1 < n) {
+            if (TREE && carry) {                       // terms already in this link's frame
+#pragma unroll
+                for (int c = 0; c < 36; ++c) jh[c] += pi[c];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) pp[c] = pc[c];
+            } else if (!TREE && i + 1 < n) {
                 wrench_to_parent(tn, pc, pp);
                 T y[36];
                 congruence_up(tn, pi, y);
@@ -163,20 +168,25 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
             for (int c = 0; c < 6; ++c) pc[c] = pp[c] + h[c] * u * dinv;
             tn = pose_il(m, i, sl, q[st]);
             if constexpr (TREE) {
+                // into the parent's frame on every lane; only the record update diverges
+                T x[6], y[36];
+                wrench_to_parent(tn, pc, x);
+                congruence_up(tn, pi, y);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) pc[c] = x[c];
+#pragma unroll
+                for (int c = 0; c < 36; ++c) pi[c] = y[c];
                 carry = (code & TREE_CHAIN) != 0;
                 const int p = tree_parent(code);
                 if (!carry && p >= 0) {                // hand the terms to a branch point now
                     const bool first = (code & TREE_FIRST) != 0;
-                    T x[6], y[36];
-                    wrench_to_parent(tn, pc, x);
 #pragma unroll
-                    for (int c = 0; c < 6; ++c) add_into(&w(p, VJP_WB + c), x[c], first);
-                    congruence_up(tn, pi, y);
+                    for (int c = 0; c < 6; ++c) add_into(&w(p, VJP_WB + c), pc[c], first);
                     int k = VJP_WB + 6;
 #pragma unroll
                     for (int r = 0; r < 6; ++r)
 #pragma unroll
-                        for (int c = r; c < 6; ++c, ++k) add_into(&w(p, k), y[6 * r + c], first);
+                        for (int c = r; c < 6; ++c, ++k) add_into(&w(p, k), pi[6 * r + c], first);
                 }
             }
         }
@@ -248,7 +258,10 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
             T f[6], fp[6];
 #pragma unroll
             for (int c = 0; c < 6; ++c) f[c] = w(i, VJP_F + c);
-            if (TREE ? carry : i + 1 < n) {
+            if (TREE && carry) {                       // already in this link's frame
+#pragma unroll
+                for (int c = 0; c < 6; ++c) f[c] += fc[c];
+            } else if (!TREE && i + 1 < n) {
                 wrench_to_parent(tn, fc, fp);
 #pragma unroll
                 for (int c = 0; c < 6; ++c) f[c] += fp[c];
@@ -260,13 +273,13 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
             }
             tn = pose_il(m, i, sl, q[ci.state0 + i]);
             if constexpr (TREE) {
+                wrench_to_parent(tn, f, fc);
                 const int32_t code = code_of(i);
                 carry = (code & TREE_CHAIN) != 0;
                 const int p = tree_parent(code);
                 if (!carry && p >= 0) {                // into the parent's f_p (+ its other children's terms)
-                    wrench_to_parent(tn, f, fp);
 #pragma unroll
-                    for (int c = 0; c < 6; ++c) w(p, VJP_F + c) += fp[c];
+                    for (int c = 0; c < 6; ++c) w(p, VJP_F + c) += fc[c];
                 }
             }
         }
@@ -321,7 +334,13 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
                 a[c] = w(i, VJP_A + c);
             }
             T na[6], nv[6];
-            if (TREE ? carry : i + 1 < n) {
+            if (TREE && carry) {                       // terms already in this link's frame
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    na[c] = ab[c];
+                    nv[c] = vb[c];
+                }
+            } else if (!TREE && i + 1 < n) {
                 wrench_to_parent(tn, ab, na);
                 wrench_to_parent(tn, vb, nv);
             } else {
@@ -369,17 +388,22 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
             gqd[st] = accumulate ? gqd[st] - gqd_id : -gqd_id;
             tn = pose_il(m, i, sl, q[st]);
             if constexpr (TREE) {
+                T x[6], y[6];
+                wrench_to_parent(tn, ab, x);
+                wrench_to_parent(tn, vb, y);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    ab[c] = x[c];
+                    vb[c] = y[c];
+                }
                 carry = (code & TREE_CHAIN) != 0;
                 const int p = tree_parent(code);
                 if (!carry && p >= 0) {
                     const bool first = (code & TREE_FIRST) != 0;
-                    T x[6], y[6];
-                    wrench_to_parent(tn, ab, x);
-                    wrench_to_parent(tn, vb, y);
 #pragma unroll
                     for (int c = 0; c < 6; ++c) {
-                        add_into(&w(p, VJP_WB + c), x[c], first);
-                        add_into(&w(p, VJP_WB + 6 + c), y[c], first);
+                        add_into(&w(p, VJP_WB + c), ab[c], first);
+                        add_into(&w(p, VJP_WB + 6 + c), vb[c], first);
                     }
                 }
             }
