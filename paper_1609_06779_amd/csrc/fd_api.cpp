@@ -471,10 +471,12 @@ fd_status_t fd_backward(const fd_model_t* m, const fd_batch_t* b, const void* q,
     if (m->dtype == FD_F64)
         return from_hip(fdk::launch_fd_vjp<double>(view<double>(m), p.cm, p.nmax, (const double*)q, (const double*)qd,
                                                    (const double*)qdd, (const double*)gqdd, (double*)gq, (double*)gqd,
-                                                   (double*)gtau, accumulate, (double*)ws, st));
+                                                   (double*)gtau, accumulate, (double*)ws,
+                                                   stream_model(m, b->batch, p.nmax), st));
     return from_hip(fdk::launch_fd_vjp<float>(view<float>(m), p.cm, p.nmax, (const float*)q, (const float*)qd,
                                               (const float*)qdd, (const float*)gqdd, (float*)gq, (float*)gqd,
-                                              (float*)gtau, accumulate, (float*)ws, st));
+                                              (float*)gtau, accumulate, (float*)ws,
+                                              stream_model(m, b->batch, p.nmax), st));
 }
 
 fd_status_t fd_euler_step(fd_dtype_t dtype, int64_t count, double dt, const void* q, const void* qd, const void* qdd,

@@ -20,7 +20,11 @@
 //     (dID/dqd)^T lambda |_i = S . Vb_i + S . ad_{V_i}^T ab_i
 //     (dID/dq)^T lambda |_i  = -Vb_i . ad_S V_i - ab_i . ad_S (a_i - ad_{V_i}(S qd_i))
 //                              - (ad_S A_i Fb_{i-1}) . F_i
-// using d A_i / d q_i = -ad_S A_i. One lane per chain, robot-interleaved model.
+// using d A_i / d q_i = -ad_S A_i. One lane per chain, robot-interleaved model,
+// three sweeps over the links: A (backward) the articulated-body inertias for
+// lambda; B (forward) lambda, Fb and the recomputed V, a, f; CE (backward) F,
+// ab, Vb and the gradients. Fb needs only lambda, so it rides with the forward
+// recursions, and F runs backward like ab and Vb, so those share one sweep.
 //
 // Branched robots (trees): i - 1 reads p(i) in the forward recursions, and the
 // backward ones sum the terms A_c^T (.) of all children c of i, as in the
@@ -37,15 +41,16 @@
 namespace fdk {
 
 // workspace fields per link (block-interleaved like the ABIA workspace)
-constexpr int VJP_HD = 0;      // h / D (6), then lambda (field 0) and the force-term q_bar (field 1)
+constexpr int VJP_HD = 0;      // h / D (6), written in sweep A
+constexpr int VJP_FB = 0;      // then Fb (6), written over h / D in sweep B
 constexpr int VJP_UD = 6;      // u / D
 constexpr int VJP_V = 7;       // V (6)
 constexpr int VJP_A = 13;      // a (6)
-constexpr int VJP_F = 19;      // f -> F -> Fb (6)
+constexpr int VJP_F = 19;      // f (6); trees add the children's A_c^T F_c into it
 constexpr int VJP_FIELDS = 25;
-// Trees add a branch-point record after those 25 fields, reused phase by phase:
+// Trees add a branch-point record after those 25 fields, reused sweep by sweep:
 // A: the children's p terms (6) and Jh - h h^T / D (21, upper triangle by rows);
-// B: the acceleration of the M^-1 g recursion (6); E: the children's ab (6) and vb (6).
+// B: the acceleration of the M^-1 g recursion (6); CE: the children's ab (6) and vb (6).
 constexpr int VJP_WB = VJP_FIELDS;
 constexpr int VJP_TREE_FIELDS = VJP_FIELDS + 27;
 template <bool TREE> constexpr int vjp_fields() { return TREE ? VJP_TREE_FIELDS : VJP_FIELDS; }
@@ -55,10 +60,10 @@ size_t vjp_workspace_elems(int batch, int nmax, bool tree) {
     return blocks * (size_t)nmax * (tree ? VJP_TREE_FIELDS : VJP_FIELDS) * 64;
 }
 
-template <typename T>
+template <bool NT, typename T>
 __device__ __forceinline__ Pose<T> pose_il(const ModelView<T>& m, int i, int slot, T q) {
     T rh[9], p[3];
-    m.home_il(i, slot, rh, p);
+    m.template home_il<NT>(i, slot, rh, p);
     return joint_pose(rh, p, q);
 }
 
@@ -87,7 +92,7 @@ template <typename T> __device__ __forceinline__ void ad_z(const T x[6], T y[6])
 // Adds x (or stores it, when first) into the workspace entry d.
 template <typename T> __device__ __forceinline__ void add_into(T* d, T x, bool first) { *d = first ? x : *d + x; }
 
-template <typename T, bool TREE>
+template <typename T, bool TREE, bool NT>
 __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int nmax, const T* __restrict__ q,
                                                const T* __restrict__ qd, const T* __restrict__ qdd,
                                                const T* __restrict__ gqdd, T* __restrict__ gq,
@@ -107,6 +112,10 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
     const int sl = ci.slot;
     T* wsb = ws + (size_t)blockIdx.x * nmax * vjp_fields<TREE>() * 64 + lane;
     auto w = [&](int i, int f) -> T& { return wsb[((size_t)i * vjp_fields<TREE>() + f) * 64]; };
+    // per-link fields stream (NT) when the launch outgrows the last-level cache;
+    // branch-point records and the tree's F updates keep the default policy
+    auto ldw = [&](int i, int f) -> T { return ld_ws<NT>(&w(i, f)); };
+    auto stw = [&](int i, int f, T v) { st_ws<NT>(v, &w(i, f)); };
     auto code_of = [&](int i) -> int32_t { return TREE ? m.template tree_il<false>(i, sl) : 0; };
 
     // A: articulated-body inertias and the p recursion with tau_delta := g
@@ -121,7 +130,7 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
             const int64_t st = ci.state0 + i;
             const int32_t code = code_of(i);
             T jh[36], pp[6];
-            inertia_to_mat6(m.inertia_il(i, sl), jh);
+            inertia_to_mat6(m.template inertia_il<NT>(i, sl), jh);
             if (TREE && carry) {                       // terms already in this link's frame
 #pragma unroll
                 for (int c = 0; c < 36; ++c) jh[c] += pi[c];
@@ -158,15 +167,15 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
 #pragma unroll
             for (int c = 0; c < 6; ++c) h[c] = jh[6 * c + 2];
 #pragma unroll
-            for (int c = 0; c < 6; ++c) w(i, VJP_HD + c) = h[c] * dinv;
-            w(i, VJP_UD) = u * dinv;
+            for (int c = 0; c < 6; ++c) stw(i, VJP_HD + c, h[c] * dinv);
+            stw(i, VJP_UD, u * dinv);
 #pragma unroll
             for (int rr = 0; rr < 6; ++rr)
 #pragma unroll
                 for (int c = 0; c < 6; ++c) pi[6 * rr + c] = jh[6 * rr + c] - h[rr] * h[c] * dinv;
 #pragma unroll
             for (int c = 0; c < 6; ++c) pc[c] = pp[c] + h[c] * u * dinv;
-            tn = pose_il(m, i, sl, q[st]);
+            tn = pose_il<NT>(m, i, sl, q[st]);
             if constexpr (TREE) {
                 // into the parent's frame on every lane; only the record update diverges
                 T x[6], y[36];
@@ -191,9 +200,11 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
             }
         }
     }
-    // B: lambda, and the inverse dynamics forward sweep at the given qdd
+    // B (forward): lambda, the force adjoint Fb_i = lambda_i S + A_i Fb_p(i), and
+    // the inverse dynamics recursions at the given qdd
     {
         T acc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+        T fb[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
         T v[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
         T a[6] = {T(0), T(0), T(0), -m.g[0], -m.g[1], -m.g[2]};
         for (int i = 0; i < n; ++i) {
@@ -205,22 +216,29 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
 #pragma unroll
                     for (int c = 0; c < 6; ++c) {
                         acc[c] = p < 0 ? T(0) : w(p, VJP_WB + c);
-                        v[c] = p < 0 ? T(0) : w(p, VJP_V + c);
-                        a[c] = p < 0 ? (c < 3 ? T(0) : -m.g[c - 3]) : w(p, VJP_A + c);
+                        fb[c] = p < 0 ? T(0) : ldw(p, VJP_FB + c);
+                        v[c] = p < 0 ? T(0) : ldw(p, VJP_V + c);
+                        a[c] = p < 0 ? (c < 3 ? T(0) : -m.g[c - 3]) : ldw(p, VJP_A + c);
                     }
                 }
             }
-            const Pose<T> tl = pose_il(m, i, sl, q[st]);
+            const Pose<T> tl = pose_il<NT>(m, i, sl, q[st]);
             T t[6];
             ad_inv_apply(tl, acc, t);
-            T lam = w(i, VJP_UD);
+            T lam = ldw(i, VJP_UD);
 #pragma unroll
-            for (int c = 0; c < 6; ++c) lam -= w(i, VJP_HD + c) * t[c];
+            for (int c = 0; c < 6; ++c) lam -= ldw(i, VJP_HD + c) * t[c];
             t[2] += lam;
 #pragma unroll
             for (int c = 0; c < 6; ++c) acc[c] = t[c];
-            w(i, VJP_HD) = lam;
             gtau[st] = accumulate ? gtau[st] + lam : lam;
+            ad_inv_apply(tl, fb, t);
+            t[2] += lam;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                fb[c] = t[c];
+                stw(i, VJP_FB + c, t[c]);               // h / D of this link is spent
+            }
             if constexpr (TREE) {
                 if (code & TREE_BRANCH) {
 #pragma unroll
@@ -240,84 +258,20 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
 #pragma unroll
             for (int c = 0; c < 6; ++c) a[c] = t[c];
             T f[6];
-            link_force(m.inertia_il(i, sl), v, a, f);
+            link_force(m.template inertia_il<NT>(i, sl), v, a, f);
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
-                w(i, VJP_V + c) = v[c];
-                w(i, VJP_A + c) = a[c];
-                w(i, VJP_F + c) = f[c];
+                stw(i, VJP_V + c, v[c]);
+                stw(i, VJP_A + c, a[c]);
+                stw(i, VJP_F + c, f[c]);
             }
         }
     }
-    // C: force recursion F_i = f_i + sum over children c of A_c^T F_c
+    // CE (backward): the force recursion F_i = f_i + sum over children c of A_c^T F_c,
+    // the force term of q_bar, and the adjoints of the velocity and acceleration
+    // recursions, all in one sweep
     {
-        T fc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-        Pose<T> tn = pose_identity<T>();
-        bool carry = false;
-        for (int i = n - 1; i >= 0; --i) {
-            T f[6], fp[6];
-#pragma unroll
-            for (int c = 0; c < 6; ++c) f[c] = w(i, VJP_F + c);
-            if (TREE && carry) {                       // already in this link's frame
-#pragma unroll
-                for (int c = 0; c < 6; ++c) f[c] += fc[c];
-            } else if (!TREE && i + 1 < n) {
-                wrench_to_parent(tn, fc, fp);
-#pragma unroll
-                for (int c = 0; c < 6; ++c) f[c] += fp[c];
-            }
-#pragma unroll
-            for (int c = 0; c < 6; ++c) {
-                fc[c] = f[c];
-                w(i, VJP_F + c) = f[c];
-            }
-            tn = pose_il(m, i, sl, q[ci.state0 + i]);
-            if constexpr (TREE) {
-                wrench_to_parent(tn, f, fc);
-                const int32_t code = code_of(i);
-                carry = (code & TREE_CHAIN) != 0;
-                const int p = tree_parent(code);
-                if (!carry && p >= 0) {                // into the parent's f_p (+ its other children's terms)
-#pragma unroll
-                    for (int c = 0; c < 6; ++c) w(p, VJP_F + c) += fc[c];
-                }
-            }
-        }
-    }
-    // D: Fb_i = lambda_i S + A_i Fb_p(i); force term of q_bar
-    {
-        T fb[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-        for (int i = 0; i < n; ++i) {
-            bool has_parent = i > 0;
-            if constexpr (TREE) {
-                const int32_t code = code_of(i);
-                const int p = tree_parent(code);
-                has_parent = p >= 0;
-                if (!(code & TREE_CHAIN)) {
-#pragma unroll
-                    for (int c = 0; c < 6; ++c) fb[c] = p < 0 ? T(0) : w(p, VJP_F + c);   // Fb_p, written at p
-                }
-            }
-            const Pose<T> tl = pose_il(m, i, sl, q[ci.state0 + i]);
-            T t[6], z[6];
-            ad_inv_apply(tl, fb, t);           // A_i Fb_p(i)
-            T qf = T(0);
-            if (has_parent) {
-                ad_z(t, z);
-#pragma unroll
-                for (int c = 0; c < 6; ++c) qf -= z[c] * w(i, VJP_F + c);
-            }
-            t[2] += w(i, VJP_HD);              // + lambda_i S
-#pragma unroll
-            for (int c = 0; c < 6; ++c) {
-                fb[c] = t[c];
-                w(i, VJP_F + c) = t[c];
-            }
-            w(i, VJP_HD + 1) = qf;
-        }
-    }
-    // E: adjoints of the velocity and acceleration recursions
-    {
+        T fc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};   // link i+1's F, ab, Vb for link i
         T ab[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
         T vb[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
         Pose<T> tn = pose_identity<T>();
@@ -325,36 +279,54 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
         for (int i = n - 1; i >= 0; --i) {
             const int64_t st = ci.state0 + i;
             const int32_t code = code_of(i);
-            const Inertia<T> j = m.inertia_il(i, sl);
-            T fb[6], v[6], a[6];
+            const Inertia<T> j = m.template inertia_il<NT>(i, sl);
+            T f[6], fb[6], v[6], a[6], na[6], nv[6];
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
-                fb[c] = w(i, VJP_F + c);
-                v[c] = w(i, VJP_V + c);
-                a[c] = w(i, VJP_A + c);
+                f[c] = ldw(i, VJP_F + c);
+                fb[c] = ldw(i, VJP_FB + c);
+                v[c] = ldw(i, VJP_V + c);
+                a[c] = ldw(i, VJP_A + c);
             }
-            T na[6], nv[6];
             if (TREE && carry) {                       // terms already in this link's frame
 #pragma unroll
                 for (int c = 0; c < 6; ++c) {
+                    f[c] += fc[c];
                     na[c] = ab[c];
                     nv[c] = vb[c];
                 }
             } else if (!TREE && i + 1 < n) {
+                T fp[6];
+                wrench_to_parent(tn, fc, fp);
                 wrench_to_parent(tn, ab, na);
                 wrench_to_parent(tn, vb, nv);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) f[c] += fp[c];
             } else {
 #pragma unroll
                 for (int c = 0; c < 6; ++c) na[c] = nv[c] = T(0);
             }
             if constexpr (TREE) {
-                if (code & TREE_BRANCH) {              // the other children's terms, summed
+                if (code & TREE_BRANCH) {              // the other children's ab and Vb, summed
 #pragma unroll
                     for (int c = 0; c < 6; ++c) {
                         na[c] += w(i, VJP_WB + c);
                         nv[c] += w(i, VJP_WB + 6 + c);
                     }
                 }
+            }
+            tn = pose_il<NT>(m, i, sl, q[st]);             // A_i
+            // force term of q_bar: -(ad_S A_i Fb_p(i)) . F_i
+            const int p = TREE ? tree_parent(code) : i - 1;
+            T gq_id = T(0);
+            if (p >= 0) {
+                T fbp[6], t[6], z[6];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) fbp[c] = ldw(p, VJP_FB + c);
+                ad_inv_apply(tn, fbp, t);
+                ad_z(t, z);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) gq_id -= z[c] * f[c];
             }
             T jf[6];
             inertia_apply(j, fb, jf);
@@ -381,27 +353,30 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
 #pragma unroll
             for (int c = 0; c < 6; ++c) am[c] = a[c] - avs[c];
             ad_z(am, za);
-            T gq_id = w(i, VJP_HD + 1);
 #pragma unroll
             for (int c = 0; c < 6; ++c) gq_id -= vb[c] * zv[c] + ab[c] * za[c];
             gq[st] = accumulate ? gq[st] - gq_id : -gq_id;
             gqd[st] = accumulate ? gqd[st] - gqd_id : -gqd_id;
-            tn = pose_il(m, i, sl, q[st]);
-            if constexpr (TREE) {
-                T x[6], y[6];
-                wrench_to_parent(tn, ab, x);
-                wrench_to_parent(tn, vb, y);
 #pragma unroll
-                for (int c = 0; c < 6; ++c) {
-                    ab[c] = x[c];
-                    vb[c] = y[c];
-                }
+            for (int c = 0; c < 6; ++c) fc[c] = f[c];
+            if constexpr (TREE) {
+                // into the parent's frame on every lane; only the parent updates diverge
+                T x[6];
+                wrench_to_parent(tn, fc, x);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) fc[c] = x[c];
+                wrench_to_parent(tn, ab, x);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) ab[c] = x[c];
+                wrench_to_parent(tn, vb, x);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) vb[c] = x[c];
                 carry = (code & TREE_CHAIN) != 0;
-                const int p = tree_parent(code);
                 if (!carry && p >= 0) {
                     const bool first = (code & TREE_FIRST) != 0;
 #pragma unroll
                     for (int c = 0; c < 6; ++c) {
+                        w(p, VJP_F + c) += fc[c];      // f_p plus its other children's terms
                         add_into(&w(p, VJP_WB + c), ab[c], first);
                         add_into(&w(p, VJP_WB + 6 + c), vb[c], first);
                     }
@@ -436,14 +411,18 @@ __global__ void k_euler_vjp(int64_t count, T dt, const T* __restrict__ gqn, cons
 
 template <typename T>
 hipError_t launch_fd_vjp(const ModelView<T>& m, const ChainMap& cm, int nmax, const T* q, const T* qd, const T* qdd,
-                         const T* gqdd, T* gq, T* gqd, T* gtau, int accumulate, T* ws, hipStream_t st) {
+                         const T* gqdd, T* gq, T* gqd, T* gtau, int accumulate, T* ws, bool stream, hipStream_t st) {
     if (cm.batch <= 0) return hipSuccess;
+    const dim3 grid((cm.batch + 63) / 64);
     if (m.tree)
-        hipLaunchKernelGGL((k_fd_vjp<T, true>), dim3((cm.batch + 63) / 64), dim3(64), 0, st, m, cm, nmax, q, qd, qdd,
-                           gqdd, gq, gqd, gtau, accumulate, ws);
+        hipLaunchKernelGGL((k_fd_vjp<T, true, false>), grid, dim3(64), 0, st, m, cm, nmax, q, qd, qdd, gqdd, gq, gqd,
+                           gtau, accumulate, ws);
+    else if (stream)
+        hipLaunchKernelGGL((k_fd_vjp<T, false, true>), grid, dim3(64), 0, st, m, cm, nmax, q, qd, qdd, gqdd, gq, gqd,
+                           gtau, accumulate, ws);
     else
-        hipLaunchKernelGGL((k_fd_vjp<T, false>), dim3((cm.batch + 63) / 64), dim3(64), 0, st, m, cm, nmax, q, qd,
-                           qdd, gqdd, gq, gqd, gtau, accumulate, ws);
+        hipLaunchKernelGGL((k_fd_vjp<T, false, false>), grid, dim3(64), 0, st, m, cm, nmax, q, qd, qdd, gqdd, gq,
+                           gqd, gtau, accumulate, ws);
     return hipGetLastError();
 }
 
@@ -466,7 +445,7 @@ hipError_t launch_euler_vjp(int64_t count, T dt, const T* gqn, const T* gqdn, T*
 
 #define FDK_ADJ_INST(T)                                                                                          \
     template hipError_t launch_fd_vjp<T>(const ModelView<T>&, const ChainMap&, int, const T*, const T*, const T*, \
-                                         const T*, T*, T*, T*, int, T*, hipStream_t);                           \
+                                         const T*, T*, T*, T*, int, T*, bool, hipStream_t);                     \
     template hipError_t launch_euler<T>(int64_t, T, const T*, const T*, const T*, T*, T*, hipStream_t);          \
     template hipError_t launch_euler_vjp<T>(int64_t, T, const T*, const T*, T*, T*, T*, hipStream_t);
 FDK_ADJ_INST(double)

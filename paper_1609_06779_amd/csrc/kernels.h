@@ -52,7 +52,8 @@ hipError_t launch_abia_persistent(const ModelView<T>& m, const ChainMap& cm, int
 size_t vjp_workspace_elems(int batch, int nmax, bool tree);
 template <typename T>
 hipError_t launch_fd_vjp(const ModelView<T>& m, const ChainMap& cm, int nmax, const T* q, const T* qd, const T* qdd,
-                         const T* gqdd, T* gq, T* gqd, T* gtau, int accumulate, T* ws, hipStream_t st);
+                         const T* gqdd, T* gq, T* gqd, T* gtau, int accumulate, T* ws, bool stream_model,
+                         hipStream_t st);
 template <typename T>
 hipError_t launch_euler(int64_t count, T dt, const T* q, const T* qd, const T* qdd, T* qn, T* qdn, hipStream_t st);
 template <typename T>

@@ -189,3 +189,39 @@ def test_rollout_full_size_sampled(fdm, dev):
     ours = _chain_sums(g0[idx] * dq + gd0[idx] * dqd + (gt[:, idx] * dtaus).sum(axis=0), off)
     scale = _chain_sums(np.abs(g0[idx] * dq) + np.abs(gd0[idx] * dqd) + np.abs(gt[:, idx] * dtaus).sum(axis=0), off)
     assert np.all(np.abs(ours - exact) <= 1e-10 * (1 + np.maximum(np.abs(exact), scale))), np.abs(ours - exact).max()
+
+
+def test_vjp_full_size_streaming_sampled(fdm, dev):
+    """65536 chains of 64 links: the launch outgrows the last-level cache, so the
+    kernel streams its model and workspace. Sampled chains against the oracle
+    through the adjoint identity, tau_bar against a dense solve, all finite."""
+    batch, n = 65536, 64
+    lengths = np.full(batch, n, np.int32)
+    rb = synth.make_robots(lengths, cfg=2)
+    q, qd, tau = synth.make_state(lengths, cfg=2)
+    model = fdm.Model(rb, "f64", device=dev)
+    tq, tqd, ttau = _t(q, dev), _t(qd, dev), _t(tau, dev)
+    qdd = model.forward(tq, tqd, ttau, batch=batch, algo="abia")
+    g = np.random.default_rng(21).standard_normal(len(q))
+    gq, gqd, gtau = (x.cpu().numpy() for x in model.backward(tq, tqd, qdd, _t(g, dev), batch=batch))
+    assert np.all(np.isfinite(gq)) and np.all(np.isfinite(gqd)) and np.all(np.isfinite(gtau))
+    pick = np.array([0, 1, 12345, 40000, 65535])
+    sub = rb.take(pick)
+    idx = np.concatenate([np.arange(n * b, n * b + n) for b in pick])
+    off = sub.offsets
+    ms = oracle.crba(sub, q[idx])
+    kappa = np.array([np.linalg.cond(m) for m in ms])
+    for k in range(len(pick)):
+        sl = slice(off[k], off[k + 1])
+        ref = np.linalg.solve(ms[k], g[idx][sl])
+        bar = max(1e-10, 16 * kappa[k] * 2.0 ** -53)
+        assert np.linalg.norm(gtau[idx][sl] - ref) <= bar * np.linalg.norm(ref), (pick[k], "tau_bar")
+    rng = np.random.default_rng(22)
+    dq, dqd, dtau = (rng.standard_normal(len(idx)) for _ in range(3))
+    _, dqdd = oracle.fd_jvp(sub, q[idx], qd[idx], tau[idx], dq, dqd, dtau)
+    lhs = _chain_sums(g[idx] * dqdd, off)
+    rhs = _chain_sums(gq[idx] * dq + gqd[idx] * dqd + gtau[idx] * dtau, off)
+    scale = _chain_sums(np.abs(g[idx] * dqdd), off) + _chain_sums(
+        np.abs(gq[idx] * dq) + np.abs(gqd[idx] * dqd) + np.abs(gtau[idx] * dtau), off)
+    bar = np.maximum(1e-11, 16 * kappa * 2.0 ** -53)
+    assert np.all(np.abs(lhs - rhs) <= bar * scale), (np.abs(lhs - rhs) / scale).max()
