@@ -428,6 +428,40 @@ def transfer_leg(dtype: str, reps: int = 10):
             "solves_per_s": batch / (ms * 1e-3), "bytes_over_pcie": 4 * len(q) * (8 if dtype == "f64" else 4)}
 
 
+def nsweep_leg(dtypes=("f64", "f32"), ns=(16, 32, 64, 128), batch: int = 65536, reps: int = 10):
+    """The three algorithms at `batch` chains of n links for each n, in FP64 and
+    FP32 (the headline workload's generator; FP32 robots rounded to FP32): ms per
+    launch and solves/s. JSIIA stops at its largest lane grid (128 links)."""
+    import torch
+
+    from paper_1609_06779_amd import fd, synth, tune
+
+    dev = torch.device("cuda:0")
+    out = {}
+    for dtype in dtypes:
+        tdt = torch.float64 if dtype == "f64" else torch.float32
+        out[dtype] = {}
+        for n in ns:
+            lengths = synth.uniform_lengths(batch, n)
+            rb = synth.make_robots(lengths, cfg=2)
+            if dtype == "f32":
+                rb = rb.astype_rounded(np.float32)
+            q, qd, tau = synth.make_state(lengths, cfg=2)
+            model = fd.Model(rb, dtype, device=dev)
+            tq, tqd, ttau = (torch.from_numpy(a).to(dev, tdt) for a in (q, qd, tau))
+            row = {}
+            for algo in ("abia", "jsiia", "cfa"):
+                if n > model.max_links(algo):
+                    continue
+                ms = tune.time_forward(model, tq, tqd, ttau, batch, algo, reps=reps)
+                row[algo] = {"ms_per_launch": ms, "solves_per_s": batch / (ms * 1e-3)}
+            out[dtype][str(n)] = row
+            model.close()
+            del tq, tqd, ttau
+            torch.cuda.empty_cache()
+    return out
+
+
 def levels_leg(dtype: str, ns=(16, 32, 64, 128), batch: int = 65536, reps: int = 20):
     """The two building blocks on their own at `batch` systems of n blocks each:
     the segmented scan of block bi-diagonal 6x6 systems (fd_scan6) and the
@@ -663,6 +697,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-transfer", action="store_true")
     ap.add_argument("--no-levels", action="store_true")
+    ap.add_argument("--no-nsweep", action="store_true")
     ap.add_argument("--only-step", action="store_true",
                     help="time the step alone: no legs and no CPU baseline (the profiled command)")
     ap.add_argument("--only-trees", action="store_true", help="run the branched-robot leg alone")
@@ -682,7 +717,7 @@ def main():
     args = ap.parse_args()
     if args.only_step:
         args.no_cpu = args.no_serve = args.no_ragged = args.no_tree = args.no_adjoint = args.no_transfer = True
-        args.no_levels = True
+        args.no_levels = args.no_nsweep = True
     wl = args.workload or f"fd_forward_n{args.n}_b{args.batch}_{args.dtype}"
     wl_flag = f" --workload {args.workload}" if args.workload else ""
     if args.trace_summary:
@@ -802,6 +837,9 @@ def main():
     if not args.no_transfer:
         print("[bench] transfer leg", file=sys.stderr, flush=True)
         result["host_transfer"] = transfer_leg(args.dtype)
+    if not args.no_nsweep:
+        print("[bench] n sweep leg", file=sys.stderr, flush=True)
+        result["n_sweep"] = nsweep_leg()
     if not args.no_levels:
         print("[bench] levels leg", file=sys.stderr, flush=True)
         result["levels"] = levels_leg(args.dtype)

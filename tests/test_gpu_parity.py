@@ -367,3 +367,86 @@ def test_length_bound_sizes_the_launch(fdm, dev, algo):
         with pytest.raises(_lib.FdError) as ei:
             model.forward(tq, tqd, ttau, batch=len(ids), algo=algo, robot_id=rid, offsets=toff, max_links=bad)
         assert ei.value.status == _lib.FD_ERR_INVALID_ARG
+
+
+def _skew_rows(v):
+    """Cross-product matrices of the rows of v: (k, 3) -> (k, 3, 3)."""
+    z = np.zeros(len(v))
+    return np.stack([np.stack([z, -v[:, 2], v[:, 1]], -1), np.stack([v[:, 2], z, -v[:, 0]], -1),
+                     np.stack([-v[:, 1], v[:, 0], z], -1)], 1)
+
+
+def _kappa_many(algo, rb, q, n, chains, chunk=1024):
+    """The error-model factor of `_kappa` for many chains of a uniform batch of n
+    links, chunk by chunk: cond_2(M), or for the CFA ||C||_2 ||M||_2 with C the
+    tri-diagonal S^T Phi S of `dense.cfa_c_matrix`, built for a whole chunk at once."""
+    out = []
+    for k0 in range(0, len(chains), chunk):
+        ch = chains[k0:k0 + chunk]
+        idx = (ch[:, None] * n + np.arange(n)).reshape(-1)
+        sub = rb.take(ch)
+        ms = np.stack(oracle.crba(sub, q[idx]))
+        ev = np.linalg.eigvalsh(ms)
+        if algo != "cfa":
+            out.append(ev[:, -1] / ev[:, 0])
+            continue
+        b = len(ch)
+        jinv, ad, s = [], [], []
+        for i in range(n):
+            li = ch * n + i
+            m = rb.mass[li][:, None, None]
+            it = rb.inertia[li]
+            ic = np.stack([np.stack([it[:, 0], it[:, 3], it[:, 4]], -1), np.stack([it[:, 3], it[:, 1], it[:, 5]], -1),
+                           np.stack([it[:, 4], it[:, 5], it[:, 2]], -1)], 1)
+            c = _skew_rows(rb.com[li])
+            j = np.zeros((b, 6, 6))
+            j[:, :3, :3] = ic - m * (c @ c)
+            j[:, :3, 3:] = m * c
+            j[:, 3:, :3] = -m * c
+            j[:, 3:, 3:] = m * np.eye(3)
+            jinv.append(np.linalg.inv(j))
+            kx = _skew_rows(rb.axis[li])
+            qq = q[li][:, None, None]
+            r = rb.home_rot[li].reshape(b, 3, 3) @ (np.eye(3) + np.sin(qq) * kx + (1.0 - np.cos(qq)) * (kx @ kx))
+            rt = r.transpose(0, 2, 1)
+            pt = -(rt @ rb.offset[li][:, :, None])[:, :, 0]
+            x = np.zeros((b, 6, 6))                  # Ad(T^-1) = ad_pose(R^T, -R^T p)
+            x[:, :3, :3] = rt
+            x[:, 3:, 3:] = rt
+            x[:, 3:, :3] = _skew_rows(pt) @ rt
+            ad.append(x)
+            s.append(np.concatenate([rb.axis[li], np.zeros((b, 3))], 1))
+        cm = np.zeros((b, n, n))
+        for i in range(n):
+            phi = jinv[i] + (ad[i] @ jinv[i - 1] @ ad[i].transpose(0, 2, 1) if i > 0 else 0.0)
+            cm[:, i, i] = np.einsum("bi,bij,bj->b", s[i], phi, s[i])
+            if i + 1 < n:
+                cm[:, i, i + 1] = cm[:, i + 1, i] = np.einsum("bi,bij,bj->b", s[i],
+                                                               -jinv[i] @ ad[i + 1].transpose(0, 2, 1), s[i + 1])
+        out.append(np.abs(np.linalg.eigvalsh(cm)).max(axis=1) * ev[:, -1])
+    return np.concatenate(out) if out else np.zeros(0)
+
+
+@pytest.mark.parametrize("n", [16, 32, 64, 128])
+def test_every_chain_at_65536(fdm, dev, n):
+    """65536 chains of n links (16 .. 128), FP64: every chain of every algorithm
+    against the oracle (all host threads). The forward error bar is 1e-10, or
+    the factorisation's error model for the chains above it."""
+    batch = 65536
+    lengths = synth.uniform_lengths(batch, n)
+    rb, q, qd, tau = _prep(lengths, "f64", cfg=2)
+    ref = oracle.fd(rb, q, qd, tau, threads=0)
+    off = rb.offsets
+    model = fdm.Model(rb, "f64", device=dev)
+    for algo in ALGOS:
+        if n > model.max_links(algo):
+            continue
+        got = _forward(fdm, dev, rb, q, qd, tau, "f64", algo, model=model)
+        assert np.all(np.isfinite(got)), algo
+        err = oracle.relative_error(got, ref, off)
+        over = np.nonzero(err > TOL["f64"])[0]
+        print(f"{algo} n={n}: {len(over)} of {batch} chains above 1e-10, worst {err.max():.2e}", flush=True)
+        if len(over):                              # the error model, for those chains only
+            bar = np.maximum(TOL["f64"], COND_FACTOR[algo] * _kappa_many(algo, rb, q, n, over) * U["f64"])
+            bad = over[~(err[over] <= bar)]
+            assert len(bad) == 0, f"{algo} n={n}: {len(bad)} chains over the bar (chain {bad[:5]})"
