@@ -683,8 +683,8 @@ def tree_leg(dtype: str, reps: int = 10, keys=TREE_WORKLOADS):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--batch", type=int, default=65536)
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
@@ -801,10 +801,11 @@ def main():
           flush=True)
     per_algo = {}
     for a in algos:
-        ms = float(np.mean([e[a][0].elapsed_time(e[a][1]) for e in ev]))
+        times = [e[a][0].elapsed_time(e[a][1]) for e in ev]
+        ms = float(np.mean(times))
         fl = 2.0 * fma_per_solve(a, args.n) * args.batch
-        per_algo[a] = {"ms_per_launch": ms, "solves_per_s": args.batch / (ms * 1e-3),
-                       "tflops": fl / (ms * 1e-3) / 1e12}
+        per_algo[a] = {"ms_per_launch": ms, "median_ms": float(np.median(times)), "min_ms": float(np.min(times)),
+                       "solves_per_s": args.batch / (ms * 1e-3), "tflops": fl / (ms * 1e-3) / 1e12}
     for a in algos:
         assert torch.isfinite(outs[a]).all().item(), f"{a} produced non-finite qdd"
     dominant = max(algos, key=lambda a: per_algo[a]["ms_per_launch"])
