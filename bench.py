@@ -149,13 +149,15 @@ def summarize_pmc(fetch_dir: str, write_dir: str, workload: str, commands, summa
 
 
 def summarize_flops(p1_dir: str, p2_dir: str, workload: str, commands, summary_cmd: str, bench_log: str,
-                    n: int, batch: int, dtype: str) -> str:
+                    n: int, batch: int, dtype: str, p3_dir=None) -> str:
     """Write profiles/<workload>_valu_flops.md from two rocprofv3 --pmc passes:
     SQ_INSTS_VALU_FLOPS_FP64 (FP64 flops per wave instruction: 2 per FMA, 1 per
     add or multiply), then SQ_INSTS_MFMA, SQ_INSTS_VALU and the FP64 FMA / MUL /
     ADD counts. Executed flops per launch = the flops counter x 64 lanes (masked
     lanes included); the time per launch is bench.py's HIP-event average from
-    `bench_log` (an unprofiled or trace-only run of the same step)."""
+    `bench_log` (an unprofiled or trace-only run of the same step). An optional
+    third pass (SQ_INSTS_LDS, SQ_LDS_BANK_CONFLICT, SQ_WAVES) adds the LDS
+    instructions per wave and the bank-conflict cycles per LDS instruction."""
     import csv
     import glob
     import re
@@ -168,11 +170,13 @@ def summarize_flops(p1_dir: str, p2_dir: str, workload: str, commands, summary_c
         return vals
 
     c1, c2 = load(p1_dir), load(p2_dir)
+    c3 = load(p3_dir) if p3_dir else {}
     events = {}
     for line in open(bench_log):
         if line.startswith("{"):
             events = {a: v["ms_per_launch"] for a, v in json.loads(line).get("per_algo", {}).items()}
     peak = PEAK_FLOPS[dtype] / 1e12
+    lds_rows = []
     lines = [f"# FP64 VALU work per launch: {workload}", "", "Commands:", "", "```", *commands, summary_cmd, "```", "",
              "Executed flops = `SQ_INSTS_VALU_FLOPS_FP64` x 64 lanes (it counts 2 per FMA and 1 per add or "
              "multiply, per wave instruction, so masked lanes are included). The algorithmic count is "
@@ -195,6 +199,16 @@ def summarize_flops(p1_dir: str, p2_dir: str, workload: str, commands, summary_c
         lines.append(f"| {algo} | `{k1.split('(')[0].replace('void ', '')}` | {ex / 1e9:.2f} | {alg / 1e9:.2f} | "
                      f"{ms:.3f} | {rate:.1f} | {rate / peak:.2f} | {mean(c2[k2], 'SQ_INSTS_MFMA'):.0f} | "
                      f"{f64 / mean(c2[k2], 'SQ_INSTS_VALU'):.2f} |")
+        k3 = next((k for k in c3 if re.search(pat, k)), None)
+        if k3:
+            waves = mean(c3[k3], "SQ_WAVES")
+            lds = mean(c3[k3], "SQ_INSTS_LDS")
+            lds_rows.append(f"| {algo} | {waves:.0f} | {lds / waves:.0f} | {mean(c2[k2], 'SQ_INSTS_VALU') / waves:.0f} | "
+                            f"{mean(c3[k3], 'SQ_LDS_BANK_CONFLICT') / max(lds, 1.0):.2f} |")
+    if lds_rows:
+        lines += ["", "LDS use (third pass; counters per launch, divided by the waves of the launch):", "",
+                  "| algorithm | waves | LDS instructions / wave | VALU instructions / wave | "
+                  "bank-conflict cycles / LDS instruction |", "|---|---|---|---|---|", *lds_rows]
     path = os.path.join(ROOT, "profiles", f"{workload}_valu_flops.md")
     with open(path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
@@ -712,6 +726,7 @@ def main():
     ap.add_argument("--trace-summary", metavar="TRACE_DIR",
                     help="summarise a rocprofv3 --kernel-trace --stats run into profiles/ and exit (no GPU use)")
     ap.add_argument("--bench-log", help="with --trace-summary or --flops-summary: output of the profiled bench.py run")
+    ap.add_argument("--lds-pass", metavar="P3_DIR", help="with --flops-summary: the LDS counter pass")
     ap.add_argument("--flops-summary", nargs=2, metavar=("P1_DIR", "P2_DIR"),
                     help="summarise the two FP64 VALU counter passes into profiles/ and exit (no GPU use)")
     args = ap.parse_args()
@@ -730,7 +745,8 @@ def main():
         print(summarize_flops(*args.flops_summary, wl, args.pmc_command,
                               f"python bench.py --flops-summary {' '.join(args.flops_summary)} --n {args.n} "
                               f"--batch {args.batch} --dtype {args.dtype}{wl_flag} --bench-log {args.bench_log} "
-                              f"--pmc-command ...", args.bench_log, args.n, args.batch, args.dtype))
+                              f"{' --lds-pass ' + args.lds_pass if args.lds_pass else ''} --pmc-command ...",
+                              args.bench_log, args.n, args.batch, args.dtype, args.lds_pass))
         return
     if args.pmc_summary:
         print(summarize_pmc(*args.pmc_summary, wl, args.pmc_command,
