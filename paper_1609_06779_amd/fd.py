@@ -111,7 +111,22 @@ class Model:
         return int(_lib.load().fd_max_links(self._h, _lib.ALGOS[algo]))
 
     # ---- batches ----
-    def _batch(self, batch: int, robot_id=None, offsets=None, max_links: int = 0) -> _lib.Batch:
+    def _batch(self, batch: int, robot_id=None, offsets=None, max_links: int = 0, state=()) -> _lib.Batch:
+        """The batch descriptor, after the size checks the library cannot make on
+        raw pointers: robot_id needs `batch` entries, offsets `batch + 1`, and with
+        no offsets on a model whose robots share one length n, every per-link
+        array in `state` needs batch * n entries (per-chain offsets live on the
+        device and are the caller's to keep within the arrays)."""
+        if robot_id is not None and robot_id.numel() < batch:
+            raise ValueError(f"robot_id has {robot_id.numel()} entries for a batch of {batch}")
+        if offsets is not None and offsets.numel() < batch + 1:
+            raise ValueError(f"offsets has {offsets.numel()} entries for a batch of {batch} (needs batch + 1)")
+        if offsets is None and len(self.n_links) and np.all(self.n_links == self.n_links[0]):
+            need = int(batch) * int(self.n_links[0])
+            for name, t in state:
+                if t is not None and t.numel() < need:
+                    raise ValueError(f"{name} has {t.numel()} entries; {batch} chains of {self.n_links[0]} "
+                                     f"links need {need}")
         b = _lib.Batch()
         b.batch = int(batch)
         b.max_links = int(max_links)
@@ -142,7 +157,8 @@ class Model:
         if out is None:
             out = torch.empty_like(q)
         _dev_tensor(out, dt, self.device, "out")
-        b = self._batch(batch, robot_id, offsets, max_links)
+        b = self._batch(batch, robot_id, offsets, max_links,
+                        state=(("q", q), ("qd", qd), ("tau", tau), ("out", out)))
         if workspace is None:
             workspace = self.workspace(batch, algo, robot_id, offsets, max_links)
         _lib.check(_lib.load().fd_forward(self._h, ctypes.byref(b), _ptr(q), _ptr(qd), _ptr(tau), _ptr(out),
@@ -164,7 +180,7 @@ class Model:
         for name, t in (("q", q), ("qd", qd), ("tau", tau)):
             _dev_tensor(t, dt, self.device, name)
         out = torch.empty_like(q) if out is None else _dev_tensor(out, dt, self.device, "out")
-        b = self._batch(batch, robot_id, offsets)
+        b = self._batch(batch, robot_id, offsets, state=(("q", q), ("qd", qd), ("tau", tau), ("out", out)))
         if workspace is None:
             workspace = self.persistent_workspace(batch, grid, robot_id, offsets)
         _lib.check(_lib.load().fd_forward_persistent(self._h, ctypes.byref(b), _ptr(q), _ptr(qd), _ptr(tau),
@@ -189,7 +205,9 @@ class Model:
         grad_q = torch.empty_like(q) if grad_q is None else _dev_tensor(grad_q, dt, self.device, "grad_q")
         grad_qd = torch.empty_like(q) if grad_qd is None else _dev_tensor(grad_qd, dt, self.device, "grad_qd")
         grad_tau = torch.empty_like(q) if grad_tau is None else _dev_tensor(grad_tau, dt, self.device, "grad_tau")
-        b = self._batch(batch, robot_id, offsets)
+        b = self._batch(batch, robot_id, offsets, state=(("q", q), ("qd", qd), ("qdd", qdd), ("grad_qdd", grad_qdd),
+                                                          ("grad_q", grad_q), ("grad_qd", grad_qd),
+                                                          ("grad_tau", grad_tau)))
         if workspace is None:
             workspace = self.backward_workspace(batch, robot_id, offsets)
         _lib.check(_lib.load().fd_backward(self._h, ctypes.byref(b), _ptr(q), _ptr(qd), _ptr(qdd), _ptr(grad_qdd),
@@ -224,9 +242,8 @@ class Model:
         qd = _dev_tensor(qd, dt, self.device, "qd")
         if qdd is not None:
             _dev_tensor(qdd, dt, self.device, "qdd")
-        if out is None:
-            out = torch.empty_like(q)
-        b = self._batch(batch, robot_id, offsets)
+        out = torch.empty_like(q) if out is None else _dev_tensor(out, dt, self.device, "out")
+        b = self._batch(batch, robot_id, offsets, state=(("q", q), ("qd", qd), ("qdd", qdd), ("out", out)))
         _lib.check(_lib.load().fd_inverse(self._h, ctypes.byref(b), _ptr(q), _ptr(qd), _ptr(qdd), int(bool(gravity)),
                                           _ptr(out), _stream(stream)), "fd_inverse")
         return out
@@ -235,9 +252,13 @@ class Model:
         """M(q) of every chain of a uniform batch, shape [batch, n, n]."""
         dt = self.torch_dtype
         q = _dev_tensor(q, dt, self.device, "q")
+        if len(self.n_links) and int(self.n_links[0]) != n:      # uniform batches: every chain has n_links[0]
+            raise ValueError(f"n = {n}, but the batch's chains have {int(self.n_links[0])} links")
         if out is None:
             out = torch.empty((batch, n, n), dtype=dt, device=self.device)
-        b = self._batch(batch, robot_id, None)
+        elif _dev_tensor(out, dt, self.device, "out").numel() < batch * n * n:
+            raise ValueError(f"out has {out.numel()} entries; {batch} matrices of {n} x {n} need {batch * n * n}")
+        b = self._batch(batch, robot_id, None, state=(("q", q),))
         _lib.check(_lib.load().fd_joint_inertia(self._h, ctypes.byref(b), _ptr(q), _ptr(out), _stream(stream)),
                    "fd_joint_inertia")
         return out

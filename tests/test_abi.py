@@ -113,3 +113,31 @@ def test_null_arguments(lib):
     fake = ctypes.c_void_p(8)   # never dereferenced: the length check fails first
     assert lib.fd_btd_solve6(0, 1, fake, 300, fake, fake, fake, fake, None, None) == _lib.FD_ERR_UNSUPPORTED
     assert lib.fd_max_links(None, 0) == 0
+
+
+def test_binding_checks_array_sizes_before_any_launch():
+    """The C ABI takes raw device pointers, so the binding checks what it can:
+    robot_id and offsets entries for the batch, and per-link arrays of a
+    uniform batch (batch * n entries). The checks run before the library is
+    called, so they need no GPU."""
+    torch = pytest.importorskip("torch")
+    from paper_1609_06779_amd import fd
+
+    class _Stub(fd.Model):
+        def __init__(self, n_links):
+            self.n_links = np.asarray(n_links, np.int32)
+            self.device = torch.device("cuda:0")
+            self._h = None
+
+    m = _Stub([8, 8, 8])
+    t = torch.empty(8 * 3)
+    with pytest.raises(ValueError, match="robot_id"):
+        m._batch(4, robot_id=torch.empty(3, dtype=torch.int32))
+    with pytest.raises(ValueError, match="offsets"):
+        m._batch(4, offsets=torch.empty(4, dtype=torch.int64))
+    with pytest.raises(ValueError, match="q has 24 entries"):
+        m._batch(4, state=(("q", t),))
+    assert m._batch(3, state=(("q", t),)).batch == 3
+    # robots of two lengths: the chain starts come from device offsets, so the
+    # binding has no size to check and leaves the batch to the library
+    assert _Stub([8, 5])._batch(2, state=(("q", torch.empty(1)),)).batch == 2
