@@ -322,6 +322,37 @@ def test_cfa_schur_complement_and_force_consistency(n):
         assert abs(minv[0, 0] - 1.0 / (sv @ j @ sv)) < 1e-12 / (sv @ j @ sv)
 
 
+@pytest.mark.parametrize("n", [2, 5])
+def test_cfa_result_does_not_depend_on_the_constraint_basis(n):
+    """Sec. III: W only has to span the complement of S at every joint (W^T S = 0,
+    full column rank); the paper leaves other choices open. Any such W_i' = W_i Q_i
+    (Q_i invertible, 5 x 5, not orthogonal here) turns A into Q^T A Q and B into
+    Q^T B, so M^-1 = C - B^T A^-1 B and qdd are unchanged. The kernels take the
+    canonical W_i = [e1 e2 e4 e5 e6] of their joint frames; the oracle's dense
+    form takes an SVD basis; this is the statement that both are the same CFA."""
+    rb = synth.make_robots([n], seed=93, random_home=True)
+    q, qd, tau = synth.make_state([n], seed=93)
+    ch = dense.Chain(rb, 0, n)
+    phi, w, s, a, b, c = dense.cfa_matrices(ch, q)
+    rng = np.random.default_rng(n)
+    qb = np.zeros((5 * n, 5 * n))
+    for i in range(n):
+        qb[5 * i:5 * i + 5, 5 * i:5 * i + 5] = rng.standard_normal((5, 5)) + 3.0 * np.eye(5)
+    w2 = w @ qb
+    np.testing.assert_allclose(w2.T @ s, 0, atol=1e-13)
+    a2, b2 = w2.T @ phi @ w2, w2.T @ phi @ s
+    minv1 = c - b.T @ np.linalg.solve(a, b)
+    minv2 = c - b2.T @ np.linalg.solve(a2, b2)
+    np.testing.assert_allclose(minv2, minv1, rtol=1e-9, atol=1e-10)
+    td = tau - oracle.rnea(rb, q, qd)
+    np.testing.assert_allclose(minv2 @ td, oracle.fd(rb, q, qd, tau), rtol=1e-9, atol=1e-9)
+    # and a W that is not a complement (it has a component along S) changes the result
+    w3 = w.copy()
+    w3[:, 0] += s[:, 0]
+    a3, b3 = w3.T @ phi @ w3, w3.T @ phi @ s
+    assert np.abs(c - b3.T @ np.linalg.solve(a3, b3) - minv1).max() > 1e-6
+
+
 def test_abia_single_link_is_axis_inertia():
     rb = synth.make_robots([1], seed=92)
     ch = dense.Chain(rb, 0, 1)
