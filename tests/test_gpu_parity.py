@@ -228,9 +228,12 @@ def test_empty_batch_and_workspace_errors(fdm, dev):
     with pytest.raises(_lib.FdError) as ei:
         model.forward(tq, tq, tq, batch=4, algo="abia", workspace=torch.empty(8, dtype=torch.uint8, device=dev))
     assert ei.value.status == _lib.FD_ERR_WORKSPACE
+    t30 = torch.zeros(30, dtype=torch.float64, device=dev)
     with pytest.raises(_lib.FdError) as ei:
-        model.forward(tq, tq, tq, batch=5, algo="cfa")          # more chains than robots
+        model.forward(t30, t30, t30, batch=5, algo="cfa")       # more chains than robots
     assert ei.value.status == _lib.FD_ERR_INVALID_ARG
+    with pytest.raises(ValueError, match="q has 24 entries"):   # the binding's size check, before any launch
+        model.forward(tq, tq, tq, batch=5, algo="cfa")
     big = synth.make_robots([200], cfg=5)
     mb = fdm.Model(big, "f64", device=dev)
     t200 = torch.zeros(200, dtype=torch.float64, device=dev)
