@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -29,6 +30,7 @@ struct fd_model {
     int32_t* d_slot_robot = nullptr;  // [num_robots] robot of each column
     bool tree = false;                // some robot is branched (a link's parent is not link i-1)
     bool depth_first = true;          // every robot's links are numbered depth-first (subtrees are runs)
+    bool shared_topology = true;      // robots of one length share one parent array
     int32_t* d_tree = nullptr;        // [nmax][num_robots] tree codes (see lanes.h), null without branches
 };
 
@@ -155,6 +157,13 @@ fd_algo_t pick_algo(const fd_model* m, int nmax, int batch) {
     if (!t.empty() && nmax >= 1 && nmax <= kMaxLinks) a = (fd_algo_t)t[nmax * 21 + log2_bucket(batch)];
     // branched robots: the CFA is built for serial chains, JSIIA for depth-first numbering
     if (m->tree && (a == FD_ALGO_CFA || (a == FD_ALGO_JSIIA && !m->depth_first))) a = FD_ALGO_ABIA;
+    // Robots of different topologies in one wavefront make the lane-per-chain
+    // ABIA diverge at every branch point of any of its lanes (65536 trees of 64
+    // links: 2.1 ms, against 0.66 ms with one shared topology); JSIIA puts one
+    // tree on a lane group and does not diverge (1.1 ms either way).
+    const int jmax = m->dtype == FD_F64 ? fdk::jsiia_max_np<double>() : fdk::jsiia_max_np<float>();
+    if (m->tree && !m->shared_topology && m->depth_first && a == FD_ALGO_ABIA && pow2_lanes(nmax) <= jmax)
+        a = FD_ALGO_JSIIA;
     return a;
 }
 
@@ -212,7 +221,8 @@ fd_status_t fd_init(const fd_model_desc_t* d, fd_dtype_t dtype, fd_model_t** out
         return FD_ERR_OUT_OF_MEMORY;
     }
     // topology: parent links and the tree codes (lanes.h)
-    bool tree = false, depth_first = true;
+    bool tree = false, depth_first = true, shared_topology = true;
+    std::map<int, int64_t> first_of_length;   // length -> start of the first robot of that length
     for (int64_t r = 0, s0 = 0; r < d->num_robots; s0 += d->n_links[r], ++r) {
         const int n = d->n_links[r];
         std::vector<int> par(n), size(n, 1);
@@ -226,6 +236,11 @@ fd_status_t fd_init(const fd_model_desc_t* d, fd_dtype_t dtype, fd_model_t** out
             int k = i - 1;
             while (k >= 0 && k != p) k = par[k];
             depth_first = depth_first && k == p;
+        }
+        const auto seen = first_of_length.emplace(n, s0);
+        if (!seen.second && d->parent) {
+            const int64_t f0 = seen.first->second;
+            for (int i = 0; i < n && shared_topology; ++i) shared_topology = d->parent[f0 + i] == d->parent[s0 + i];
         }
         for (int i = n - 1; i >= 1; --i)
             if (par[i] >= 0) size[par[i]] += size[i];
@@ -277,6 +292,7 @@ fd_status_t fd_init(const fd_model_desc_t* d, fd_dtype_t dtype, fd_model_t** out
     m->uniform = uni;
     m->tree = tree;
     m->depth_first = depth_first;
+    m->shared_topology = shared_topology;
     for (int k = 0; k < 3; ++k) m->g[k] = d->gravity[k];
     // interleaved columns: robots by decreasing length, ties in robot order, so a
     // model of equal lengths keeps its order and 64 consecutive columns hold

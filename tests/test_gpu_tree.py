@@ -469,3 +469,24 @@ def test_tree_vjp_full_size_sampled(fdm, dev):
     kappa = np.array([np.linalg.cond(x) for x in oracle.crba(sub, q[idx])])
     bar = np.maximum(1e-11, COND_FACTOR * kappa * U["f64"])
     assert np.all(np.abs(lhs - rhs) <= bar * scale), (np.abs(lhs - rhs) / scale).max()
+
+
+def test_auto_takes_jsiia_for_trees_of_mixed_topologies(fdm, dev):
+    """AUTO on branched robots: the tuned table's choice (the CFA mapped to ABIA)
+    while every robot of a length shares one topology; JSIIA when topologies
+    differ, where ABIA's lanes would diverge at every robot's branch points.
+    Checked bit for bit against the explicit algorithm."""
+    from paper_1609_06779_amd import tune
+
+    n, count = 40, 300
+    mixed = synth.make_tree_robots([n] * count, seed=31, cfg=5, random_home=True)
+    shared = synth.make_tree_robots([n] * count, seed=31, cfg=5, random_home=True, shared_topology=True)
+    q, qd, tau = synth.make_state([n] * count, seed=31, cfg=5)
+    for rb, want in ((mixed, "jsiia"), (shared, None)):
+        m = fdm.Model(rb, "f64", device=dev)
+        assert m.branched
+        if want is None:
+            want = tune.best_algo("f64", n, count)
+            want = "abia" if want == "cfa" else want
+        auto = _forward(m, rb, q, qd, tau, "f64", dev, algo="auto")
+        np.testing.assert_array_equal(auto, _forward(m, rb, q, qd, tau, "f64", dev, algo=want))
