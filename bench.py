@@ -278,8 +278,14 @@ def cpu_baseline(rb, q, qd, tau, chains: int, min_s: float = 10.0, max_s: float 
     t1 = time.perf_counter()
     oracle.fd(sub.take(np.arange(one)), q[sl], qd[sl], tau[sl], threads=1)
     dt1 = time.perf_counter() - t1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), model)
+    except OSError:
+        pass
     return {"value": passes * chains / dt, "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "single_thread_value": one / dt1,
+            "cpu": model, "host_cpus": os.cpu_count(), "single_thread_value": one / dt1,
             "sample": f"{passes} passes over the first {chains} chains of the same workload (n={n}, FP64), "
                       f"plain CRBA + RNEA + Cholesky, all host threads, {dt:.1f} s wall; single thread: "
                       f"the first {one} chains, {dt1:.1f} s"}
