@@ -612,6 +612,35 @@ def adjoint_leg(dtype: str, reps: int = 10, steps: int = 50):
     model.close()
     del tq, tqd, ttau, taus, qdd, g, gq, gqd, gt, ws, bws
     torch.cuda.empty_cache()
+    # launch-bound sizes: a 100-step rollout (no gradient) of 64 chains of 16 links
+    # (JSIIA, the fastest there), launched step by step against the same steps
+    # recorded in one HIP graph
+    sb, sn, ssteps = 64, 16, 100
+    sl = synth.uniform_lengths(sb, sn)
+    srb = synth.make_robots(sl, cfg=2)
+    if dtype == "f32":
+        srb = srb.astype_rounded(np.float32)
+    smodel = fd.Model(srb, dtype, device=dev)
+    sq0, sqd0, _ = (torch.from_numpy(a).to(dev, tdt) for a in synth.make_state(sl, cfg=2))
+    staus = torch.from_numpy(np.random.default_rng(9).standard_normal((ssteps, sb * sn))).to(dev, tdt)
+    sws = smodel.workspace(sb, "jsiia")
+    sq, sqd, sqdd = sq0.clone(), sqd0.clone(), torch.empty_like(sq0)
+
+    def eager_rollout():
+        sq.copy_(sq0)
+        sqd.copy_(sqd0)
+        for t in range(ssteps):
+            smodel.forward(sq, sqd, staus[t], batch=sb, algo="jsiia", out=sqdd, workspace=sws, stream=stream)
+            smodel.euler_step(sq, sqd, sqdd, dt, q_next=sq, qd_next=sqd, stream=stream)
+
+    rg = fd.RolloutGraph(smodel, sb, ssteps, dt, algo="jsiia")
+    ms_eager = timed(eager_rollout, 5)
+    ms_graph = timed(lambda: rg.run(sq0, sqd0, staus), 5)
+    assert torch.equal(rg.q, sq) and torch.equal(rg.qd, sqd)
+    out["small_batch_rollout"] = {"chains": sb, "n_links": sn, "steps": ssteps, "algo": "jsiia", "eager_ms": ms_eager,
+                                  "graph_ms": ms_graph, "speedup": ms_eager / ms_graph}
+    del rg
+    smodel.close()
     # the same VJP on branched robots of the same size (tree workloads of the tree leg)
     out["trees"] = {}
     for key in TREE_WORKLOADS:

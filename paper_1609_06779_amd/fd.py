@@ -374,3 +374,55 @@ def rollout(model: Model, q0, qd0, taus, batch: int, dt: float, every: int = 10,
     """Differentiable (q_T, qd_T) after T = taus.shape[0] semi-implicit Euler steps of
     forward dynamics with step dt, checkpointing (q, qd) every ``every`` steps."""
     return _Rollout.apply(q0, qd0, taus, model, batch, float(dt), int(every), algo)
+
+
+class RolloutGraph:
+    """A rollout of fixed shape (T semi-implicit Euler steps of forward dynamics,
+    no gradient) recorded once into a HIP graph and replayed. For small batches a
+    step is a few microseconds of kernel time, so launching 2 T kernels from the
+    host costs more than running them; a replay submits them all at once.
+
+    The graph owns its buffers: ``run`` copies (q0, qd0, taus) into them, replays
+    and returns the graph's (q_T, qd_T), which the next ``run`` overwrites. The
+    recorded path clears no memory and allocates nothing (the workspace is taken
+    before recording)."""
+
+    def __init__(self, model: Model, batch: int, steps: int, dt: float, algo: str = "abia", robot_id=None,
+                 offsets=None, n_state: int = 0):
+        if algo == "auto":
+            raise ValueError("a recorded rollout needs a fixed algorithm (abia, jsiia or cfa)")
+        if n_state <= 0:
+            if offsets is not None or len(model.n_links) == 0 or np.any(model.n_links != model.n_links[0]):
+                raise ValueError("give n_state (total links) for ragged batches")
+            n_state = int(batch) * int(model.n_links[0])
+        dev, dt_ = model.device, model.torch_dtype
+        self.model, self.batch, self.steps, self.dt, self.algo = model, int(batch), int(steps), float(dt), algo
+        self.robot_id, self.offsets = robot_id, offsets
+        self.q = torch.zeros(n_state, dtype=dt_, device=dev)
+        self.qd = torch.zeros_like(self.q)
+        self.qdd = torch.zeros_like(self.q)
+        self.taus = torch.zeros((self.steps, n_state), dtype=dt_, device=dev)
+        self.ws = model.workspace(batch, algo, robot_id, offsets)
+        side = torch.cuda.Stream(device=dev)           # torch records graphs after a warm-up off the main stream
+        side.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(side):
+            self._steps()
+        torch.cuda.current_stream(dev).wait_stream(side)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._steps()
+
+    def _steps(self):
+        m = self.model
+        for t in range(self.steps):
+            m.forward(self.q, self.qd, self.taus[t], batch=self.batch, algo=self.algo, robot_id=self.robot_id,
+                      offsets=self.offsets, out=self.qdd, workspace=self.ws)
+            m.euler_step(self.q, self.qd, self.qdd, self.dt, q_next=self.q, qd_next=self.qd)
+
+    def run(self, q0, qd0, taus):
+        """(q_T, qd_T) from (q0, qd0) under the torques taus [T, links]."""
+        self.q.copy_(q0)
+        self.qd.copy_(qd0)
+        self.taus.copy_(taus)
+        self.graph.replay()
+        return self.q, self.qd
