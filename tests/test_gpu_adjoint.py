@@ -225,3 +225,44 @@ def test_vjp_full_size_streaming_sampled(fdm, dev):
         np.abs(gq[idx] * dq) + np.abs(gqd[idx] * dqd) + np.abs(gtau[idx] * dtau), off)
     bar = np.maximum(1e-11, 16 * kappa * 2.0 ** -53)
     assert np.all(np.abs(lhs - rhs) <= bar * scale), (np.abs(lhs - rhs) / scale).max()
+
+
+@pytest.mark.parametrize("tree", [False, True])
+@pytest.mark.parametrize("n", [5, 16, 32])
+def test_vjp_fp32(fdm, dev, n, tree):
+    """fd_backward in FP32 (robots and states rounded to FP32 first, the oracle in
+    FP64 on the rounded values): tau_bar against a dense solve and the adjoint
+    identity, with the FP32 error model 16 cond_2(M) u (u = 2^-24), at least 1e-4."""
+    batch = 12
+    lengths = np.full(batch, n, np.int32)
+    if tree:
+        rb = synth.make_tree_robots(lengths, seed=40 + n, cfg=5, random_home=True)
+    else:
+        rb = synth.make_robots(lengths, cfg=5, random_home=True)
+    rb = rb.astype_rounded(np.float32)
+    q, qd, tau = (a.astype(np.float32).astype(np.float64) for a in synth.make_state(lengths, cfg=5))
+    off = rb.offsets
+    model = fdm.Model(rb, "f32", device=dev)
+    f32 = torch.float32
+    tq, tqd, ttau = _t(q, dev, f32), _t(qd, dev, f32), _t(tau, dev, f32)
+    qdd = model.forward(tq, tqd, ttau, batch=batch, algo="abia")
+    rng = np.random.default_rng(n)
+    g = rng.standard_normal(len(q)).astype(np.float32).astype(np.float64)
+    gq, gqd, gtau = (x.cpu().numpy().astype(np.float64) for x in model.backward(tq, tqd, qdd, _t(g, dev, f32),
+                                                                                batch=batch))
+    ms = oracle.crba(rb, q)
+    kappa = np.array([np.linalg.cond(m) for m in ms])
+    u32 = 2.0 ** -24
+    for b in range(batch):
+        sl = slice(off[b], off[b + 1])
+        ref = np.linalg.solve(ms[b], g[sl])
+        bar = max(1e-4, 16 * kappa[b] * u32)
+        assert np.linalg.norm(gtau[sl] - ref) <= bar * np.linalg.norm(ref), (b, "tau_bar")
+    dq, dqd, dtau = (rng.standard_normal(len(q)) for _ in range(3))
+    _, dqdd = oracle.fd_jvp(rb, q, qd, tau, dq, dqd, dtau)
+    lhs = _chain_sums(g * dqdd, off)
+    rhs = _chain_sums(gq * dq + gqd * dqd + gtau * dtau, off)
+    scale = _chain_sums(np.abs(g * dqdd), off) + _chain_sums(np.abs(gq * dq) + np.abs(gqd * dqd) +
+                                                             np.abs(gtau * dtau), off)
+    bar = np.maximum(1e-4, 16 * kappa * u32)
+    assert np.all(np.abs(lhs - rhs) <= bar * scale), (np.abs(lhs - rhs) / scale).max()
