@@ -57,7 +57,7 @@ extern "C" {
 typedef enum {
     FD_OK = 0,
     FD_ERR_INVALID_ARG = -1,   /* a null pointer, size or value out of range, inconsistent batch */
-    FD_ERR_UNSUPPORTED = -2,   /* valid request this build does not handle (chain too long, ...) */
+    FD_ERR_UNSUPPORTED = -2,   /* valid request this library does not handle (chain too long, ...) */
     FD_ERR_OUT_OF_MEMORY = -3, /* fd_init could not allocate device memory */
     FD_ERR_DEVICE = -4,        /* a HIP call or kernel launch failed */
     FD_ERR_WORKSPACE = -5      /* workspace missing or smaller than fd_workspace_size */
@@ -105,7 +105,7 @@ typedef struct {
 fd_status_t fd_init(const fd_model_desc_t* desc, fd_dtype_t dtype, fd_model_t** out);
 void fd_destroy(fd_model_t* model);
 fd_dtype_t fd_model_dtype(const fd_model_t* model);
-/* Longest chain any algorithm of this build takes for the model's precision (JSIIA may be lower;
+/* Longest chain any algorithm of this library takes for the model's precision (JSIIA may be lower;
  * 0 for an algorithm that does not take the model's branched robots). */
 int32_t fd_max_links(const fd_model_t* model, fd_algo_t algo);
 

@@ -605,7 +605,7 @@ const char* fd_status_string(fd_status_t s) {
     switch (s) {
         case FD_OK: return "ok";
         case FD_ERR_INVALID_ARG: return "invalid argument";
-        case FD_ERR_UNSUPPORTED: return "unsupported by this build";
+        case FD_ERR_UNSUPPORTED: return "unsupported by this library";
         case FD_ERR_OUT_OF_MEMORY: return "out of device memory";
         case FD_ERR_DEVICE: return "device error";
         case FD_ERR_WORKSPACE: return "workspace missing or too small";
