@@ -453,3 +453,25 @@ def test_every_chain_at_65536(fdm, dev, n):
             bar = np.maximum(TOL["f64"], COND_FACTOR[algo] * _kappa_many(algo, rb, q, n, over) * U["f64"])
             bad = over[~(err[over] <= bar)]
             assert len(bad) == 0, f"{algo} n={n}: {len(bad)} chains over the bar (chain {bad[:5]})"
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_non_finite_inputs_stay_in_their_chain(fdm, dev, algo):
+    """A NaN or infinite entry makes its own chain's q-ddot non-finite and leaves
+    every other chain of the batch bit for bit as in a clean run (chains share
+    no arithmetic). The kernels branch on no input value, so nothing else moves."""
+    lengths = np.full(10, 9, np.int32)
+    rb, q, qd, tau = _prep(lengths, "f64", cfg=5)
+    model = fdm.Model(rb, "f64", device=dev)
+    clean = _forward(fdm, dev, rb, q, qd, tau, "f64", algo, model=model)
+    q2, qd2, tau2 = q.copy(), qd.copy(), tau.copy()
+    q2[3 * 9 + 4] = np.nan
+    qd2[5 * 9 + 0] = np.inf
+    tau2[7 * 9 + 8] = -np.inf
+    dirty = _forward(fdm, dev, rb, q2, qd2, tau2, "f64", algo, model=model)
+    for b in range(10):
+        sl = slice(9 * b, 9 * b + 9)
+        if b in (3, 5, 7):
+            assert not np.all(np.isfinite(dirty[sl])), b
+        else:
+            np.testing.assert_array_equal(dirty[sl], clean[sl])
