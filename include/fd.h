@@ -114,8 +114,12 @@ fd_status_t fd_workspace_size(const fd_model_t* model, const fd_batch_t* batch, 
 
 /* Forward dynamics, eq. (tau-bias): qdd = M(q)^-1 (tau - tau_bias(q, qd)).
  * q, qd, tau, qdd: device arrays of the model's precision (double or float),
- * packed per chain. algo FD_ALGO_AUTO picks by chain length. hip_stream: a
- * hipStream_t (NULL = default stream). Asynchronous. */
+ * packed per chain. algo FD_ALGO_AUTO picks by the batch's longest chain and its
+ * size (fd_set_auto_table); where that is ABIA on a batch with offsets, it runs
+ * the persistent launch of fd_forward_persistent (grid 0), whose results are the
+ * same bit for bit; fd_workspace_size with FD_ALGO_AUTO sizes the workspace for
+ * the path AUTO takes. hip_stream: a hipStream_t (NULL = default stream).
+ * Asynchronous. */
 fd_status_t fd_forward(const fd_model_t* model, const fd_batch_t* batch, const void* q, const void* qd,
                        const void* tau, void* qdd, fd_algo_t algo, void* workspace, size_t ws_bytes,
                        void* hip_stream);

@@ -167,6 +167,11 @@ fd_algo_t pick_algo(const fd_model* m, int nmax, int batch) {
     return a;
 }
 
+// AUTO on a ragged batch (offsets given) that picks ABIA runs the persistent,
+// length-sorted launch: the same results bit for bit, without every wavefront
+// running to the longest chain of its 64.
+bool auto_persistent(const fd_batch_t* b, fd_algo_t picked) { return b->offsets != nullptr && picked == FD_ALGO_ABIA; }
+
 template <typename T>
 fd_status_t forward_t(const fd_model* m, const BatchPlan& p, const void* q, const void* qd, const void* tau,
                       void* qdd, fd_algo_t algo, void* ws, size_t ws_bytes, hipStream_t st) {
@@ -394,7 +399,10 @@ fd_status_t fd_workspace_size(const fd_model_t* m, const fd_batch_t* b, fd_algo_
     BatchPlan p;
     fd_status_t s = plan_batch(m, b, &p);
     if (s != FD_OK) return s;
-    if (algo == FD_ALGO_AUTO) algo = pick_algo(m, p.nmax, b->batch);
+    if (algo == FD_ALGO_AUTO) {
+        algo = pick_algo(m, p.nmax, b->batch);
+        if (auto_persistent(b, algo)) return fd_persistent_workspace_size(m, b, 0, bytes);
+    }
     const size_t esz = m->dtype == FD_F64 ? sizeof(double) : sizeof(float);
     *bytes = algo == FD_ALGO_ABIA ? fdk::abia_workspace_elems(b->batch, p.nmax, m->tree) * esz : 0;
     return FD_OK;
@@ -408,7 +416,10 @@ fd_status_t fd_forward(const fd_model_t* m, const fd_batch_t* b, const void* q, 
     if (algo < FD_ALGO_ABIA || algo > FD_ALGO_AUTO) return FD_ERR_INVALID_ARG;
     if (b->batch == 0) return FD_OK;
     if (!q || !qd || !tau || !qdd) return FD_ERR_INVALID_ARG;
-    if (algo == FD_ALGO_AUTO) algo = pick_algo(m, p.nmax, b->batch);
+    if (algo == FD_ALGO_AUTO) {
+        algo = pick_algo(m, p.nmax, b->batch);
+        if (auto_persistent(b, algo)) return fd_forward_persistent(m, b, q, qd, tau, qdd, 0, ws, ws_bytes, hip_stream);
+    }
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     if (m->dtype == FD_F64) return forward_t<double>(m, p, q, qd, tau, qdd, algo, ws, ws_bytes, st);
     return forward_t<float>(m, p, q, qd, tau, qdd, algo, ws, ws_bytes, st);

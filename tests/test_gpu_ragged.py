@@ -62,3 +62,25 @@ def test_persistent_skips_out_of_range_robot_ids(dev):
     model.forward_persistent(t(q), t(qd), t(tau), batch=6, robot_id=t(rid), offsets=t(off), out=out)
     plain = model.forward(t(q), t(qd), t(tau), batch=6, algo="abia", robot_id=t(rid), offsets=t(off))
     assert torch.equal(out, plain)
+
+
+def test_auto_on_a_ragged_batch_takes_the_persistent_launch(dev):
+    """AUTO on a batch with offsets, where the tuned table picks ABIA, runs the
+    persistent length-sorted launch: its workspace size is the persistent one,
+    and its q-ddot equals the plain ABIA launch bit for bit. Where the table
+    picks another algorithm, AUTO equals that algorithm."""
+    from paper_1609_06779_amd import fd, tune
+
+    lengths = synth.ragged_lengths(65536, 4, 128, cfg=3)       # the tuned table picks ABIA at this size
+    rb = synth.make_robots(lengths, cfg=3)
+    q, qd, tau = synth.make_state(lengths, cfg=3)
+    model = fd.Model(rb, "f64", device=dev)
+    tq, tqd, ttau = (torch.from_numpy(a).to(dev) for a in (q, qd, tau))
+    toff = torch.from_numpy(rb.offsets).to(dev)
+    batch = len(lengths)
+    picked = tune.best_algo("f64", int(lengths.max()), batch)
+    auto = model.forward(tq, tqd, ttau, batch=batch, algo="auto", offsets=toff)
+    if picked == "abia":
+        assert model.workspace_size(batch, "auto", offsets=toff) == model.persistent_workspace(batch, 0, offsets=toff).numel()
+    ref = model.forward(tq, tqd, ttau, batch=batch, algo=picked, offsets=toff)
+    assert torch.equal(auto, ref), picked
