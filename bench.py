@@ -371,6 +371,9 @@ def ragged_leg(dtype: str, batch: int = 100000, lo: int = 4, hi: int = 256, reps
     aws = model.workspace(batch, "abia", offsets=toff)
     ms_plain = timed(lambda: model.forward(tq, tqd, ttau, batch=batch, algo="abia", offsets=toff, out=out,
                                            workspace=aws, stream=stream))
+    autows = model.workspace(batch, "auto", offsets=toff)
+    ms_auto = timed(lambda: model.forward(tq, tqd, ttau, batch=batch, algo="auto", offsets=toff, out=out,
+                                          workspace=autows, stream=stream))
     groups = []
     for n in np.unique(lengths):
         ids = np.nonzero(lengths == n)[0].astype(np.int32)
@@ -388,7 +391,8 @@ def ragged_leg(dtype: str, batch: int = 100000, lo: int = 4, hi: int = 256, reps
     model.close()
     return {"workload": f"ragged-b{batch}-n{lo}..{hi}", "links": int(lengths.sum()), "grid": grid,
             "persistent_ms": ms_pers, "persistent_solves_per_s": batch / (ms_pers * 1e-3),
-            "plain_ragged_ms": ms_plain, "per_length_launches": len(groups), "per_length_ms": ms_split}
+            "plain_ragged_ms": ms_plain, "auto_ms": ms_auto, "auto_choice": tune.best_algo(dtype, int(lengths.max()), batch),
+            "per_length_launches": len(groups), "per_length_ms": ms_split}
 
 
 def copy_calibration(dev):
