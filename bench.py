@@ -528,14 +528,17 @@ def levels_leg(dtype: str, ns=(16, 32, 64, 128), batch: int = 65536, reps: int =
         x = torch.empty_like(r)
         st = torch.zeros(1, dtype=torch.int32, device=dev)
         ms_oee = timed(lambda: fd.btd_solve6(d, u, r, off, n, out=x, status=st, stream=stream))
-        if int(st.item()) != 0:
-            raise RuntimeError(f"btd_solve6 status {int(st.item())} at n={n}")
+        status = int(st.item())
+        # FP64 must factor every system; in FP32 the generator's worst systems
+        # (cond_2 up to ~1e7 at 128 blocks) can lose a pivot, which the status reports
+        if status != 0 and dtype == "f64":
+            raise RuntimeError(f"btd_solve6 status {status} at n={n}")
         rows = batch * n
         out[str(n)] = {
             "levels": levels,
             "scan_ms": ms_scan, "scan_us_per_level": 1e3 * ms_scan / levels,
             "scan_gb_s": rows * (36 + 12) * w / (ms_scan * 1e-3) / 1e9,
-            "oee_ms": ms_oee, "oee_us_per_level": 1e3 * ms_oee / levels,
+            "oee_ms": ms_oee, "oee_us_per_level": 1e3 * ms_oee / levels, "oee_status": status,
             "oee_gb_s": rows * (72 + 12) * w / (ms_oee * 1e-3) / 1e9,
         }
         del sb, sc, sx, d, u, r, x
