@@ -76,3 +76,39 @@ def test_trace_and_counter_summaries(tmp_path, monkeypatch):
     assert bench.measured_traffic("cfa", "w") == pytest.approx((1000.0 * 2 + 500.0) * 1024)
     (tmp_path / "paper_1609_06779_amd" / "csrc" / "k.hip").write_text("// changed\n")
     assert bench.measured_traffic("cfa", "w") is None              # stale once the kernels change
+
+
+def test_flops_summary_scales_the_wave_counter_by_64_lanes(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    (tmp_path / "profiles").mkdir()
+    hdr = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    k = "void fdk::k_cfa<double, 64>(int)"
+    for sub, rows in (("p1", [[1, k, "SQ_INSTS_VALU_FLOPS_FP64", 5e8]]),
+                      ("p2", [[1, k, "SQ_INSTS_MFMA", 0], [1, k, "SQ_INSTS_VALU", 4e8],
+                              [1, k, "SQ_INSTS_VALU_FMA_F64", 2e8], [1, k, "SQ_INSTS_VALU_MUL_F64", 6e7],
+                              [1, k, "SQ_INSTS_VALU_ADD_F64", 4e7]]),
+                      ("p3", [[1, k, "SQ_INSTS_LDS", 2e7], [1, k, "SQ_LDS_BANK_CONFLICT", 0],
+                              [1, k, "SQ_WAVES", 65536]])):
+        d = tmp_path / sub
+        d.mkdir()
+        _write_csv(d / "run_counter_collection.csv", hdr, rows)
+    log = tmp_path / "bench.log"
+    log.write_text(json.dumps({"per_algo": {"cfa": {"ms_per_launch": 1.0}}}) + "\n")
+    out = bench.summarize_flops(str(tmp_path / "p1"), str(tmp_path / "p2"), "w", ["c"], "s", str(log), 64, 65536,
+                                "f64", str(tmp_path / "p3"))
+    row = next(ln for ln in open(out) if ln.startswith("| cfa | `"))
+    cells = [c.strip() for c in row.split("|")[1:-1]]
+    assert float(cells[2]) == pytest.approx(5e8 * 64 / 1e9)              # executed GFLOP per launch
+    assert float(cells[5]) == pytest.approx(5e8 * 64 / 1e-3 / 1e12, rel=1e-3)   # TFLOP/s at 1 ms
+    assert cells[7] == "0" and float(cells[8]) == pytest.approx(3e8 / 4e8)   # no MFMA; FP64 share
+    lds = next(ln for ln in open(out) if ln.startswith("| cfa | 65536"))
+    assert "| 305 |" in lds                                               # 2e7 / 65536 LDS instructions
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+
+    r = subprocess.run([sys.executable, os.path.join(os.path.dirname(bench.__file__), "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
