@@ -112,8 +112,9 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
     const int sl = ci.slot;
     T* wsb = ws + (size_t)blockIdx.x * nmax * vjp_fields<TREE>() * 64 + lane;
     auto w = [&](int i, int f) -> T& { return wsb[((size_t)i * vjp_fields<TREE>() + f) * 64]; };
-    // per-link fields stream (NT) when the launch outgrows the last-level cache;
-    // branch-point records and the tree's F updates keep the default policy
+    // per-link fields stream (NT) when the launch outgrows the last-level cache,
+    // a child's update of its parent's F field included; branch-point records
+    // keep the default policy
     auto ldw = [&](int i, int f) -> T { return ld_ws<NT>(&w(i, f)); };
     auto stw = [&](int i, int f, T v) { st_ws<NT>(v, &w(i, f)); };
     auto code_of = [&](int i) -> int32_t { return TREE ? m.template tree_il<false>(i, sl) : 0; };
@@ -376,7 +377,7 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
                     const bool first = (code & TREE_FIRST) != 0;
 #pragma unroll
                     for (int c = 0; c < 6; ++c) {
-                        w(p, VJP_F + c) += fc[c];      // f_p plus its other children's terms
+                        stw(p, VJP_F + c, ldw(p, VJP_F + c) + fc[c]);   // f_p plus its other children's terms
                         add_into(&w(p, VJP_WB + c), ab[c], first);
                         add_into(&w(p, VJP_WB + 6 + c), vb[c], first);
                     }
@@ -414,7 +415,10 @@ hipError_t launch_fd_vjp(const ModelView<T>& m, const ChainMap& cm, int nmax, co
                          const T* gqdd, T* gq, T* gqd, T* gtau, int accumulate, T* ws, bool stream, hipStream_t st) {
     if (cm.batch <= 0) return hipSuccess;
     const dim3 grid((cm.batch + 63) / 64);
-    if (m.tree)
+    if (m.tree && stream)
+        hipLaunchKernelGGL((k_fd_vjp<T, true, true>), grid, dim3(64), 0, st, m, cm, nmax, q, qd, qdd, gqdd, gq, gqd,
+                           gtau, accumulate, ws);
+    else if (m.tree)
         hipLaunchKernelGGL((k_fd_vjp<T, true, false>), grid, dim3(64), 0, st, m, cm, nmax, q, qd, qdd, gqdd, gq, gqd,
                            gtau, accumulate, ws);
     else if (stream)
