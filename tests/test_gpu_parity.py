@@ -113,11 +113,15 @@ def _forward(fdm, dev, rb, q, qd, tau, dtype, algo, offsets=None, robot_id=None,
 @pytest.mark.parametrize("algo", ALGOS)
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 13, 16, 24, 32, 33, 50, 64, 100, 128, 200, 256])
 def test_forward_uniform(fdm, dev, algo, dtype, n):
-    if algo == "jsiia" and n > 128:
-        pytest.skip("JSIIA keeps M in LDS: n <= 128 in this library")
     batch = 37 if n <= 64 else 11            # not a multiple of the chains per workgroup
     lengths = np.full(batch, n, np.int32)
     rb, q, qd, tau = _prep(lengths, dtype, random_home=(n % 2 == 1))
+    if algo == "jsiia" and n > 128:          # JSIIA keeps M in LDS: the library refuses, before any launch
+        from paper_1609_06779_amd import _lib
+        with pytest.raises(_lib.FdError) as ei:
+            _forward(fdm, dev, rb, q, qd, tau, dtype, algo)
+        assert ei.value.status == _lib.FD_ERR_UNSUPPORTED
+        return
     off = rb.offsets
     ref = oracle.fd(rb, q, qd, tau)
     got = _forward(fdm, dev, rb, q, qd, tau, dtype, algo)
