@@ -438,3 +438,39 @@ def test_fd_jvp_along_torque_is_the_inverse_inertia():
     z = np.zeros(5)
     _, dqdd = oracle.fd_jvp(rb, q, qd, tau, z, z, v)
     np.testing.assert_allclose(dqdd, np.linalg.solve(oracle.crba(rb, q)[0], v), rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 6])
+def test_cfa_c_matrix_equals_the_global_form(n):
+    """C = S^T Phi S assembled from Phi's blocks (dense.cfa_c_matrix, and the
+    batched copy the GPU tests use for their diagnostics) equals the C of the
+    global matrices, Phi = (I - Gamma) J^-1 (I - Gamma)^T built as 6n x 6n
+    (Sec. III, eq. (fijany-final)). A slip in a block (a sign, an index, a
+    transposed Ad) changes C."""
+    import _errmodel
+
+    lengths = [n] * 4
+    rb = synth.make_robots(lengths, seed=93, random_home=True)
+    q, _, _ = synth.make_state(lengths, seed=93)
+    batched = _errmodel.cfa_c_batched(rb, q, n, np.arange(4))
+    for b in range(4):
+        ch = dense.Chain(rb, b * n, n)
+        ref = dense.cfa_matrices(ch, q[b * n:(b + 1) * n])[5]
+        scale = np.abs(ref).max()
+        np.testing.assert_allclose(dense.cfa_c_matrix(ch, q[b * n:(b + 1) * n]), ref, rtol=0, atol=1e-12 * scale)
+        np.testing.assert_allclose(batched[b], ref, rtol=0, atol=1e-12 * scale)
+        assert np.count_nonzero(np.abs(ref) > 1e-14 * scale) <= 3 * n - 2     # tri-diagonal
+
+
+def test_cfa_c_matrix_catches_a_planted_sign_error():
+    """The pin above is sharp: flipping the sign of the coupling block
+    Phi_{i,i+1} changes C by far more than the pin's bar."""
+    n = 4
+    rb = synth.make_robots([n], seed=94, random_home=True)
+    q, _, _ = synth.make_state([n], seed=94)
+    ch = dense.Chain(rb, 0, n)
+    ref = dense.cfa_matrices(ch, q)[5]
+    bad = dense.cfa_c_matrix(ch, q).copy()
+    bad[np.arange(n - 1), np.arange(1, n)] *= -1
+    bad[np.arange(1, n), np.arange(n - 1)] *= -1
+    assert np.abs(bad - ref).max() > 1e-3 * np.abs(ref).max()
