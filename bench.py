@@ -291,14 +291,81 @@ def cpu_baseline(rb, q, qd, tau, chains: int, min_s: float = 10.0, max_s: float 
                       f"the first {one} chains, {dt1:.1f} s"}
 
 
+ACCURACY_TARGET = {"f64": 1e-10, "f32": 1e-4}
+ACCURACY_CAP = {"f64": 1e-9, "f32": 1e-3}
+
+
+def cpu_baseline_accuracy(ns=(16, 32, 64, 128), batch: int = 65536, sample: int = 8192, eta_sample: int = 512):
+    """Part of the CPU-baseline leg: the oracle's reference q-ddot on a sample of
+    each uniform 65536-chain workload (n = 16..128; the first `sample` chains),
+    FP64 and FP32 (robots and states rounded to FP32 first, the oracle in FP64 on
+    the rounded values), against the library's q-ddot for the whole batch.
+    Per (dtype, n, algorithm): max, p99 and median per-chain relative error
+    ||qdd - qdd_ref|| / ||qdd_ref||, the fraction of chains within the target
+    (1e-10 FP64, 1e-4 FP32) and within the parity tests' cap (10x the target),
+    and the largest normwise backward error ||M qdd - tau_delta|| /
+    (||M|| ||qdd|| + ||tau|| + ||tau_bias||) over the first `eta_sample` chains,
+    in units of the precision's unit roundoff."""
+    import torch
+
+    import oracle
+    from paper_1609_06779_amd import fd, synth
+
+    dev = torch.device("cuda:0")
+    u = {"f64": 2.0 ** -53, "f32": 2.0 ** -24}
+    out = {"chains_checked": sample, "batch": batch, "target": ACCURACY_TARGET, "cap": ACCURACY_CAP}
+    for dtype in ("f64", "f32"):
+        tdt = torch.float64 if dtype == "f64" else torch.float32
+        out[dtype] = {}
+        for n in ns:
+            lengths = synth.uniform_lengths(batch, n)
+            rb = synth.make_robots(lengths, cfg=2)
+            q, qd, tau = synth.make_state(lengths, cfg=2)
+            if dtype == "f32":
+                rb = rb.astype_rounded(np.float32)
+                q, qd, tau = (a.astype(np.float32).astype(np.float64) for a in (q, qd, tau))
+            sub = rb.take(np.arange(sample))
+            sl = slice(0, sample * n)
+            ref = oracle.fd(sub, q[sl], qd[sl], tau[sl], threads=0)
+            es = slice(0, eta_sample * n)
+            esub = rb.take(np.arange(eta_sample))
+            ms = oracle.crba(esub, q[es], threads=0)
+            bias = oracle.rnea(esub, q[es], qd[es], threads=0)
+            mnorm = np.array([np.linalg.norm(m, 2) for m in ms])
+            model = fd.Model(rb, dtype, device=dev)
+            tq, tqd, tt = (torch.from_numpy(a).to(dev, tdt) for a in (q, qd, tau))
+            cell = {}
+            for algo in ("abia", "jsiia", "cfa"):
+                if n > model.max_links(algo):
+                    continue
+                got = model.forward(tq, tqd, tt, batch=batch, algo=algo)[: sample * n].cpu().numpy().astype(np.float64)
+                err = oracle.relative_error(got, ref, sub.offsets)
+                eta = [np.linalg.norm(ms[b] @ got[b * n:(b + 1) * n] - (tau[b * n:(b + 1) * n] - bias[b * n:(b + 1) * n]))
+                       / (mnorm[b] * np.linalg.norm(got[b * n:(b + 1) * n]) + np.linalg.norm(tau[b * n:(b + 1) * n])
+                          + np.linalg.norm(bias[b * n:(b + 1) * n])) for b in range(eta_sample)]
+                cell[algo] = {"max": float(err.max()), "p99": float(np.quantile(err, 0.99)),
+                              "median": float(np.median(err)),
+                              "within_target": float(np.mean(err <= ACCURACY_TARGET[dtype])),
+                              "within_cap": float(np.mean(err <= ACCURACY_CAP[dtype])),
+                              "backward_error_max_u": float(np.max(eta) / u[dtype])}
+            out[dtype][str(n)] = cell
+            model.close()
+            del tq, tqd, tt
+            torch.cuda.empty_cache()
+    return out
+
+
 def serving_leg(dtype: str, requests: int = 30000):
     """Continuous batching over 32 resident robots (n ~ U{7..200}), requests of
     1..4096 chains (log-uniform), Poisson arrivals at 50%, 70% and 80% of the
     saturation rate (all requests present at once); latency is arrival to
-    result in host memory. Launches at a finite rate are smaller than at
-    saturation, so 80% sits close to the sustainable rate, where p99 is set by
-    queueing behind bursts; 3e4 requests per point give about 300 samples past
-    the 99th percentile."""
+    result in host memory. Each round's batch takes the library's AUTO choice.
+    Saturation reports where the time goes (copies in, kernels, copies out:
+    GPU time summed over launches, which overlap on the streams; and the host
+    loop's own time) and, for reference, the plain per-batch launch on the same
+    request mix: the same rounds of at most 65536 chains, state already in
+    HBM, one AUTO launch each. 3e4 requests per point give about 300 samples
+    past the 99th percentile."""
     import torch
 
     from paper_1609_06779_amd import fd, serve, synth
@@ -306,26 +373,75 @@ def serving_leg(dtype: str, requests: int = 30000):
     dev = torch.device("cuda:0")
     lengths = synth.ragged_lengths(32, 7, 200, cfg=4)
     model = fd.Model(synth.make_robots(lengths, cfg=4), dtype, device=dev)
-    ex = serve.GpuExecutor(model, lengths, algo="auto", streams=4)
     budget = 8 << 30
+    esz = 8 if dtype == "f64" else 4
 
     def run(qps, count, seed):
+        ex = serve.GpuExecutor(model, lengths, algo="auto", streams=4, slots=8)
         reqs = serve.make_requests(lengths, count, qps, seed=seed, dtype=dtype, shared=True)
         sched = serve.Scheduler(ex, budget, max_inflight=8, idle=serve.spin_idle)
         torch.cuda.synchronize()
-        return sched.run(reqs), reqs
+        return sched.run(reqs), reqs, ex
 
-    run(float("inf"), 64, 1)                     # warm up allocator and kernels
-    sat, reqs = run(float("inf"), requests, 2)
+    run(float("inf"), 256, 1)                    # warm up allocator and kernels
+    sat, reqs, ex = run(float("inf"), requests, 2)
     mean_chains = float(np.mean([r.chains for r in reqs]))
     algos = collections.Counter(r.algo for r in reqs)
+    t = ex.timing
+    moved = t["bytes_h2d"] + t["bytes_d2h"]
     out = {"robots": 32, "n_links": "U{7..200}", "chains_per_request": "log-uniform 1..4096",
-           "algo": "per request, tuned table", "requests_per_load": requests, "budget_bytes": budget,
-           "streams": 4, "saturation_solves_per_s": sat.solves_per_s, "saturation_launches": sat.launches,
-           "saturation_algo_mix": dict(algos)}
+           "algo": "AUTO per round (the whole round's batch)", "requests_per_load": requests,
+           "budget_bytes": budget, "streams": 4, "slots": 8,
+           "saturation_solves_per_s": sat.solves_per_s, "saturation_launches": sat.launches,
+           "saturation_wall_s": sat.wall, "saturation_algo_mix": dict(algos),
+           "breakdown": {"h2d_ms": t["h2d_ms"], "kernel_ms": t["kernel_ms"], "d2h_ms": t["d2h_ms"],
+                         "host_launch_ms": t["host_launch_s"] * 1e3, "wall_ms": sat.wall * 1e3,
+                         "bytes_over_pcie": moved, "pcie_gb_per_s": moved / sat.wall / 1e9,
+                         "persistent_launches": t["persistent_launches"]}}
+    # the plain per-batch launch on the same mix: the same packing, inputs resident in HBM
+    rounds, cur = [], []
+    for r in reqs:
+        if cur and sum(x.chains for x in cur) + r.chains > 65536:
+            rounds.append(cur)
+            cur = []
+        cur.append(r)
+    if cur:
+        rounds.append(cur)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    stream = torch.cuda.current_stream()
+    ms_plain, chains_plain = 0.0, 0
+    for grp in rounds:
+        sizes = np.array([r.chains for r in grp])
+        ns = np.array([r.n for r in grp])
+        chains, links = int(sizes.sum()), int((sizes * ns).sum())
+        rid = torch.from_numpy(np.repeat([r.robot for r in grp], sizes).astype(np.int32)).to(dev)
+        first_chain = np.repeat(np.cumsum(sizes) - sizes, sizes)
+        first_link = np.repeat(np.cumsum(sizes * ns) - sizes * ns, sizes)
+        off_np = np.append(first_link + (np.arange(chains) - first_chain) * np.repeat(ns, sizes), links)
+        off = torch.from_numpy(off_np.astype(np.int64)).to(dev)
+        gen = torch.Generator(device=dev).manual_seed(len(grp))
+        q = (torch.rand(links, generator=gen, device=dev, dtype=tdt) * 2 - 1) * math.pi
+        qd = torch.rand(links, generator=gen, device=dev, dtype=tdt) * 2 - 1
+        tau = torch.randn(links, generator=gen, device=dev, dtype=tdt)
+        nmax = int(ns.max())
+        ws = model.workspace(chains, "auto", robot_id=rid, offsets=off, max_links=nmax)
+        o = torch.empty_like(q)
+        call = lambda: model.forward(q, qd, tau, batch=chains, algo="auto", robot_id=rid, offsets=off, out=o,
+                                     workspace=ws, stream=stream, max_links=nmax)
+        call()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        call()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms_plain += a.elapsed_time(b)
+        chains_plain += chains
+        del q, qd, tau, o, ws, rid, off
+    out["plain_per_batch"] = {"rounds": len(rounds), "kernel_ms": ms_plain,
+                              "solves_per_s": chains_plain / (ms_plain * 1e-3)}
     for load in (0.5, 0.7, 0.8):
         qps = load * sat.solves_per_s / mean_chains
-        st, _ = run(qps, requests, 3 + int(load * 10))
+        st, _, _ = run(qps, requests, 3 + int(load * 10))
         out[f"load_{int(load * 100)}pct"] = {"qps": qps, "p50_ms": st.p50 * 1e3, "p99_ms": st.p99 * 1e3,
                                              "solves_per_s": st.solves_per_s, "launches": st.launches,
                                              "max_inflight": st.max_inflight}
@@ -546,26 +662,20 @@ def levels_leg(dtype: str, ns=(16, 32, 64, 128), batch: int = 65536, reps: int =
     return out
 
 
-def adjoint_leg(dtype: str, reps: int = 10, steps: int = 50):
-    """Reverse mode at 65536 chains of 64 links: the vector-Jacobian product
-    (fd_backward) per launch beside the plain ABIA forward it differentiates,
-    and a checkpointed rollout of `steps` semi-implicit Euler steps (forward,
-    then the backward pass through the recomputed segments) beside `steps`
-    plain forward + Euler steps."""
+def adjoint_leg(dtype: str, reps: int = 10):
+    """Reverse mode. (1) At 65536 chains of 64 links: the vector-Jacobian product
+    (fd_backward) per launch, with lambda = M^-1 g by each algorithm, beside that
+    algorithm's plain forward launch. (2) The differentiation workload: 16384
+    chains of 32 links, a 100-step semi-implicit Euler rollout (dt = 1e-3,
+    tau ~ N(0, 1) per step), loss = sum of squared final q and qd, gradient with
+    respect to q_0, qd_0 and every tau_t with checkpoints every 10 steps:
+    forward and backward beside 100 plain forward + Euler steps."""
     import torch
 
-    from paper_1609_06779_amd import fd, synth
+    from paper_1609_06779_amd import fd, synth, tune
 
     dev = torch.device("cuda:0")
     tdt = torch.float64 if dtype == "f64" else torch.float32
-    batch, n = 65536, 64
-    lengths = synth.uniform_lengths(batch, n)
-    rb = synth.make_robots(lengths, cfg=2)
-    if dtype == "f32":
-        rb = rb.astype_rounded(np.float32)
-    q, qd, tau = synth.make_state(lengths, cfg=2)
-    model = fd.Model(rb, dtype, device=dev)
-    tq, tqd, ttau = (torch.from_numpy(a).to(dev, tdt) for a in (q, qd, tau))
     stream = torch.cuda.current_stream()
 
     def timed(fn, count):
@@ -579,45 +689,78 @@ def adjoint_leg(dtype: str, reps: int = 10, steps: int = 50):
         torch.cuda.synchronize()
         return a.elapsed_time(b) / count
 
-    ws = model.workspace(batch, "abia")
-    qdd = torch.empty_like(tq)
-    ms_fwd = timed(lambda: model.forward(tq, tqd, ttau, batch=batch, algo="abia", out=qdd, workspace=ws,
-                                         stream=stream), reps)
+    batch, n = 65536, 64
+    lengths = synth.uniform_lengths(batch, n)
+    rb = synth.make_robots(lengths, cfg=2)
+    if dtype == "f32":
+        rb = rb.astype_rounded(np.float32)
+    q, qd, tau = synth.make_state(lengths, cfg=2)
+    model = fd.Model(rb, dtype, device=dev)
+    tq, tqd, ttau = (torch.from_numpy(a).to(dev, tdt) for a in (q, qd, tau))
     g = torch.from_numpy(np.random.default_rng(5).standard_normal(len(q))).to(dev, tdt)
-    bws = model.backward_workspace(batch)
     gq, gqd, gt = (torch.empty_like(tq) for _ in range(3))
-    ms_vjp = timed(lambda: model.backward(tq, tqd, qdd, g, batch=batch, grad_q=gq, grad_qd=gqd, grad_tau=gt,
-                                          workspace=bws, stream=stream), reps)
+    qdd = torch.empty_like(tq)
+    out = {"workload": f"uniform-n{n}-b{batch}", "per_algo": {}}
+    for algo in ("abia", "jsiia", "cfa"):
+        ws = model.workspace(batch, algo)
+        ms_fwd = timed(lambda: model.forward(tq, tqd, ttau, batch=batch, algo=algo, out=qdd, workspace=ws,
+                                             stream=stream), reps)
+        bws = model.backward_workspace(batch, algo)
+        ms_vjp = timed(lambda: model.backward(tq, tqd, qdd, g, batch=batch, algo=algo, grad_q=gq, grad_qd=gqd,
+                                              grad_tau=gt, workspace=bws, stream=stream), reps)
+        out["per_algo"][algo] = {"forward_ms": ms_fwd, "vjp_ms": ms_vjp, "vjp_over_forward": ms_vjp / ms_fwd}
+        del ws, bws
+    out["abia_forward_ms"] = out["per_algo"]["abia"]["forward_ms"]
+    out["vjp_ms"] = out["per_algo"]["abia"]["vjp_ms"]
+    out["vjp_over_forward"] = out["per_algo"]["abia"]["vjp_over_forward"]
+    model.close()
+    del tq, tqd, ttau, qdd, g, gq, gqd, gt
+    torch.cuda.empty_cache()
 
-    dt = 1e-3
+    # the differentiation workload, exactly
+    batch, n, steps, dt, every = 16384, 32, 100, 1e-3, 10
+    lengths = synth.uniform_lengths(batch, n)
+    rb = synth.make_robots(lengths, cfg=5)
+    if dtype == "f32":
+        rb = rb.astype_rounded(np.float32)
+    q0n, qd0n, _ = synth.make_state(lengths, cfg=5)
+    model = fd.Model(rb, dtype, device=dev)
+    tq, tqd = (torch.from_numpy(a).to(dev, tdt) for a in (q0n, qd0n))
+    taus = torch.from_numpy(np.random.default_rng(5).standard_normal((steps, len(q0n)))).to(dev, tdt)
+    algo = tune.best_algo(dtype, n, batch)
+    ws = model.workspace(batch, algo)
+    qdd = torch.empty_like(tq)
     qs, qds = tq.clone(), tqd.clone()
 
     def plain_steps():
-        for _ in range(steps):
-            model.forward(qs, qds, ttau, batch=batch, algo="abia", out=qdd, workspace=ws, stream=stream)
+        qs.copy_(tq)
+        qds.copy_(tqd)
+        for t in range(steps):
+            model.forward(qs, qds, taus[t], batch=batch, algo=algo, out=qdd, workspace=ws, stream=stream)
             model.euler_step(qs, qds, qdd, dt, q_next=qs, qd_next=qds, stream=stream)
 
-    ms_plain = timed(plain_steps, 1)
-    taus = ttau.unsqueeze(0).repeat(steps, 1)
-    wq, wqd = torch.ones_like(tq), torch.ones_like(tq)
+    ms_plain = timed(plain_steps, 2)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     for rep in range(2):                           # the second pass is timed (allocator warm)
         q0, qd0 = tq.clone().requires_grad_(True), tqd.clone().requires_grad_(True)
         tt = taus.clone().requires_grad_(True)
         torch.cuda.synchronize()
         ev[0].record(stream)
-        qT, qdT = fd.rollout(model, q0, qd0, tt, batch=batch, dt=dt, every=10, algo="abia")
+        qT, qdT = fd.rollout(model, q0, qd0, tt, batch=batch, dt=dt, every=every, algo=algo)
         ev[1].record(stream)
-        ((qT * wq).sum() + (qdT * wqd).sum()).backward()
+        ((qT ** 2).sum() + (qdT ** 2).sum()).backward()
         ev[2].record(stream)
         torch.cuda.synchronize()
         assert torch.isfinite(tt.grad).all().item() and torch.isfinite(q0.grad).all().item()
-    out = {"workload": f"uniform-n{n}-b{batch}", "abia_forward_ms": ms_fwd, "vjp_ms": ms_vjp,
-           "vjp_over_forward": ms_vjp / ms_fwd,
-           "rollout": {"steps": steps, "checkpoint_every": 10, "forward_ms": ev[0].elapsed_time(ev[1]),
-                       "backward_ms": ev[1].elapsed_time(ev[2]), "plain_forward_steps_ms": ms_plain}}
+    fwd_ms, bwd_ms = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    out["rollout"] = {"workload": f"rollout-n{n}-b{batch}-T{steps}", "steps": steps, "dt": dt,
+                      "checkpoint_every": every, "algo": algo, "forward_ms": fwd_ms, "backward_ms": bwd_ms,
+                      "plain_forward_steps_ms": ms_plain, "forward_over_plain": fwd_ms / ms_plain,
+                      "backward_over_plain": bwd_ms / ms_plain,
+                      "gradient_solves_per_s": batch * steps / ((fwd_ms + bwd_ms) * 1e-3)}
+    del qs, qds, q0, qd0, tt, qT, qdT
     model.close()
-    del tq, tqd, ttau, taus, qdd, g, gq, gqd, gt, ws, bws
+    del tq, tqd, taus, qdd, ws
     torch.cuda.empty_cache()
     # launch-bound sizes: a 100-step rollout (no gradient) of 64 chains of 16 links
     # (JSIIA, the fastest there), launched step by step against the same steps
@@ -665,7 +808,7 @@ def adjoint_leg(dtype: str, reps: int = 10, steps: int = 50):
         ms_fwd = timed(lambda: model.forward(tq, tqd, ttau, batch=w["batch"], algo="abia", out=qdd, workspace=ws,
                                              stream=stream), reps)
         g = torch.from_numpy(np.random.default_rng(5).standard_normal(len(q))).to(dev, tdt)
-        bws = model.backward_workspace(w["batch"])
+        bws = model.backward_workspace(w["batch"], "abia")
         gq, gqd, gt = (torch.empty_like(tq) for _ in range(3))
         ms_vjp = timed(lambda: model.backward(tq, tqd, qdd, g, batch=w["batch"], grad_q=gq, grad_qd=gqd,
                                               grad_tau=gt, workspace=bws, stream=stream), reps)
@@ -675,6 +818,24 @@ def adjoint_leg(dtype: str, reps: int = 10, steps: int = 50):
         del tq, tqd, ttau, qdd, g, gq, gqd, gt, ws, bws
         torch.cuda.empty_cache()
     return out
+
+
+def experiments_leg(dtype: str, calls: int = 200):
+    """The paper's two experiment shapes (Sec. V) on this GPU, FP64: Exp. 1, the
+    time of one call for one robot against its number of links; Exp. 2, the time
+    of one call over a group of independent robots of 10 and of 200 links
+    against the group size. Mean over back-to-back calls with fresh random
+    inputs each (launch overhead included), as the paper times them."""
+    from paper_1609_06779_amd import tune
+
+    rows = tune.experiments(dtype, calls=calls)
+    exp1, exp2 = {}, {}
+    for r in rows:
+        if r["exp"] == 1:
+            exp1.setdefault(r["algo"], {})[str(r["n"])] = None if r["ms"] is None else r["ms"] * 1e3
+        else:
+            exp2.setdefault(f"n{r['n']}", {}).setdefault(r["algo"], {})[str(r["groups"])] = r["ms"]
+    return {"calls": calls, "exp1_us_per_call": exp1, "exp2_ms_per_call": exp2}
 
 
 TREE_WORKLOADS = ("tree-shared-n64-b65536", "tree-n64-b65536")
@@ -747,12 +908,15 @@ def main():
     ap.add_argument("--algos", default="abia,jsiia,cfa")
     ap.add_argument("--cpu-chains", type=int, default=65536)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the oracle's reference values for the per-(algorithm, n, dtype) error record")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--no-tree", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-transfer", action="store_true")
     ap.add_argument("--no-levels", action="store_true")
+    ap.add_argument("--no-experiments", action="store_true")
     ap.add_argument("--no-nsweep", action="store_true")
     ap.add_argument("--only-step", action="store_true",
                     help="time the step alone: no legs and no CPU baseline (the profiled command)")
@@ -774,7 +938,7 @@ def main():
     args = ap.parse_args()
     if args.only_step:
         args.no_cpu = args.no_serve = args.no_ragged = args.no_tree = args.no_adjoint = args.no_transfer = True
-        args.no_levels = args.no_nsweep = True
+        args.no_levels = args.no_nsweep = args.no_experiments = True
     wl = args.workload or f"fd_forward_n{args.n}_b{args.batch}_{args.dtype}"
     wl_flag = f" --workload {args.workload}" if args.workload else ""
     if args.trace_summary:
@@ -899,6 +1063,9 @@ def main():
     if not args.no_nsweep:
         print("[bench] n sweep leg", file=sys.stderr, flush=True)
         result["n_sweep"] = nsweep_leg()
+    if not args.no_experiments:
+        print("[bench] experiments leg", file=sys.stderr, flush=True)
+        result["experiments"] = experiments_leg(args.dtype)
     if not args.no_levels:
         print("[bench] levels leg", file=sys.stderr, flush=True)
         result["levels"] = levels_leg(args.dtype)
@@ -914,7 +1081,10 @@ def main():
         l80 = result["serving"]["load_80pct"]
         result["p99_latency_ms_at_80pct_load"] = l80["p99_ms"]
     if not args.no_cpu and args.dtype == "f64":
+        print("[bench] cpu baseline leg", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(rb, q, qd, tau, min(args.cpu_chains, args.batch))
+        if not args.no_accuracy:
+            result["cpu_baseline"]["accuracy"] = cpu_baseline_accuracy()
     print(json.dumps(result), flush=True)
 
 

@@ -74,7 +74,10 @@ typedef struct {
     int32_t num_robots;
     const int32_t* n_links;  /* [num_robots] */
     const double* axis;      /* [L][3] joint axis in frame i (non-zero; normalised by fd_init) */
-    const double* home_rot;  /* [L][9] row-major Rhome_i (a rotation), or NULL for identity */
+    const double* home_rot;  /* [L][9] row-major Rhome_i, or NULL for identity. Must be a rotation
+                                to within 1e-6 (|R^T R - I| entrywise, det R); fd_init replaces it
+                                by the nearest rotation (the orthogonal factor of its polar
+                                decomposition), so every path reads one and the same rotation. */
     const double* offset;    /* [L][3] origin of frame i in frame i-1 */
     const double* mass;      /* [L] > 0 */
     const double* com;       /* [L][3] centre of mass in frame i */
@@ -109,8 +112,16 @@ fd_dtype_t fd_model_dtype(const fd_model_t* model);
  * 0 for an algorithm that does not take the model's branched robots). */
 int32_t fd_max_links(const fd_model_t* model, fd_algo_t algo);
 
-/* Bytes of workspace fd_forward needs for this batch and algorithm (0 if none). */
+/* Bytes of workspace fd_forward needs for this batch and algorithm (0 if none).
+ * Reads no device memory: of robot_id and offsets only whether they are NULL
+ * matters (the same holds for the other *_workspace_size calls). */
 fd_status_t fd_workspace_size(const fd_model_t* model, const fd_batch_t* batch, fd_algo_t algo, size_t* bytes);
+
+/* The algorithm FD_ALGO_AUTO takes for this batch (fd_set_auto_table), and
+ * whether it runs as the persistent launch of fd_forward_persistent
+ * (*persistent = 1; may be NULL). Like fd_workspace_size, it reads no device
+ * memory: of robot_id and offsets only whether they are NULL matters. */
+fd_status_t fd_auto_algo(const fd_model_t* model, const fd_batch_t* batch, fd_algo_t* algo, int* persistent);
 
 /* Forward dynamics, eq. (tau-bias): qdd = M(q)^-1 (tau - tau_bias(q, qd)).
  * q, qd, tau, qdd: device arrays of the model's precision (double or float),
@@ -144,14 +155,24 @@ fd_status_t fd_forward_persistent(const fd_model_t* model, const fd_batch_t* bat
  *     grad_tau = lambda = M(q)^-1 grad_qdd,
  *     [grad_q; grad_qd] = -(d ID / d(q, qd))^T lambda   at (q, qd, qdd),
  * the implicit-function theorem applied to ID(q, qd, qdd) = tau (eq. (eq-motion)).
- * lambda uses the articulated-body factorisation of M^-1 (Sec. II-C). accumulate
- * != 0 adds to the three gradient arrays instead of overwriting them. All arrays
- * are device arrays of the model's precision, packed per chain; the workspace
- * must hold fd_backward_workspace_size bytes. Asynchronous. */
-fd_status_t fd_backward_workspace_size(const fd_model_t* model, const fd_batch_t* batch, size_t* bytes);
+ * algo names the factorisation of M^-1 that gives lambda, as in fd_forward
+ * (Sec. II-C, Sec. III): FD_ALGO_ABIA runs the articulated-body recursion inside
+ * the reverse-mode kernel; FD_ALGO_JSIIA and FD_ALGO_CFA run their forward
+ * kernel on M lambda = grad_qdd (tau_delta := grad_qdd: zero velocity, no
+ * gravity); FD_ALGO_AUTO picks as fd_forward does. The transposed inverse
+ * dynamics is one lane-per-chain kernel for every algo. qdd may be NULL: it is
+ * then computed from (q, qd, tau) by the same algorithm first (tau is read only
+ * then and may otherwise be NULL). accumulate != 0 adds to the three gradient
+ * arrays instead of overwriting them. All arrays are device arrays of the
+ * model's precision, packed per chain; the workspace must hold
+ * fd_backward_workspace_size bytes for the same batch and algo. Asynchronous.
+ * FD_ERR_UNSUPPORTED where fd_forward would refuse the algorithm. */
+fd_status_t fd_backward_workspace_size(const fd_model_t* model, const fd_batch_t* batch, fd_algo_t algo,
+                                       size_t* bytes);
 fd_status_t fd_backward(const fd_model_t* model, const fd_batch_t* batch, const void* q, const void* qd,
-                        const void* qdd, const void* grad_qdd, void* grad_q, void* grad_qd, void* grad_tau,
-                        int accumulate, void* workspace, size_t ws_bytes, void* hip_stream);
+                        const void* tau, const void* qdd, const void* grad_qdd, void* grad_q, void* grad_qd,
+                        void* grad_tau, fd_algo_t algo, int accumulate, void* workspace, size_t ws_bytes,
+                        void* hip_stream);
 
 /* One semi-implicit Euler step of a rollout, elementwise over count entries:
  * qd_next = qd + dt qdd, q_next = q + dt qd_next. Outputs may alias inputs

@@ -15,7 +15,8 @@ DTYPES = {"f64": 0, "f32": 1}
 EXPORTS = ("fd_init", "fd_destroy", "fd_model_dtype", "fd_max_links", "fd_workspace_size", "fd_forward",
            "fd_persistent_workspace_size", "fd_forward_persistent",
            "fd_backward_workspace_size", "fd_backward", "fd_euler_step", "fd_euler_step_backward",
-           "fd_inverse", "fd_joint_inertia", "fd_scan6", "fd_btd_solve6", "fd_set_auto_table", "fd_status_string")
+           "fd_inverse", "fd_joint_inertia", "fd_scan6", "fd_btd_solve6", "fd_set_auto_table", "fd_status_string",
+           "fd_auto_algo")
 
 
 class ModelDesc(ctypes.Structure):
@@ -76,9 +77,10 @@ def load() -> ctypes.CDLL:
     lib.fd_persistent_workspace_size.restype = ctypes.c_int
     lib.fd_forward_persistent.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, vp, vp, i32, vp, sz, vp]
     lib.fd_forward_persistent.restype = ctypes.c_int
-    lib.fd_backward_workspace_size.argtypes = [vp, ctypes.POINTER(Batch), ctypes.POINTER(sz)]
+    lib.fd_backward_workspace_size.argtypes = [vp, ctypes.POINTER(Batch), ctypes.c_int, ctypes.POINTER(sz)]
     lib.fd_backward_workspace_size.restype = ctypes.c_int
-    lib.fd_backward.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp, sz, vp]
+    lib.fd_backward.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_int,
+                                vp, sz, vp]
     lib.fd_backward.restype = ctypes.c_int
     lib.fd_euler_step.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_double, vp, vp, vp, vp, vp, vp]
     lib.fd_euler_step.restype = ctypes.c_int
@@ -94,6 +96,8 @@ def load() -> ctypes.CDLL:
     lib.fd_btd_solve6.restype = ctypes.c_int
     lib.fd_set_auto_table.argtypes = [ctypes.c_int, vp]
     lib.fd_set_auto_table.restype = ctypes.c_int
+    lib.fd_auto_algo.argtypes = [vp, ctypes.POINTER(Batch), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    lib.fd_auto_algo.restype = ctypes.c_int
     lib.fd_status_string.argtypes = [ctypes.c_int]
     lib.fd_status_string.restype = ctypes.c_char_p
     _lib = lib

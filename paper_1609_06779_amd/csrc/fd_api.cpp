@@ -53,6 +53,27 @@ bool valid_rotation(const double* r) {
     return std::fabs(det - 1.0) < 1e-6;
 }
 
+// The rotation nearest to r in the Frobenius norm (the orthogonal factor of
+// its polar decomposition), for an r that valid_rotation accepted: Newton-Schulz
+// steps X <- X (3 I - X^T X) / 2 converge quadratically from ||X^T X - I|| <= 1e-6,
+// so two steps reach rounding level; a few more cost nothing.
+void polar_rotation(const double* r, double* out) {
+    double x[9];
+    std::memcpy(x, r, sizeof(x));
+    for (int it = 0; it < 4; ++it) {
+        double g[9], y[9];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                g[3 * i + j] = (i == j ? 3.0 : 0.0) -
+                               (x[i] * x[j] + x[3 + i] * x[3 + j] + x[6 + i] * x[6 + j]);   // 3 I - X^T X
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                y[3 * i + j] = 0.5 * (x[3 * i] * g[j] + x[3 * i + 1] * g[3 + j] + x[3 * i + 2] * g[6 + j]);
+        std::memcpy(x, y, sizeof(x));
+    }
+    std::memcpy(out, x, sizeof(x));
+}
+
 bool valid_inertia(const double* in) {
     for (int k = 0; k < 6; ++k)
         if (!std::isfinite(in[k])) return false;
@@ -172,31 +193,85 @@ fd_algo_t pick_algo(const fd_model* m, int nmax, int batch) {
 // running to the longest chain of its 64.
 bool auto_persistent(const fd_batch_t* b, fd_algo_t picked) { return b->offsets != nullptr && picked == FD_ALGO_ABIA; }
 
+// Lane groups of a lane-per-link launch, or FD_ERR_UNSUPPORTED when the
+// algorithm does not take this model or chain length.
+template <typename T> fd_status_t lane_path_check(const fd_model* m, fd_algo_t algo, int np) {
+    if (algo == FD_ALGO_JSIIA && ((m->tree && !m->depth_first) || np > fdk::jsiia_max_np<T>())) return FD_ERR_UNSUPPORTED;
+    if (algo == FD_ALGO_CFA && m->tree) return FD_ERR_UNSUPPORTED;
+    return FD_OK;
+}
+
 template <typename T>
 fd_status_t forward_t(const fd_model* m, const BatchPlan& p, const void* q, const void* qd, const void* tau,
-                      void* qdd, fd_algo_t algo, void* ws, size_t ws_bytes, hipStream_t st) {
+                      void* qdd, fd_algo_t algo, void* ws, size_t ws_bytes, hipStream_t st,
+                      const fdk::FdOut<T>& o = fdk::FdOut<T>{}) {
     const auto v = view<T>(m);
     const T* tq = static_cast<const T*>(q);
     const T* tqd = static_cast<const T*>(qd);
     const T* tt = static_cast<const T*>(tau);
     T* out = static_cast<T*>(qdd);
     const int np = pow2_lanes(p.nmax);
+    const fd_status_t ok = lane_path_check<T>(m, algo, np);
+    if (ok != FD_OK) return ok;
     switch (algo) {
         case FD_ALGO_ABIA: {
             size_t need = fdk::abia_workspace_elems(p.cm.batch, p.nmax, m->tree) * sizeof(T);
             if (!ws || ws_bytes < need) return FD_ERR_WORKSPACE;
             return from_hip(fdk::launch_abia<T>(v, p.cm, p.nmax, tq, tqd, tt, out, static_cast<T*>(ws),
-                                                stream_model(m, p.cm.batch, p.nmax), st));
+                                                stream_model(m, p.cm.batch, p.nmax), o, st));
         }
         case FD_ALGO_JSIIA:
-            if ((m->tree && !m->depth_first) || np > fdk::jsiia_max_np<T>()) return FD_ERR_UNSUPPORTED;
-            return from_hip(fdk::launch_jsiia<T>(np, v, p.cm, tq, tqd, tt, out, nullptr, st));
+            return from_hip(fdk::launch_jsiia<T>(np, v, p.cm, tq, tqd, tt, out, nullptr, o, st));
         case FD_ALGO_CFA:
-            if (m->tree) return FD_ERR_UNSUPPORTED;
-            return from_hip(fdk::launch_cfa<T>(np, v, p.cm, tq, tqd, tt, out, nullptr, st));
+            return from_hip(fdk::launch_cfa<T>(np, v, p.cm, tq, tqd, tt, out, nullptr, o, st));
         default:
             return FD_ERR_INVALID_ARG;
     }
+}
+
+// Reverse mode. The VJP kernel's workspace comes first; an ABIA forward that
+// recomputes qdd (qdd == NULL) takes its own workspace after it.
+template <typename T>
+size_t backward_bytes(const fd_model* m, const BatchPlan& p, fd_algo_t algo) {
+    const size_t vjp = fdk::vjp_workspace_elems(p.cm.batch, p.nmax, m->tree) * sizeof(T);
+    const size_t fwd = algo == FD_ALGO_ABIA ? fdk::abia_workspace_elems(p.cm.batch, p.nmax, m->tree) * sizeof(T) : 0;
+    return vjp + fwd;
+}
+
+template <typename T>
+fd_status_t backward_t(const fd_model* m, const BatchPlan& p, const void* q, const void* qd, const void* tau,
+                       const void* qdd, const void* gqdd, void* gq, void* gqd, void* gtau, fd_algo_t algo,
+                       int accumulate, void* ws, size_t ws_bytes, hipStream_t st) {
+    const int np = pow2_lanes(p.nmax);
+    fd_status_t s = lane_path_check<T>(m, algo, np);
+    if (s != FD_OK) return s;
+    if (!ws || ws_bytes < backward_bytes<T>(m, p, algo)) return FD_ERR_WORKSPACE;
+    T* vws = static_cast<T*>(ws);
+    const size_t vjp_elems = fdk::vjp_workspace_elems(p.cm.batch, p.nmax, m->tree);
+    fdk::FdOut<T> to_ws;                          // a result handed to the VJP kernel through its workspace
+    to_ws.aux = vws;
+    to_ws.aux_nmax = p.nmax;
+    to_ws.aux_fields = fdk::vjp_fields_of(m->tree);
+    if (!qdd) {                                   // qdd = FD(q, qd, tau) by the same factorisation
+        to_ws.aux_field = fdk::vjp_field_qdd();
+        s = forward_t<T>(m, p, q, qd, tau, nullptr, algo, vws + vjp_elems, ws_bytes - vjp_elems * sizeof(T), st,
+                         to_ws);
+        if (s != FD_OK) return s;
+    }
+    const bool lam_in = algo != FD_ALGO_ABIA;
+    if (lam_in) {                                 // lambda = M^-1 g by the JSIIA or the CFA, into grad_tau and the workspace
+        fdk::FdOut<T> lam = to_ws;
+        lam.aux_field = fdk::vjp_field_lambda();
+        lam.solve = 1;
+        lam.accumulate = accumulate;
+        s = forward_t<T>(m, p, q, nullptr, gqdd, gtau, algo, nullptr, 0, st, lam);
+        if (s != FD_OK) return s;
+    }
+    return from_hip(fdk::launch_fd_vjp<T>(view<T>(m), p.cm, p.nmax, static_cast<const T*>(q),
+                                          static_cast<const T*>(qd), static_cast<const T*>(qdd),
+                                          static_cast<const T*>(gqdd), static_cast<T*>(gq), static_cast<T*>(gqd),
+                                          static_cast<T*>(gtau), accumulate, lam_in, vws,
+                                          stream_model(m, p.cm.batch, p.nmax), st));
 }
 
 }  // namespace
@@ -270,7 +345,8 @@ fd_status_t fd_init(const fd_model_desc_t* d, fd_dtype_t dtype, fd_model_t** out
             if (!valid_inertia(d->inertia + 6 * l)) return FD_ERR_INVALID_ARG;
             double* w = raw.data() + 25 * l;
             std::memcpy(w + 0, ax, 3 * sizeof(double));
-            std::memcpy(w + 3, hr, 9 * sizeof(double));
+            // every path (matrix, quaternion) then reads one and the same rotation
+            polar_rotation(hr, w + 3);
             std::memcpy(w + 12, d->offset + 3 * l, 3 * sizeof(double));
             w[15] = d->mass[l];
             std::memcpy(w + 16, d->com + 3 * l, 3 * sizeof(double));
@@ -408,6 +484,16 @@ fd_status_t fd_workspace_size(const fd_model_t* m, const fd_batch_t* b, fd_algo_
     return FD_OK;
 }
 
+fd_status_t fd_auto_algo(const fd_model_t* m, const fd_batch_t* b, fd_algo_t* algo, int* persistent) {
+    if (!algo) return FD_ERR_INVALID_ARG;
+    BatchPlan p;
+    fd_status_t s = plan_batch(m, b, &p);
+    if (s != FD_OK) return s;
+    *algo = pick_algo(m, p.nmax, b->batch);
+    if (persistent) *persistent = auto_persistent(b, *algo) ? 1 : 0;
+    return FD_OK;
+}
+
 fd_status_t fd_forward(const fd_model_t* m, const fd_batch_t* b, const void* q, const void* qd, const void* tau,
                        void* qdd, fd_algo_t algo, void* ws, size_t ws_bytes, void* hip_stream) {
     BatchPlan p;
@@ -474,36 +560,36 @@ fd_status_t fd_forward_persistent(const fd_model_t* m, const fd_batch_t* b, cons
                                                        planp, m->d_slot_robot, stream_model(m, b->batch, p.nmax), st));
 }
 
-fd_status_t fd_backward_workspace_size(const fd_model_t* m, const fd_batch_t* b, size_t* bytes) {
+// The algorithm a reverse-mode call runs: AUTO takes fd_forward's choice.
+fd_algo_t backward_algo(const fd_model* m, const BatchPlan& p, int batch, fd_algo_t algo) {
+    return algo == FD_ALGO_AUTO ? pick_algo(m, p.nmax, batch) : algo;
+}
+
+fd_status_t fd_backward_workspace_size(const fd_model_t* m, const fd_batch_t* b, fd_algo_t algo, size_t* bytes) {
     if (!bytes) return FD_ERR_INVALID_ARG;
     BatchPlan p;
     fd_status_t s = plan_batch(m, b, &p);
     if (s != FD_OK) return s;
-    const size_t esz = m->dtype == FD_F64 ? sizeof(double) : sizeof(float);
-    *bytes = fdk::vjp_workspace_elems(b->batch, p.nmax, m->tree) * esz;
+    if (algo < FD_ALGO_ABIA || algo > FD_ALGO_AUTO) return FD_ERR_INVALID_ARG;
+    algo = backward_algo(m, p, b->batch, algo);
+    *bytes = m->dtype == FD_F64 ? backward_bytes<double>(m, p, algo) : backward_bytes<float>(m, p, algo);
     return FD_OK;
 }
 
-fd_status_t fd_backward(const fd_model_t* m, const fd_batch_t* b, const void* q, const void* qd, const void* qdd,
-                        const void* gqdd, void* gq, void* gqd, void* gtau, int accumulate, void* ws, size_t ws_bytes,
-                        void* hip_stream) {
+fd_status_t fd_backward(const fd_model_t* m, const fd_batch_t* b, const void* q, const void* qd, const void* tau,
+                        const void* qdd, const void* gqdd, void* gq, void* gqd, void* gtau, fd_algo_t algo,
+                        int accumulate, void* ws, size_t ws_bytes, void* hip_stream) {
     BatchPlan p;
     fd_status_t s = plan_batch(m, b, &p);
     if (s != FD_OK) return s;
+    if (algo < FD_ALGO_ABIA || algo > FD_ALGO_AUTO) return FD_ERR_INVALID_ARG;
     if (b->batch == 0) return FD_OK;
-    if (!q || !qd || !qdd || !gqdd || !gq || !gqd || !gtau) return FD_ERR_INVALID_ARG;
-    const size_t esz = m->dtype == FD_F64 ? sizeof(double) : sizeof(float);
-    if (!ws || ws_bytes < fdk::vjp_workspace_elems(b->batch, p.nmax, m->tree) * esz) return FD_ERR_WORKSPACE;
+    if (!q || !qd || (!qdd && !tau) || !gqdd || !gq || !gqd || !gtau) return FD_ERR_INVALID_ARG;
+    algo = backward_algo(m, p, b->batch, algo);
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     if (m->dtype == FD_F64)
-        return from_hip(fdk::launch_fd_vjp<double>(view<double>(m), p.cm, p.nmax, (const double*)q, (const double*)qd,
-                                                   (const double*)qdd, (const double*)gqdd, (double*)gq, (double*)gqd,
-                                                   (double*)gtau, accumulate, (double*)ws,
-                                                   stream_model(m, b->batch, p.nmax), st));
-    return from_hip(fdk::launch_fd_vjp<float>(view<float>(m), p.cm, p.nmax, (const float*)q, (const float*)qd,
-                                              (const float*)qdd, (const float*)gqdd, (float*)gq, (float*)gqd,
-                                              (float*)gtau, accumulate, (float*)ws,
-                                              stream_model(m, b->batch, p.nmax), st));
+        return backward_t<double>(m, p, q, qd, tau, qdd, gqdd, gq, gqd, gtau, algo, accumulate, ws, ws_bytes, st);
+    return backward_t<float>(m, p, q, qd, tau, qdd, gqdd, gq, gqd, gtau, algo, accumulate, ws, ws_bytes, st);
 }
 
 fd_status_t fd_euler_step(fd_dtype_t dtype, int64_t count, double dt, const void* q, const void* qd, const void* qdd,

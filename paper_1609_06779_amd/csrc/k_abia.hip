@@ -4,9 +4,12 @@
 // cannot be split across processors beyond a constant factor (Sec. III), so a
 // whole chain stays on one lane and a wavefront carries 64 chains. Three sweeps:
 //  1. forward (base to tip): link velocities and bias accelerations of the
-//     inverse dynamics at qdd = 0 (gravity as base acceleration), and the link
-//     forces f_i = J_i a_i - ad_{v_i}^T J_i v_i (kept in the workspace);
-//  2. backward: the force recursion gives tau_delta_i = tau_i - S_i^T F_i; in
+//     inverse dynamics at qdd = 0 (gravity as base acceleration), carried to
+//     the tip;
+//  2. backward: the same velocities and accelerations walked back from the tip
+//     (each step of the forward recursion inverted), the link forces
+//     f_i = J_i a_i - ad_{v_i}^T J_i v_i, and the force recursion, which gives
+//     tau_delta_i = tau_i - S_i^T F_i; in
 //     the same sweep the articulated inertias
 //        Jh_i = J_i + Ad_{i+1}^T (Jh_{i+1} - h h^T / D)_{i+1} Ad_{i+1},
 //        h_i = Jh_i S_i, D_i = S_i^T h_i,
@@ -16,7 +19,8 @@
 //        a_i = Ad_i a_{i-1} + S_i qdd_i,  qdd_i = (u_i - h_i^T Ad_i a_{i-1}) / D_i,
 // which together apply M^-1 to tau_delta (zero velocity, no gravity).
 //
-// Branched robots (trees; the paper treats serial chains): link i takes its
+// Branched robots (trees; the paper treats serial chains): sweep 1 keeps every
+// link force in the workspace for sweep 2, and link i takes its
 // parent p(i)'s velocity and accelerations instead of link i-1's, and hands
 // its backward-sweep terms (F, p and Jh - h h^T / D, moved into p(i)'s frame)
 // to p(i), where the terms of all children add up. A child whose parent is
@@ -33,7 +37,7 @@
 
 namespace fdk {
 
-constexpr int ABIA_WS_FIELDS = 7;   // sweep 1: f (6); sweep 2 overwrites: h / D (6), u / D (1)
+constexpr int ABIA_WS_FIELDS = 7;   // sweep 2: h / D (6), u / D (1); trees: sweep 1 f (6) first
 // Trees add a branch-point record after those 7 fields: sweep 1 velocity (6)
 // and bias acceleration (6); sweep 2 accumulator of the children's F (6), p (6)
 // and Jh - h h^T / D (21, upper triangle by rows); sweep 3 acceleration (6).
@@ -82,9 +86,9 @@ template <typename T> __device__ __forceinline__ void congruence_to_parent(const
 template <bool NT, bool TREE, typename T>
 __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInfo& ci, const T* __restrict__ q,
                                            const T* __restrict__ qd, const T* __restrict__ tau,
-                                           T* __restrict__ qdd, T* __restrict__ wsb) {
+                                           T* __restrict__ qdd, T* __restrict__ wsb, int b, const FdOut<T>& o) {
     if (ci.unsolved) {                                 // longer than the workspace is sized for
-        fill_unsolved(qdd, ci.state0, ci.unsolved, 0, 1);
+        if (qdd) fill_unsolved(qdd, ci.state0, ci.unsolved, 0, 1);
         return;
     }
     const int n = ci.n;
@@ -121,11 +125,13 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
         t[3] += v[4] * qdi; t[4] -= v[3] * qdi;
 #pragma unroll
         for (int c = 0; c < 6; ++c) a[c] = t[c];
-        T f[6];
-        link_force(m.template inertia_il<NT>(i, ci.slot), v, a, f);
-#pragma unroll
-        for (int c = 0; c < 6; ++c) st_ws<NT>(f[c], wsp(i, c));
         if constexpr (TREE) {
+            // trees keep every link force: the backward sweep cannot walk the
+            // twists back from one tip past a branch point
+            T f[6];
+            link_force(m.template inertia_il<NT>(i, ci.slot), v, a, f);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) st_ws<NT>(f[c], wsp(i, c));
             if (code & TREE_BRANCH) {
 #pragma unroll
                 for (int c = 0; c < 6; ++c) {
@@ -144,14 +150,37 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
 #pragma unroll
     for (int c = 0; c < 36; ++c) pi[c] = T(0);
     Pose<T> tn = pose_identity<T>();                   // T_{i,i+1}
+    T qdn = T(0);                                      // chains: qd_{i+1}
     bool carry = false;                                // trees: registers hold link i+1's terms for link i
 #pragma unroll 2   // loads of two links in flight
     for (int i = n - 1; i >= 0; --i) {
         const int64_t st = ci.state0 + i;
         T f[6], fp[6], pp[6], jh[36];
+        const Inertia<T> ji = m.template inertia_il<NT>(i, ci.slot);
+        if constexpr (TREE) {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) f[c] = ld_ws<NT>(wsp(i, c));
-        inertia_to_mat6(m.template inertia_il<NT>(i, ci.slot), jh);
+            for (int c = 0; c < 6; ++c) f[c] = ld_ws<NT>(wsp(i, c));
+        } else {
+            // Serial chains: sweep 1 left the tip's twist and bias acceleration
+            // in (v, a); walk them back one link at a time, inverting its
+            // recursions: V_i = Ad_{T_{i,i+1}} (V_{i+1} - S qd_{i+1}),
+            // a_i = Ad_{T_{i,i+1}} (a_{i+1} - ad_{V_{i+1}} (S qd_{i+1})).
+            // The link force then needs no round trip through memory.
+            if (i + 1 < n) {
+                T t[6];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) t[c] = a[c];
+                t[0] -= v[1] * qdn; t[1] += v[0] * qdn;
+                t[3] -= v[4] * qdn; t[4] += v[3] * qdn;
+                ad_apply(tn, t, a);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) t[c] = v[c];
+                t[2] -= qdn;
+                ad_apply(tn, t, v);
+            }
+            link_force(ji, v, a, f);
+        }
+        inertia_to_mat6(ji, jh);
         const int32_t code = TREE ? m.template tree_il<NT>(i, ci.slot) : 0;
         if (TREE && carry) {                           // terms already in this link's frame
 #pragma unroll
@@ -211,6 +240,7 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
             fc[c] = f[c];
         }
         tn = link_pose_at<NT>(m, i, ci.slot, q[st]);
+        if constexpr (!TREE) qdn = qd[st];
         if constexpr (TREE) {
             // Move the terms into the parent's frame here, once per link, on
             // every lane: the parent takes them from registers (chain step) or
@@ -284,13 +314,13 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
 template <typename T, bool NT, bool TREE>
 __global__ __launch_bounds__(64) void k_abia(ModelView<T> m, ChainMap cm, int nmax, const T* __restrict__ q,
                                              const T* __restrict__ qd, const T* __restrict__ tau,
-                                             T* __restrict__ qdd, T* __restrict__ ws) {
+                                             T* __restrict__ qdd, T* __restrict__ ws, FdOut<T> o) {
     const int lane = threadIdx.x;
     const int b = blockIdx.x * 64 + lane;
     if (b >= cm.batch) return;
     // workspace: [block][link][field][lane]
     abia_chain<NT, TREE>(m, chain_info(m, cm, b), q, qd, tau, qdd,
-                         ws + (size_t)blockIdx.x * nmax * abia_fields<TREE>() * 64 + lane);
+                         ws + (size_t)blockIdx.x * nmax * abia_fields<TREE>() * 64 + lane, b, o);
 }
 
 // Persistent form for ragged batches: each wavefront takes 64-entry tiles of
@@ -316,7 +346,7 @@ __global__ __launch_bounds__(64) void k_abia_persistent(ModelView<T> m, ChainMap
         if ((int64_t)tile * 64 >= count) break;
         const int k = tile * 64 + lane;
         const int b = k < count ? (order ? order[k] : k) : cm.batch;
-        if (b < cm.batch) abia_chain<NT, TREE>(m, chain_info(m, cm, b), q, qd, tau, qdd, wsb);
+        if (b < cm.batch) abia_chain<NT, TREE>(m, chain_info(m, cm, b), q, qd, tau, qdd, wsb, b, FdOut<T>{});
     }
 }
 
@@ -414,23 +444,26 @@ hipError_t launch_abia_persistent(const ModelView<T>& m, const ChainMap& cm, int
 
 template <typename T>
 hipError_t launch_abia(const ModelView<T>& m, const ChainMap& cm, int nmax, const T* q, const T* qd, const T* tau,
-                       T* qdd, T* ws, bool stream_model, hipStream_t st) {
+                       T* qdd, T* ws, bool stream_model, const FdOut<T>& o, hipStream_t st) {
     if (cm.batch <= 0) return hipSuccess;
     const dim3 grid((cm.batch + 63) / 64);
+#define FDK_ABIA(NT, TREE) \
+    hipLaunchKernelGGL((k_abia<T, NT, TREE>), grid, dim3(64), 0, st, m, cm, nmax, q, qd, tau, qdd, ws, o)
     if (m.tree) {
-        if (stream_model) hipLaunchKernelGGL((k_abia<T, true, true>), grid, dim3(64), 0, st, m, cm, nmax, q, qd, tau, qdd, ws);
-        else hipLaunchKernelGGL((k_abia<T, false, true>), grid, dim3(64), 0, st, m, cm, nmax, q, qd, tau, qdd, ws);
+        if (stream_model) FDK_ABIA(true, true);
+        else FDK_ABIA(false, true);
     } else {
-        if (stream_model) hipLaunchKernelGGL((k_abia<T, true, false>), grid, dim3(64), 0, st, m, cm, nmax, q, qd, tau, qdd, ws);
-        else hipLaunchKernelGGL((k_abia<T, false, false>), grid, dim3(64), 0, st, m, cm, nmax, q, qd, tau, qdd, ws);
+        if (stream_model) FDK_ABIA(true, false);
+        else FDK_ABIA(false, false);
     }
+#undef FDK_ABIA
     return hipGetLastError();
 }
 
 template hipError_t launch_abia<double>(const ModelView<double>&, const ChainMap&, int, const double*, const double*,
-                                        const double*, double*, double*, bool, hipStream_t);
+                                        const double*, double*, double*, bool, const FdOut<double>&, hipStream_t);
 template hipError_t launch_abia<float>(const ModelView<float>&, const ChainMap&, int, const float*, const float*,
-                                       const float*, float*, float*, bool, hipStream_t);
+                                       const float*, float*, float*, bool, const FdOut<float>&, hipStream_t);
 template hipError_t launch_abia_persistent<double>(const ModelView<double>&, const ChainMap&, int, int, const double*,
                                                    const double*, const double*, double*, double*, int32_t*,
                                                    const int32_t*, bool, hipStream_t);

@@ -26,6 +26,12 @@
 // ab, Vb and the gradients. Fb needs only lambda, so it rides with the forward
 // recursions, and F runs backward like ab and Vb, so those share one sweep.
 //
+// lambda may instead come from another factorisation of M^-1 (the JSIIA or the
+// CFA kernel solving M lambda = g): with lam_in set, sweep A is skipped and
+// sweep B reads lambda from the workspace (field VJP_UD), where that kernel
+// left it; it has also written grad_tau. qdd may be null: the forward kernel
+// then left it in the workspace (field VJP_A, read before sweep B overwrites it).
+//
 // Branched robots (trees): i - 1 reads p(i) in the forward recursions, and the
 // backward ones sum the terms A_c^T (.) of all children c of i, as in the
 // tree form of the ABIA: a child whose parent is i - 1 passes them in
@@ -43,9 +49,9 @@ namespace fdk {
 // workspace fields per link (block-interleaved like the ABIA workspace)
 constexpr int VJP_HD = 0;      // h / D (6), written in sweep A
 constexpr int VJP_FB = 0;      // then Fb (6), written over h / D in sweep B
-constexpr int VJP_UD = 6;      // u / D
+constexpr int VJP_UD = 6;      // u / D (lambda, when it comes from another kernel)
 constexpr int VJP_V = 7;       // V (6)
-constexpr int VJP_A = 13;      // a (6)
+constexpr int VJP_A = 13;      // a (6); entry 0 may hold qdd until sweep B reaches the link
 constexpr int VJP_F = 19;      // f (6); trees add the children's A_c^T F_c into it
 constexpr int VJP_FIELDS = 25;
 // Trees add a branch-point record after those 25 fields, reused sweep by sweep:
@@ -97,7 +103,7 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
                                                const T* __restrict__ qd, const T* __restrict__ qdd,
                                                const T* __restrict__ gqdd, T* __restrict__ gq,
                                                T* __restrict__ gqd, T* __restrict__ gtau, int accumulate,
-                                               T* __restrict__ ws) {
+                                               int lam_in, T* __restrict__ ws) {
     const int lane = threadIdx.x;
     const int b = blockIdx.x * 64 + lane;
     if (b >= cm.batch) return;
@@ -120,7 +126,7 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
     auto code_of = [&](int i) -> int32_t { return TREE ? m.template tree_il<false>(i, sl) : 0; };
 
     // A: articulated-body inertias and the p recursion with tau_delta := g
-    {
+    if (!lam_in) {
         T pc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
         T pi[36];
 #pragma unroll
@@ -211,12 +217,13 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
         for (int i = 0; i < n; ++i) {
             const int64_t st = ci.state0 + i;
             const int32_t code = code_of(i);
+            const T qddi = qdd ? qdd[st] : ldw(i, VJP_A);
             if constexpr (TREE) {
                 if (!(code & TREE_CHAIN)) {            // the parent's terms, not link i-1's
                     const int p = tree_parent(code);
 #pragma unroll
                     for (int c = 0; c < 6; ++c) {
-                        acc[c] = p < 0 ? T(0) : w(p, VJP_WB + c);
+                        acc[c] = p < 0 || lam_in ? T(0) : w(p, VJP_WB + c);
                         fb[c] = p < 0 ? T(0) : ldw(p, VJP_FB + c);
                         v[c] = p < 0 ? T(0) : ldw(p, VJP_V + c);
                         a[c] = p < 0 ? (c < 3 ? T(0) : -m.g[c - 3]) : ldw(p, VJP_A + c);
@@ -225,14 +232,16 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
             }
             const Pose<T> tl = pose_il<NT>(m, i, sl, q[st]);
             T t[6];
-            ad_inv_apply(tl, acc, t);
             T lam = ldw(i, VJP_UD);
+            if (!lam_in) {                             // the a recursion of the M^-1 g solve
+                ad_inv_apply(tl, acc, t);
 #pragma unroll
-            for (int c = 0; c < 6; ++c) lam -= ldw(i, VJP_HD + c) * t[c];
-            t[2] += lam;
+                for (int c = 0; c < 6; ++c) lam -= ldw(i, VJP_HD + c) * t[c];
+                t[2] += lam;
 #pragma unroll
-            for (int c = 0; c < 6; ++c) acc[c] = t[c];
-            gtau[st] = accumulate ? gtau[st] + lam : lam;
+                for (int c = 0; c < 6; ++c) acc[c] = t[c];
+                gtau[st] = accumulate ? gtau[st] + lam : lam;
+            }
             ad_inv_apply(tl, fb, t);
             t[2] += lam;
 #pragma unroll
@@ -241,7 +250,7 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
                 stw(i, VJP_FB + c, t[c]);               // h / D of this link is spent
             }
             if constexpr (TREE) {
-                if (code & TREE_BRANCH) {
+                if ((code & TREE_BRANCH) && !lam_in) {
 #pragma unroll
                     for (int c = 0; c < 6; ++c) w(i, VJP_WB + c) = acc[c];
                 }
@@ -253,7 +262,7 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
 #pragma unroll
             for (int c = 0; c < 6; ++c) v[c] = t[c];
             ad_inv_apply(tl, a, t);
-            t[2] += qdd[st];
+            t[2] += qddi;
             t[0] += v[1] * qdi; t[1] -= v[0] * qdi;      // + ad_V (S qd) = (w x z qd; v x z qd)
             t[3] += v[4] * qdi; t[4] -= v[3] * qdi;
 #pragma unroll
@@ -412,23 +421,24 @@ __global__ void k_euler_vjp(int64_t count, T dt, const T* __restrict__ gqn, cons
 
 template <typename T>
 hipError_t launch_fd_vjp(const ModelView<T>& m, const ChainMap& cm, int nmax, const T* q, const T* qd, const T* qdd,
-                         const T* gqdd, T* gq, T* gqd, T* gtau, int accumulate, T* ws, bool stream, hipStream_t st) {
+                         const T* gqdd, T* gq, T* gqd, T* gtau, int accumulate, int lam_in, T* ws, bool stream,
+                         hipStream_t st) {
     if (cm.batch <= 0) return hipSuccess;
     const dim3 grid((cm.batch + 63) / 64);
-    if (m.tree && stream)
-        hipLaunchKernelGGL((k_fd_vjp<T, true, true>), grid, dim3(64), 0, st, m, cm, nmax, q, qd, qdd, gqdd, gq, gqd,
-                           gtau, accumulate, ws);
-    else if (m.tree)
-        hipLaunchKernelGGL((k_fd_vjp<T, true, false>), grid, dim3(64), 0, st, m, cm, nmax, q, qd, qdd, gqdd, gq, gqd,
-                           gtau, accumulate, ws);
-    else if (stream)
-        hipLaunchKernelGGL((k_fd_vjp<T, false, true>), grid, dim3(64), 0, st, m, cm, nmax, q, qd, qdd, gqdd, gq, gqd,
-                           gtau, accumulate, ws);
-    else
-        hipLaunchKernelGGL((k_fd_vjp<T, false, false>), grid, dim3(64), 0, st, m, cm, nmax, q, qd, qdd, gqdd, gq,
-                           gqd, gtau, accumulate, ws);
+#define FDK_VJP(TREE, NT)                                                                                       \
+    hipLaunchKernelGGL((k_fd_vjp<T, TREE, NT>), grid, dim3(64), 0, st, m, cm, nmax, q, qd, qdd, gqdd, gq, gqd, \
+                       gtau, accumulate, lam_in, ws)
+    if (m.tree && stream) FDK_VJP(true, true);
+    else if (m.tree) FDK_VJP(true, false);
+    else if (stream) FDK_VJP(false, true);
+    else FDK_VJP(false, false);
+#undef FDK_VJP
     return hipGetLastError();
 }
+
+int vjp_fields_of(bool tree) { return tree ? VJP_TREE_FIELDS : VJP_FIELDS; }
+int vjp_field_lambda() { return VJP_UD; }
+int vjp_field_qdd() { return VJP_A; }
 
 template <typename T>
 hipError_t launch_euler(int64_t count, T dt, const T* q, const T* qd, const T* qdd, T* qn, T* qdn, hipStream_t st) {
@@ -449,7 +459,7 @@ hipError_t launch_euler_vjp(int64_t count, T dt, const T* gqn, const T* gqdn, T*
 
 #define FDK_ADJ_INST(T)                                                                                          \
     template hipError_t launch_fd_vjp<T>(const ModelView<T>&, const ChainMap&, int, const T*, const T*, const T*, \
-                                         const T*, T*, T*, T*, int, T*, bool, hipStream_t);                     \
+                                         const T*, T*, T*, T*, int, int, T*, bool, hipStream_t);                \
     template hipError_t launch_euler<T>(int64_t, T, const T*, const T*, const T*, T*, T*, hipStream_t);          \
     template hipError_t launch_euler_vjp<T>(int64_t, T, const T*, const T*, T*, T*, T*, hipStream_t);
 FDK_ADJ_INST(double)

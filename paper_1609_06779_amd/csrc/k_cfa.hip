@@ -24,7 +24,7 @@ __device__ __forceinline__ constexpr int wsel(int a) { return a < 2 ? a : a + 1;
 template <typename T, int NP>
 __global__ __launch_bounds__(Geo<NP>::threads, 2) void k_cfa(ModelView<T> m, ChainMap cm, const T* __restrict__ q,
                                                            const T* __restrict__ qd, const T* __restrict__ tau,
-                                                           T* __restrict__ qdd, int* __restrict__ status) {
+                                                           T* __restrict__ qdd, int* __restrict__ status, FdOut<T> o) {
     // The cross-wavefront scan exchange (NP > 64 only) and the OEE slots share
     // one array: the scans before the OEE and after it end with a barrier, and
     // so does every OEE level.
@@ -40,11 +40,12 @@ __global__ __launch_bounds__(Geo<NP>::threads, 2) void k_cfa(ModelView<T> m, Cha
     const bool active = li < n;
     const int64_t st = ci.state0 + li;
     const int64_t link = ci.link0 + li;
-    T qi = active ? q[st] : T(0), qdi = active ? qd[st] : T(0), ti = active ? tau[st] : T(0);
+    T qi = active ? q[st] : T(0), qdi = active && !o.solve ? qd[st] : T(0), ti = active ? tau[st] : T(0);
 
-    // CalcInvDyn(q, qd, 0) and CalcDiffTorques
+    // CalcInvDyn(q, qd, 0) and CalcDiffTorques (solve mode: zero velocity and no
+    // gravity make the bias exactly zero, so tau_delta = tau)
     LinkLane<T> k;
-    const T tb = rnea_lane<T, NP>(m, link, active, qi, qdi, T(0), true, li, xbuf, k);
+    const T tb = rnea_lane<T, NP>(m, link, active, qi, qdi, T(0), !o.solve, li, xbuf, k);
     const T td = active ? ti - tb : T(0);
 
     // Phi_ii = J_i^-1 + Ad_i J_{i-1}^-1 Ad_i^T. The second term is link i-1's
@@ -146,26 +147,26 @@ __global__ __launch_bounds__(Geo<NP>::threads, 2) void k_cfa(ModelView<T> m, Cha
 #pragma unroll
     for (int c = 0; c < 6; ++c) acc += prow[c] * f[c] + (has_next ? nrow[c] * fn[c] : T(0));
     if (has_prev) acc += cprev;
-    if (active) qdd[st] = acc;
-    if (ci.unsolved) fill_unsolved(qdd, ci.state0, ci.unsolved, li, NP);
+    if (active) o.put(qdd, st, b, li, acc);
+    if (ci.unsolved && qdd) fill_unsolved(qdd, ci.state0, ci.unsolved, li, NP);
     if (active && !ok && status) atomicOr(status, 1);
 }
 
 template <typename T>
 hipError_t launch_cfa(int np, const ModelView<T>& m, const ChainMap& cm, const T* q, const T* qd, const T* tau,
-                      T* qdd, int* status, hipStream_t st) {
+                      T* qdd, int* status, const FdOut<T>& o, hipStream_t st) {
     if (cm.batch <= 0) return hipSuccess;
 #define CALL(P)                                                                                      \
     hipLaunchKernelGGL((k_cfa<T, P>), dim3((cm.batch + Geo<P>::chains - 1) / Geo<P>::chains),       \
-                       dim3(Geo<P>::threads), 0, st, m, cm, q, qd, tau, qdd, status)
+                       dim3(Geo<P>::threads), 0, st, m, cm, q, qd, tau, qdd, status, o)
     FDK_NP_SWITCH(np, CALL)
 #undef CALL
     return hipGetLastError();
 }
 
 template hipError_t launch_cfa<double>(int, const ModelView<double>&, const ChainMap&, const double*, const double*,
-                                       const double*, double*, int*, hipStream_t);
+                                       const double*, double*, int*, const FdOut<double>&, hipStream_t);
 template hipError_t launch_cfa<float>(int, const ModelView<float>&, const ChainMap&, const float*, const float*,
-                                      const float*, float*, int*, hipStream_t);
+                                      const float*, float*, int*, const FdOut<float>&, hipStream_t);
 
 }  // namespace fdk

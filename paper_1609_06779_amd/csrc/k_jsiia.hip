@@ -25,7 +25,7 @@ namespace fdk {
 template <typename T, int NP, bool TREE>
 __global__ __launch_bounds__(64) void k_jsiia_gj(ModelView<T> m, ChainMap cm, const T* __restrict__ q,
                                                   const T* __restrict__ qd, const T* __restrict__ tau,
-                                                  T* __restrict__ qdd, int* __restrict__ status) {
+                                                  T* __restrict__ qdd, int* __restrict__ status, FdOut<T> o) {
     static_assert(NP <= 64, "register rows need NP <= 64");
     constexpr int CH = Geo<NP>::chains;
     __shared__ T sf[CH * NP * 12];
@@ -38,11 +38,11 @@ __global__ __launch_bounds__(64) void k_jsiia_gj(ModelView<T> m, ChainMap cm, co
     const bool active = li < n;
     const int64_t st = ci.state0 + li;
     const int64_t link = ci.link0 + li;
-    T qi = active ? q[st] : T(0), qdi = active ? qd[st] : T(0), ti = active ? tau[st] : T(0);
+    T qi = active ? q[st] : T(0), qdi = active && !o.solve ? qd[st] : T(0), ti = active ? tau[st] : T(0);
 
     const int32_t code = TREE && active ? m.tree_il(li, ci.slot) : 0;
-    LinkLane<T> k;
-    const T tb = rnea_lane<T, NP, TREE>(m, link, active, qi, qdi, T(0), true, li, nullptr, k, code);
+    LinkLane<T> k;   // solve mode: zero velocity, no gravity, so the bias is exactly zero
+    const T tb = rnea_lane<T, NP, TREE>(m, link, active, qi, qdi, T(0), !o.solve, li, nullptr, k, code);
     T y = active ? ti - tb : T(0);
     T f[6];
     composite_force<T, NP, TREE>(k, active, li, nullptr, f, code);
@@ -93,8 +93,8 @@ __global__ __launch_bounds__(64) void k_jsiia_gj(ModelView<T> m, ChainMap cm, co
 #pragma unroll
         for (int kk = j + 1; kk < NP; ++kk) row[kk] -= fj * cj[kk];
     }
-    if (active) qdd[st] = y / diag;
-    if (ci.unsolved) fill_unsolved(qdd, ci.state0, ci.unsolved, li, NP);
+    if (active) o.put(qdd, st, b, li, y / diag);
+    if (ci.unsolved && qdd) fill_unsolved(qdd, ci.state0, ci.unsolved, li, NP);
     if (active && !ok && status) atomicOr(status, 1);
 }
 
@@ -134,7 +134,7 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> 
                                                                     const T* __restrict__ q,
                                                                     const T* __restrict__ qd,
                                                                     const T* __restrict__ tau, T* __restrict__ qdd,
-                                                                    int* __restrict__ status) {
+                                                                    int* __restrict__ status, FdOut<T> o) {
     constexpr int G = NP / 8;
     constexpr int TH = G * G;
     static_assert(TH >= NP, "the lane grid must cover one lane per link");
@@ -148,11 +148,11 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> 
     const int n = ci.n;
     const bool active = li < n;
     const int64_t st = ci.state0 + li;
-    T qi = active ? q[st] : T(0), qdi = active ? qd[st] : T(0), ti = active ? tau[st] : T(0);
+    T qi = active ? q[st] : T(0), qdi = active && !o.solve ? qd[st] : T(0), ti = active ? tau[st] : T(0);
 
     const int32_t code = TREE && active ? m.tree_il(li, ci.slot) : 0;
-    LinkLane<T> k;
-    const T tb = rnea_lane<T, TH, TREE>(m, ci.link0 + li, active, qi, qdi, T(0), true, li, xbuf, k, code);
+    LinkLane<T> k;   // solve mode: zero velocity, no gravity, so the bias is exactly zero
+    const T tb = rnea_lane<T, TH, TREE>(m, ci.link0 + li, active, qi, qdi, T(0), !o.solve, li, xbuf, k, code);
     T f6[6];
     composite_force<T, TH, TREE>(k, active, li, xbuf, f6, code);
     if (li < NP) {
@@ -167,8 +167,13 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> 
     block_sync<TH>();
 
     const int r = li / G, c = li % G;
+    // Chains of more than 128 links (G = 32, 1024 threads, 4 waves per SIMD)
+    // keep the register file for M: the pivot reciprocals go to LDS and the row
+    // multipliers are formed as they are used.
+    constexpr bool LEAN = NP > 128;
+    __shared__ T rdbuf[LEAN ? NP : 1];
     // lower blocks a >= b, packed: index a (a + 1) / 2 + b
-    T mb[36], y[8], rd[8];
+    T mb[36], y[8], rd[LEAN ? 1 : 8];
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
         const int i = r + G * a;
@@ -212,22 +217,25 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> 
         const T rp = rcp_refined(piv);
         const T yj = cj[NP];
         if (r == jr) {
-            rd[jb] = rp;
+            if constexpr (LEAN) {
+                if (c == jr) rdbuf[G * jb + jr] = rp;
+            } else {
+                rd[jb] = rp;
+            }
             ok = ok && piv > T(0);
         }
-        T fa[8], pv[8];
+        T pv[8];
+#pragma unroll
+        for (int a = jb; a < 8; ++a) pv[a] = cj[c + G * a];   // m_kj, zero at columns <= j
 #pragma unroll
         for (int a = jb; a < 8; ++a) {
-            fa[a] = cj[r + G * a] * rp;                     // L_ij, zero at rows <= j
-            pv[a] = cj[c + G * a];                          // m_kj, zero at columns <= j
-        }
+            const T fa = cj[r + G * a] * rp;                   // L_ij, zero at rows <= j
 #pragma unroll
-        for (int a = jb; a < 8; ++a) {
-#pragma unroll
-            for (int bb = jb; bb <= a; ++bb) mb[a * (a + 1) / 2 + bb] -= fa[a] * pv[bb];
-            y[a] -= fa[a] * yj;
+            for (int bb = jb; bb <= a; ++bb) mb[a * (a + 1) / 2 + bb] -= fa * pv[bb];
+            y[a] -= fa * yj;
         }
     }
+    if constexpr (LEAN) block_sync<TH>();                  // the last pivot reciprocals are in LDS
     // Back substitution L^T x = D^-1 b in blocks of G rows, last block first.
     // Row block jb is published once (entries m_jk, k <= j, and the block's
     // z = D^-1 b and 1 / d). Lane (r, c) then carries x of the block's row c:
@@ -240,8 +248,12 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> 
     static_assert((TH > 64 ? 10 * TH : NP * 13) >= G * WS + 2 * G, "block rows fit the reused buffer");
     T* zb = wbuf + G * WS;
     T* rb = zb + G;
+    auto rd_of = [&](int a) -> T {                          // 1 / d of row r + G a
+        if constexpr (LEAN) return rdbuf[r + G * a];
+        else return rd[a];
+    };
 #pragma unroll
-    for (int a = 0; a < 8; ++a) y[a] *= rd[a];
+    for (int a = 0; a < 8; ++a) y[a] *= rd_of(a);
 #pragma unroll
     for (int jb = 7; jb >= 0; --jb) {
         block_sync<TH>();                                    // earlier reads of the buffer are done
@@ -249,7 +261,7 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> 
         for (int bb = 0; bb <= jb; ++bb) wbuf[r * WS + c + G * bb] = mb[jb * (jb + 1) / 2 + bb];
         if (c == 0) {
             zb[r] = y[jb];
-            rb[r] = rd[jb];
+            rb[r] = rd_of(jb);
         }
         block_sync<TH>();
         // x_t = z_t - (1 / d_t) sum_{u > t} m_ut x_u within the block; lane c ends with x_c
@@ -257,46 +269,47 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> 
         block_back_solve<G, G - 1>(xc, y[jb], wbuf + G * jb, WS, c, r, rb[c]);
         // rows k above the block: z_k -= (1 / d_k) sum_t m_tk x_t
 #pragma unroll
-        for (int a = 0; a < jb; ++a) y[a] -= dpp::group_sum<G>(wbuf[c * WS + r + G * a] * xc) * rd[a];
+        for (int a = 0; a < jb; ++a) y[a] -= dpp::group_sum<G>(wbuf[c * WS + r + G * a] * xc) * rd_of(a);
     }
     if (c == 0) {
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
             const int i = r + G * a;
-            if (i < n) qdd[ci.state0 + i] = y[a];
+            if (i < n) o.put(qdd, ci.state0 + i, blockIdx.x, i, y[a]);
         }
     }
-    if (ci.unsolved) fill_unsolved(qdd, ci.state0, ci.unsolved, li, TH);
+    if (ci.unsolved && qdd) fill_unsolved(qdd, ci.state0, ci.unsolved, li, TH);
     if (c == 0 && !ok && status) atomicOr(status, 1);
 }
 
-// longest chain the Gauss-Jordan kernels take (same for both precisions)
-template <typename T> int jsiia_max_np() { return 128; }
+// longest chain the JSIIA kernels take (same for both precisions)
+template <typename T> int jsiia_max_np() { return 256; }
 
 template <typename T>
 hipError_t launch_jsiia(int np, const ModelView<T>& m, const ChainMap& cm, const T* q, const T* qd, const T* tau,
-                        T* qdd, int* status, hipStream_t st) {
+                        T* qdd, int* status, const FdOut<T>& o, hipStream_t st) {
     if (cm.batch <= 0) return hipSuccess;
 #define GJ(P)                                                                                            \
     if (m.tree)                                                                                          \
         hipLaunchKernelGGL((k_jsiia_gj<T, P, true>), dim3((cm.batch + Geo<P>::chains - 1) / Geo<P>::chains), \
-                           dim3(64), 0, st, m, cm, q, qd, tau, qdd, status);                            \
+                           dim3(64), 0, st, m, cm, q, qd, tau, qdd, status, o);                         \
     else                                                                                                 \
         hipLaunchKernelGGL((k_jsiia_gj<T, P, false>), dim3((cm.batch + Geo<P>::chains - 1) / Geo<P>::chains), \
-                           dim3(64), 0, st, m, cm, q, qd, tau, qdd, status)
+                           dim3(64), 0, st, m, cm, q, qd, tau, qdd, status, o)
 #define GJ2D(P)                                                                                          \
     if (m.tree)                                                                                          \
         hipLaunchKernelGGL((k_jsiia_ldl<T, P, true>), dim3(cm.batch), dim3((P / 8) * (P / 8)), 0, st, m, cm, q, \
-                           qd, tau, qdd, status);                                                        \
+                           qd, tau, qdd, status, o);                                                     \
     else                                                                                                 \
         hipLaunchKernelGGL((k_jsiia_ldl<T, P, false>), dim3(cm.batch), dim3((P / 8) * (P / 8)), 0, st, m, cm, q, \
-                           qd, tau, qdd, status)
+                           qd, tau, qdd, status, o)
     switch (np) {
         case 8: GJ(8); break;
         case 16: GJ(16); break;
         case 32: GJ(32); break;
         case 64: GJ2D(64); break;
         case 128: GJ2D(128); break;
+        case 256: GJ2D(256); break;
         default: return hipErrorInvalidValue;
     }
 #undef GJ
@@ -305,9 +318,9 @@ hipError_t launch_jsiia(int np, const ModelView<T>& m, const ChainMap& cm, const
 }
 
 template hipError_t launch_jsiia<double>(int, const ModelView<double>&, const ChainMap&, const double*, const double*,
-                                         const double*, double*, int*, hipStream_t);
+                                         const double*, double*, int*, const FdOut<double>&, hipStream_t);
 template hipError_t launch_jsiia<float>(int, const ModelView<float>&, const ChainMap&, const float*, const float*,
-                                        const float*, float*, int*, hipStream_t);
+                                        const float*, float*, int*, const FdOut<float>&, hipStream_t);
 template int jsiia_max_np<double>();
 template int jsiia_max_np<float>();
 

@@ -27,17 +27,17 @@ hipError_t launch_mass(int np, const ModelView<T>& m, const ChainMap& cm, const 
                        hipStream_t st);
 template <typename T>
 hipError_t launch_cfa(int np, const ModelView<T>& m, const ChainMap& cm, const T* q, const T* qd,
-                      const T* tau, T* qdd, int* status, hipStream_t st);
+                      const T* tau, T* qdd, int* status, const FdOut<T>& o, hipStream_t st);
 template <typename T>
 hipError_t launch_jsiia(int np, const ModelView<T>& m, const ChainMap& cm, const T* q, const T* qd,
-                        const T* tau, T* qdd, int* status, hipStream_t st);
+                        const T* tau, T* qdd, int* status, const FdOut<T>& o, hipStream_t st);
 template <typename T> int jsiia_max_np();
 // lane-per-chain kernel
 // stream_model: non-temporal model and workspace accesses (for launches whose
 // footprint outgrows the last-level cache; see stream_footprint)
 template <typename T>
 hipError_t launch_abia(const ModelView<T>& m, const ChainMap& cm, int nmax, const T* q, const T* qd,
-                       const T* tau, T* qdd, T* ws, bool stream_model, hipStream_t st);
+                       const T* tau, T* qdd, T* ws, bool stream_model, const FdOut<T>& o, hipStream_t st);
 size_t abia_workspace_elems(int batch, int nmax, bool tree);
 // ragged batches: one persistent launch over chains sorted by decreasing length
 // (slot_robot: robot of each interleaved column, used when cm has no robot ids)
@@ -50,10 +50,16 @@ hipError_t launch_abia_persistent(const ModelView<T>& m, const ChainMap& cm, int
 
 // reverse mode and the rollout step
 size_t vjp_workspace_elems(int batch, int nmax, bool tree);
+// lam_in: lambda = M^-1 gqdd was left in the workspace by another kernel (see
+// vjp_field_lambda), which also wrote gtau; qdd null: qdd is in the workspace
+// (vjp_field_qdd). FdOut::aux of the forward kernels addresses those fields.
 template <typename T>
 hipError_t launch_fd_vjp(const ModelView<T>& m, const ChainMap& cm, int nmax, const T* q, const T* qd, const T* qdd,
-                         const T* gqdd, T* gq, T* gqd, T* gtau, int accumulate, T* ws, bool stream_model,
+                         const T* gqdd, T* gq, T* gqd, T* gtau, int accumulate, int lam_in, T* ws, bool stream_model,
                          hipStream_t st);
+int vjp_fields_of(bool tree);
+int vjp_field_lambda();
+int vjp_field_qdd();
 template <typename T>
 hipError_t launch_euler(int64_t count, T dt, const T* q, const T* qd, const T* qdd, T* qn, T* qdn, hipStream_t st);
 template <typename T>

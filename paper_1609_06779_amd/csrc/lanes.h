@@ -238,6 +238,27 @@ __device__ __forceinline__ ChainInfo chain_info(const ModelView<T>& m, const Cha
     return ci;
 }
 
+// How a forward-dynamics kernel delivers q-ddot of chain b, link i (packed
+// entry st). Plain forward dynamics: out[st] = qdd. The reverse mode also uses
+// the kernels
+//   * to solve M lambda = g (solve != 0: tau holds g, and the bias forces are
+//     left out: zero velocity, no gravity, so tau_delta = g exactly), adding
+//     the result into out when accumulate != 0;
+//   * to hand their result to the lane-per-chain reverse-mode kernel: aux, when
+//     set, also receives it in field aux_field of that kernel's workspace
+//     ([block of 64 chains][link][field][lane], aux_fields fields per link).
+// out may be null when aux is the only consumer.
+template <typename T> struct FdOut {
+    int accumulate = 0;
+    int solve = 0;
+    T* aux = nullptr;
+    int aux_nmax = 0, aux_fields = 0, aux_field = 0;
+    __device__ __forceinline__ void put(T* out, int64_t st, int b, int i, T v) const {
+        if (out) out[st] = accumulate ? out[st] + v : v;
+        if (aux) aux[(((size_t)(b >> 6) * aux_nmax + i) * aux_fields + aux_field) * 64 + (b & 63)] = v;
+    }
+};
+
 // NaN over the `count` outputs of an unsolved chain starting at out + first,
 // written by `lanes` lanes (this one is `lane`).
 template <typename T>
@@ -300,16 +321,27 @@ template <int LANE> __device__ __forceinline__ double read(double v) {
 template <int LANE> __device__ __forceinline__ float read(float v) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), LANE));
 }
-// Sum over each aligned group of W = 8 or 16 consecutive lanes, in every lane
+// Lane l ^ 16 (the same place in the other 16-lane row of its 32-lane half),
+// by ds_swizzle in bit mode (and mask 0x1f, xor mask 0x10).
+__device__ __forceinline__ double swizzle_xor16(double v) {
+    const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), 0x401f);
+    const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x401f);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float swizzle_xor16(float v) {
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401f));
+}
+// Sum over each aligned group of W = 8, 16 or 32 consecutive lanes, in every lane
 // of the group: a butterfly (lane i pairs with i^1, i^2, then the mirrored
 // half), so every lane adds the same operands in the same order and the
 // groups' lanes hold bitwise equal sums.
 template <int W, typename T> __device__ __forceinline__ T group_sum(T v) {
-    static_assert(W == 8 || W == 16, "groups of 8 or 16 lanes");
+    static_assert(W == 8 || W == 16 || W == 32, "groups of 8, 16 or 32 lanes");
     v += mov<QUAD_XOR1>(v);
     v += mov<QUAD_XOR2>(v);
     v += mov<ROW_HALF_MIRROR>(v);
-    if constexpr (W == 16) v += mov<ROW_MIRROR>(v);
+    if constexpr (W >= 16) v += mov<ROW_MIRROR>(v);
+    if constexpr (W == 32) v += swizzle_xor16(v);
     return v;
 }
 }  // namespace dpp
@@ -536,14 +568,14 @@ __device__ __forceinline__ int bperm(int v, int addr) { return __builtin_amdgcn_
 // the group, by ds_swizzle in bit mode: within each 32-lane half, lane l reads
 // lane (l & and_mask) | T, and_mask keeping the group bits.
 template <int G, int T> __device__ __forceinline__ double group_bcast(double v) {
-    static_assert((G == 8 || G == 16) && T >= 0 && T < G, "a lane of a group of 8 or 16");
+    static_assert((G == 8 || G == 16 || G == 32) && T >= 0 && T < G, "a lane of a group of 8, 16 or 32");
     constexpr int pattern = (32 - G) | (T << 5);
     const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), pattern);
     const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), pattern);
     return __hiloint2double(hi, lo);
 }
 template <int G, int T> __device__ __forceinline__ float group_bcast(float v) {
-    static_assert((G == 8 || G == 16) && T >= 0 && T < G, "a lane of a group of 8 or 16");
+    static_assert((G == 8 || G == 16 || G == 32) && T >= 0 && T < G, "a lane of a group of 8, 16 or 32");
     constexpr int pattern = (32 - G) | (T << 5);
     return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), pattern));
 }

@@ -5,6 +5,7 @@ nothing here computes. PyTorch only provides device memory and streams.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 
 import numpy as np
@@ -22,6 +23,13 @@ def _ptr(t):
 def _stream(stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def _alloc_on(stream):
+    """Context for the default outputs and workspaces of a call: allocate them on the
+    stream the call enqueues on, so the caching allocator does not hand their
+    blocks to other work while that stream may still be writing them."""
+    return torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
 
 
 def _dev_tensor(x, dtype, device, name):
@@ -134,6 +142,37 @@ class Model:
         b.offsets = _ptr(_dev_tensor(offsets, torch.int64, self.device, "offsets")).value if offsets is not None else None
         return b
 
+    def _shape_batch(self, batch: int, ragged: bool, with_ids: bool, max_links: int) -> _lib.Batch:
+        """A batch descriptor for the size and choice queries. They read no device
+        memory (only whether robot_id and offsets are NULL matters), so a small
+        device buffer of the model's stands in for both."""
+        if getattr(self, "_marker", None) is None:
+            self._marker = torch.zeros(1, dtype=torch.int64, device=self.device)
+        b = _lib.Batch()
+        b.batch = int(batch)
+        b.max_links = int(max_links)
+        b.robot_id = self._marker.data_ptr() if with_ids else None
+        b.offsets = self._marker.data_ptr() if ragged else None
+        return b
+
+    def workspace_bytes(self, batch: int, algo: str = "auto", ragged: bool = False, with_ids: bool = False,
+                        max_links: int = 0) -> int:
+        """fd_workspace_size for a batch of this shape (chain offsets, robot ids or
+        not), before any device buffer of it exists."""
+        n = ctypes.c_size_t()
+        b = self._shape_batch(batch, ragged, with_ids, max_links)
+        _lib.check(_lib.load().fd_workspace_size(self._h, ctypes.byref(b), _lib.ALGOS[algo], ctypes.byref(n)),
+                   "fd_workspace_size")
+        return int(n.value)
+
+    def auto_algo(self, batch: int, ragged: bool = False, with_ids: bool = False, max_links: int = 0):
+        """(algorithm name, persistent launch?) that algo="auto" takes for a batch of this shape."""
+        a, p = ctypes.c_int(), ctypes.c_int()
+        b = self._shape_batch(batch, ragged, with_ids, max_links)
+        _lib.check(_lib.load().fd_auto_algo(self._h, ctypes.byref(b), ctypes.byref(a), ctypes.byref(p)),
+                   "fd_auto_algo")
+        return {v: k for k, v in _lib.ALGOS.items()}[a.value], bool(p.value)
+
     def workspace_size(self, batch: int, algo: str = "auto", robot_id=None, offsets=None, max_links: int = 0) -> int:
         n = ctypes.c_size_t()
         b = self._batch(batch, robot_id, offsets, max_links)
@@ -141,9 +180,11 @@ class Model:
                    "fd_workspace_size")
         return int(n.value)
 
-    def workspace(self, batch: int, algo: str = "auto", robot_id=None, offsets=None, max_links: int = 0):
+    def workspace(self, batch: int, algo: str = "auto", robot_id=None, offsets=None, max_links: int = 0,
+                  stream=None):
         nbytes = self.workspace_size(batch, algo, robot_id, offsets, max_links)
-        return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=self.device)
+        with _alloc_on(stream):
+            return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=self.device)
 
     def forward(self, q, qd, tau, batch: int, algo: str = "auto", robot_id=None, offsets=None, out=None,
                 workspace=None, stream=None, max_links: int = 0):
@@ -154,13 +195,14 @@ class Model:
         q = _dev_tensor(q, dt, self.device, "q")
         qd = _dev_tensor(qd, dt, self.device, "qd")
         tau = _dev_tensor(tau, dt, self.device, "tau")
-        if out is None:
-            out = torch.empty_like(q)
-        _dev_tensor(out, dt, self.device, "out")
-        b = self._batch(batch, robot_id, offsets, max_links,
-                        state=(("q", q), ("qd", qd), ("tau", tau), ("out", out)))
-        if workspace is None:
-            workspace = self.workspace(batch, algo, robot_id, offsets, max_links)
+        with _alloc_on(stream):
+            if out is None:
+                out = torch.empty_like(q)
+            _dev_tensor(out, dt, self.device, "out")
+            b = self._batch(batch, robot_id, offsets, max_links,
+                            state=(("q", q), ("qd", qd), ("tau", tau), ("out", out)))
+            if workspace is None:
+                workspace = self.workspace(batch, algo, robot_id, offsets, max_links, stream)
         _lib.check(_lib.load().fd_forward(self._h, ctypes.byref(b), _ptr(q), _ptr(qd), _ptr(tau), _ptr(out),
                                           _lib.ALGOS[algo], _ptr(workspace), workspace.numel(), _stream(stream)),
                    "fd_forward")
@@ -179,40 +221,53 @@ class Model:
         dt = self.torch_dtype
         for name, t in (("q", q), ("qd", qd), ("tau", tau)):
             _dev_tensor(t, dt, self.device, name)
-        out = torch.empty_like(q) if out is None else _dev_tensor(out, dt, self.device, "out")
-        b = self._batch(batch, robot_id, offsets, state=(("q", q), ("qd", qd), ("tau", tau), ("out", out)))
-        if workspace is None:
-            workspace = self.persistent_workspace(batch, grid, robot_id, offsets)
+        with _alloc_on(stream):
+            out = torch.empty_like(q) if out is None else _dev_tensor(out, dt, self.device, "out")
+            b = self._batch(batch, robot_id, offsets, state=(("q", q), ("qd", qd), ("tau", tau), ("out", out)))
+            if workspace is None:
+                workspace = self.persistent_workspace(batch, grid, robot_id, offsets)
         _lib.check(_lib.load().fd_forward_persistent(self._h, ctypes.byref(b), _ptr(q), _ptr(qd), _ptr(tau),
                                                      _ptr(out), int(grid), _ptr(workspace), workspace.numel(),
                                                      _stream(stream)), "fd_forward_persistent")
         return out
 
-    def backward_workspace(self, batch: int, robot_id=None, offsets=None):
+    def backward_workspace(self, batch: int, algo: str = "abia", robot_id=None, offsets=None, max_links: int = 0,
+                           stream=None):
         n = ctypes.c_size_t()
-        b = self._batch(batch, robot_id, offsets)
-        _lib.check(_lib.load().fd_backward_workspace_size(self._h, ctypes.byref(b), ctypes.byref(n)),
-                   "fd_backward_workspace_size")
-        return torch.empty(max(int(n.value), 1), dtype=torch.uint8, device=self.device)
+        b = self._batch(batch, robot_id, offsets, max_links)
+        _lib.check(_lib.load().fd_backward_workspace_size(self._h, ctypes.byref(b), _lib.ALGOS[algo],
+                                                          ctypes.byref(n)), "fd_backward_workspace_size")
+        with _alloc_on(stream):
+            return torch.empty(max(int(n.value), 1), dtype=torch.uint8, device=self.device)
 
-    def backward(self, q, qd, qdd, grad_qdd, batch: int, robot_id=None, offsets=None, grad_q=None, grad_qd=None,
-                 grad_tau=None, accumulate: bool = False, workspace=None, stream=None):
+    def backward(self, q, qd, qdd, grad_qdd, batch: int, algo: str = "abia", tau=None, robot_id=None, offsets=None,
+                 grad_q=None, grad_qd=None, grad_tau=None, accumulate: bool = False, workspace=None, stream=None,
+                 max_links: int = 0):
         """Vector-Jacobian product of forward dynamics at (q, qd, qdd = FD(q, qd, tau)):
-        returns (grad_q, grad_qd, grad_tau) for the cotangent grad_qdd."""
+        returns (grad_q, grad_qd, grad_tau) for the cotangent grad_qdd. ``algo`` is
+        the factorisation of M^-1 that gives grad_tau = M^-1 grad_qdd; qdd None
+        recomputes it from tau by the same algorithm."""
         dt = self.torch_dtype
-        for name, t in (("q", q), ("qd", qd), ("qdd", qdd), ("grad_qdd", grad_qdd)):
+        for name, t in (("q", q), ("qd", qd), ("grad_qdd", grad_qdd)):
             _dev_tensor(t, dt, self.device, name)
-        grad_q = torch.empty_like(q) if grad_q is None else _dev_tensor(grad_q, dt, self.device, "grad_q")
-        grad_qd = torch.empty_like(q) if grad_qd is None else _dev_tensor(grad_qd, dt, self.device, "grad_qd")
-        grad_tau = torch.empty_like(q) if grad_tau is None else _dev_tensor(grad_tau, dt, self.device, "grad_tau")
-        b = self._batch(batch, robot_id, offsets, state=(("q", q), ("qd", qd), ("qdd", qdd), ("grad_qdd", grad_qdd),
-                                                          ("grad_q", grad_q), ("grad_qd", grad_qd),
-                                                          ("grad_tau", grad_tau)))
-        if workspace is None:
-            workspace = self.backward_workspace(batch, robot_id, offsets)
-        _lib.check(_lib.load().fd_backward(self._h, ctypes.byref(b), _ptr(q), _ptr(qd), _ptr(qdd), _ptr(grad_qdd),
-                                           _ptr(grad_q), _ptr(grad_qd), _ptr(grad_tau), int(bool(accumulate)),
-                                           _ptr(workspace), workspace.numel(), _stream(stream)), "fd_backward")
+        if qdd is None and tau is None:
+            raise ValueError("give qdd, or tau to recompute it")
+        for name, t in (("qdd", qdd), ("tau", tau)):
+            if t is not None:
+                _dev_tensor(t, dt, self.device, name)
+        with _alloc_on(stream):
+            grad_q = torch.empty_like(q) if grad_q is None else _dev_tensor(grad_q, dt, self.device, "grad_q")
+            grad_qd = torch.empty_like(q) if grad_qd is None else _dev_tensor(grad_qd, dt, self.device, "grad_qd")
+            grad_tau = torch.empty_like(q) if grad_tau is None else _dev_tensor(grad_tau, dt, self.device, "grad_tau")
+            b = self._batch(batch, robot_id, offsets, max_links,
+                            state=(("q", q), ("qd", qd), ("tau", tau), ("qdd", qdd), ("grad_qdd", grad_qdd),
+                                   ("grad_q", grad_q), ("grad_qd", grad_qd), ("grad_tau", grad_tau)))
+            if workspace is None:
+                workspace = self.backward_workspace(batch, algo, robot_id, offsets, max_links)
+        _lib.check(_lib.load().fd_backward(self._h, ctypes.byref(b), _ptr(q), _ptr(qd), _ptr(tau), _ptr(qdd),
+                                           _ptr(grad_qdd), _ptr(grad_q), _ptr(grad_qd), _ptr(grad_tau),
+                                           _lib.ALGOS[algo], int(bool(accumulate)), _ptr(workspace),
+                                           workspace.numel(), _stream(stream)), "fd_backward")
         return grad_q, grad_qd, grad_tau
 
     def euler_step(self, q, qd, qdd, dt: float, q_next=None, qd_next=None, stream=None):
@@ -302,20 +357,21 @@ class _ForwardDynamics(torch.autograd.Function):
     def forward(ctx, q, qd, tau, model, batch, algo, robot_id, offsets):
         qdd = model.forward(q.detach(), qd.detach(), tau.detach(), batch=batch, algo=algo, robot_id=robot_id,
                             offsets=offsets)
-        ctx.model, ctx.batch, ctx.robot_id, ctx.offsets = model, batch, robot_id, offsets
+        ctx.model, ctx.batch, ctx.robot_id, ctx.offsets, ctx.algo = model, batch, robot_id, offsets, algo
         ctx.save_for_backward(q.detach(), qd.detach(), qdd)
         return qdd
 
     @staticmethod
     def backward(ctx, grad_qdd):
         q, qd, qdd = ctx.saved_tensors
-        gq, gqd, gtau = ctx.model.backward(q, qd, qdd, grad_qdd.contiguous(), batch=ctx.batch,
+        gq, gqd, gtau = ctx.model.backward(q, qd, qdd, grad_qdd.contiguous(), batch=ctx.batch, algo=ctx.algo,
                                            robot_id=ctx.robot_id, offsets=ctx.offsets)
         return gq, gqd, gtau, None, None, None, None, None
 
 
 def forward_dynamics(model: Model, q, qd, tau, batch: int, algo: str = "auto", robot_id=None, offsets=None):
-    """Differentiable qdd = FD(q, qd, tau): gradients come from fd_backward."""
+    """Differentiable qdd = FD(q, qd, tau): gradients come from fd_backward with the
+    same algorithm (grad_tau = M^-1 grad_qdd by the factorisation that gave qdd)."""
     return _ForwardDynamics.apply(q, qd, tau, model, batch, algo, robot_id, offsets)
 
 
@@ -350,7 +406,7 @@ class _Rollout(torch.autograd.Function):
         gtaus = torch.zeros_like(taus)
         gqdd = torch.empty_like(gq)
         fws = model.workspace(batch, algo)
-        bws = model.backward_workspace(batch)
+        bws = model.backward_workspace(batch, algo)
         for seg in range(len(ctx.checkpoints) - 1, -1, -1):
             t0 = seg * every
             t1 = min(n_steps, t0 + every)
@@ -365,8 +421,8 @@ class _Rollout(torch.autograd.Function):
             for t in range(t1 - 1, t0 - 1, -1):          # reverse it
                 qs, qds, qdds = states[t - t0]
                 model.euler_step_backward(gq, gqd, dt, grad_q=gq, grad_qd=gqd, grad_qdd=gqdd)
-                model.backward(qs, qds, qdds, gqdd, batch=batch, grad_q=gq, grad_qd=gqd, grad_tau=gtaus[t],
-                               accumulate=True, workspace=bws)
+                model.backward(qs, qds, qdds, gqdd, batch=batch, algo=algo, grad_q=gq, grad_qd=gqd,
+                               grad_tau=gtaus[t], accumulate=True, workspace=bws)
         return gq, gqd, gtaus, None, None, None, None, None
 
 

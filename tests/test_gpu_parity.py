@@ -1,19 +1,20 @@
 """GPU parity: the HIP path (through the C-ABI) against the CPU oracle.
 
 Forward dynamics is compared per chain by the normwise relative error
-||qdd - qdd_ref|| / ||qdd_ref||. The bar is 1e-10 in FP64 and 1e-4 in FP32
-where the problem's conditioning allows it. Past that, a chain's bar is
-COND_FACTOR * kappa * u (u = unit roundoff of the path's precision), with the
-error model of each factorisation:
-  * JSIIA and ABIA: kappa = cond_2(M). ABIA's recursions are backward stable,
-    so its normwise backward error ||M qdd - tau_delta|| / (||M|| ||qdd|| +
-    ||tau|| + ||tau_bias||) (tau and the bias torque are the data of the
-    solve) must also stay below 64 u. JSIIA inverts M by Gauss-Jordan
-    elimination, which is forward stable but not backward stable, so only its
-    forward error is bounded;
-  * the CFA's M^-1 = C - B^T A^-1 B (eq. (fijany-final)) is a difference of two
-    terms of size ||C||, so its error scales with kappa = ||C||_2 ||M||_2 (a
-    first-order scale, not a bound: hence the larger factor).
+||qdd - qdd_ref|| / ||qdd_ref||. Every bar is a fixed number per precision,
+stated before any run: the cap (1e-9 FP64, 1e-3 FP32, ten times the
+forward-dynamics target 1e-10 / 1e-4). Every chain of every test must be
+within the cap; each test also prints how many chains meet the target
+itself, and the benchmark records those fractions per algorithm, length and
+precision. Cells where chains exceed the cap are measured failures, marked
+as expected failures (strict: they fail the suite if they start passing).
+
+The normwise backward error ||M qdd - tau_delta|| / (||M|| ||qdd|| + ||tau|| +
+||tau_bias||) (tau and the bias torque are the data of the solve) is bounded
+by a fixed multiple of the unit roundoff u for every algorithm: ABIA and the
+symmetric elimination of JSIIA are backward stable; the CFA's
+M^-1 = C - B^T A^-1 B (eq. (fijany-final)) is a difference of terms of size
+||C|| and its bound is correspondingly larger.
 FP32 runs round robots and states to FP32 first and the FP64 oracle runs on
 the same rounded values.
 """
@@ -21,6 +22,7 @@ import numpy as np
 import pytest
 
 import oracle
+from _errmodel import CAP, TARGET, U
 from oracle import dense
 from paper_1609_06779_amd import synth
 
@@ -28,10 +30,8 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 ALGOS = ("abia", "jsiia", "cfa")
-U = {"f64": 2.0 ** -53, "f32": 2.0 ** -24}
-TOL = {"f64": 1e-10, "f32": 1e-4}
-COND_FACTOR = {"abia": 16.0, "jsiia": 16.0, "cfa": 64.0}   # measured maxima 12.6, 12.6, 18
-BACKWARD_FACTOR = 64.0                                      # measured maximum 16
+# normwise backward error bound in units of u, per algorithm
+BACKWARD_U = {"abia": 64.0, "jsiia": 64.0, "cfa": float(2 ** 20)}
 
 
 @pytest.fixture(scope="module")
@@ -60,17 +60,6 @@ def _t(a, dtype, dev):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64 if dtype == "f64" else np.float32)).to(dev)
 
 
-def _kappa(algo, rb, q, off):
-    ms = oracle.crba(rb, q, offsets=off)
-    if algo != "cfa":
-        return np.array([np.linalg.cond(m) for m in ms])
-    out = []
-    for b, m in enumerate(ms):
-        ch = dense.Chain(rb, off[b], int(off[b + 1] - off[b]))
-        out.append(np.linalg.norm(dense.cfa_c_matrix(ch, q[off[b]:off[b + 1]]), 2) * np.linalg.norm(m, 2))
-    return np.array(out)
-
-
 def _backward_error(rb, q, qd, tau, qdd, off):
     ms = oracle.crba(rb, q, offsets=off)
     bias = oracle.rnea(rb, q, qd, offsets=off)
@@ -83,17 +72,17 @@ def _backward_error(rb, q, qd, tau, qdd, off):
     return np.array(eta)
 
 
-def _check(got, ref, off, dtype, rb, q, what, algo, qd=None, tau=None):
+def _check(got, ref, off, dtype, what, algo, rb=None, q=None, qd=None, tau=None):
+    """Every chain within CAP[dtype]; with (rb, q, qd, tau) also the backward error bound."""
     err = oracle.relative_error(got, ref, off)
-    bar = np.full(len(err), TOL[dtype])
     worst = float(err.max()) if len(err) else 0.0
-    if worst > TOL[dtype]:
-        bar = np.maximum(bar, COND_FACTOR[algo] * _kappa(algo, rb, q, off) * U[dtype])
-    bad = np.nonzero(~(err <= bar))[0]
-    assert len(bad) == 0, f"{what}: {len(bad)} chains over the bar, worst {worst:.3e} (chain {bad[:5]})"
-    if algo == "abia" and qd is not None:
+    within = int(np.sum(err <= TARGET[dtype]))
+    print(f"{what}: worst {worst:.2e}, {within} of {len(err)} chains within {TARGET[dtype]:g}", flush=True)
+    bad = np.nonzero(~(err <= CAP[dtype]))[0]
+    assert len(bad) == 0, f"{what}: {len(bad)} chains over the cap {CAP[dtype]:g}, worst {worst:.3e} (chain {bad[:5]})"
+    if qd is not None:
         eta = _backward_error(rb, q, qd, tau, got, off)
-        assert eta.max() <= BACKWARD_FACTOR * U[dtype], f"{what}: backward error {eta.max():.3e}"
+        assert eta.max() <= BACKWARD_U[algo] * U[dtype], f"{what}: backward error {eta.max() / U[dtype]:.1f} u"
     return err
 
 
@@ -116,16 +105,10 @@ def test_forward_uniform(fdm, dev, algo, dtype, n):
     batch = 37 if n <= 64 else 11            # not a multiple of the chains per workgroup
     lengths = np.full(batch, n, np.int32)
     rb, q, qd, tau = _prep(lengths, dtype, random_home=(n % 2 == 1))
-    if algo == "jsiia" and n > 128:          # JSIIA keeps M in LDS: the library refuses, before any launch
-        from paper_1609_06779_amd import _lib
-        with pytest.raises(_lib.FdError) as ei:
-            _forward(fdm, dev, rb, q, qd, tau, dtype, algo)
-        assert ei.value.status == _lib.FD_ERR_UNSUPPORTED
-        return
     off = rb.offsets
     ref = oracle.fd(rb, q, qd, tau)
     got = _forward(fdm, dev, rb, q, qd, tau, dtype, algo)
-    _check(got, ref, off, dtype, rb, q, f"{algo} {dtype} n={n}", algo, qd, tau)
+    _check(got, ref, off, dtype, f"{algo} {dtype} n={n}", algo, rb, q, qd, tau)
 
 
 def test_config_plain_n8_b1024_all_chains(fdm, dev):
@@ -137,19 +120,19 @@ def test_config_plain_n8_b1024_all_chains(fdm, dev):
     for algo in ALGOS:
         got = _forward(fdm, dev, rb, q, qd, tau, "f64", algo, model=model)
         err = oracle.relative_error(got, ref, off)
-        assert err.max() <= 1e-10, (algo, err.max())
+        assert err.max() <= TARGET["f64"], (algo, err.max())     # the target itself, on every chain
 
 
 @pytest.mark.parametrize("algo", ALGOS)
 def test_ragged_batch_with_offsets(fdm, dev, algo):
-    hi = 128 if algo == "jsiia" else 256
+    hi = 256
     lengths = synth.ragged_lengths(61, 1, hi, cfg=3)
     lengths[:3] = [1, hi, 2]
     rb, q, qd, tau = _prep(lengths, "f64", cfg=3)
     off = rb.offsets
     ref = oracle.fd(rb, q, qd, tau)
     got = _forward(fdm, dev, rb, q, qd, tau, "f64", algo, offsets=off)
-    _check(got, ref, off, "f64", rb, q, f"{algo} ragged", algo, qd, tau)
+    _check(got, ref, off, "f64", f"{algo} ragged", algo, rb, q, qd, tau)
 
 
 @pytest.mark.parametrize("algo", ALGOS)
@@ -165,7 +148,7 @@ def test_shared_robots_by_id(fdm, dev, algo):
     ref = oracle.fd(per_chain, q, qd, tau)
     model = fdm.Model(base, "f64", device=dev)
     got = _forward(fdm, dev, base, q, qd, tau, "f64", algo, offsets=off, robot_id=rid, model=model)
-    _check(got, ref, off, "f64", per_chain, q, f"{algo} shared robots", algo, qd, tau)
+    _check(got, ref, off, "f64", f"{algo} shared robots", algo, per_chain, q, qd, tau)
 
 
 @pytest.mark.parametrize("algo", ALGOS)
@@ -181,7 +164,7 @@ def test_full_size_n64_b65536_sampled(fdm, dev, algo):
     sub = rb.take(pick)
     idx = np.concatenate([np.arange(64 * b, 64 * b + 64) for b in pick])
     ref = oracle.fd(sub, q[idx], qd[idx], tau[idx])
-    _check(got[idx], ref, sub.offsets, "f64", sub, q[idx], f"{algo} full size", algo, qd[idx], tau[idx])
+    _check(got[idx], ref, sub.offsets, "f64", f"{algo} full size", algo, sub, q[idx], qd[idx], tau[idx])
     assert np.all(np.isfinite(got))
 
 
@@ -201,7 +184,8 @@ def test_deterministic_and_independent_of_batch_neighbours(fdm, dev):
 
 def test_round_trip_on_gpu(fdm, dev):
     """ID(q, qd, FD(q, qd, tau)) = tau, both on the GPU, in the normwise sense
-    ||ID - tau|| / (||M|| ||qdd|| + ||tau_delta||) of each factorisation's error model."""
+    ||ID - tau|| / (||M|| ||qdd|| + ||tau|| + ||tau_bias||): the backward error of
+    each factorisation, within its bound."""
     lengths = np.full(64, 32, np.int32)
     rb, q, qd, tau = _prep(lengths, "f64")
     off = rb.offsets
@@ -213,12 +197,11 @@ def test_round_trip_on_gpu(fdm, dev):
         qdd = model.forward(tq, tqd, ttau, batch=64, algo=algo)
         back = model.inverse(tq, tqd, qdd, batch=64).cpu().numpy()
         qn = qdd.cpu().numpy()
-        bar = (np.full(64, BACKWARD_FACTOR) if algo == "abia" else COND_FACTOR[algo] * _kappa(algo, rb, q, off)) * U["f64"]
         for b, m in enumerate(ms):
             sl = slice(off[b], off[b + 1])
             eta = np.linalg.norm(back[sl] - tau[sl]) / (np.linalg.norm(m, 2) * np.linalg.norm(qn[sl]) +
                                                        np.linalg.norm(tau[sl]) + np.linalg.norm(bias[sl]))
-            assert eta <= bar[b], (algo, b, eta)
+            assert eta <= BACKWARD_U[algo] * U["f64"], (algo, b, eta / U["f64"])
 
 
 def test_empty_batch_and_workspace_errors(fdm, dev):
@@ -238,11 +221,11 @@ def test_empty_batch_and_workspace_errors(fdm, dev):
     assert ei.value.status == _lib.FD_ERR_INVALID_ARG
     with pytest.raises(ValueError, match="q has 24 entries"):   # the binding's size check, before any launch
         model.forward(tq, tq, tq, batch=5, algo="cfa")
-    big = synth.make_robots([200], cfg=5)
-    mb = fdm.Model(big, "f64", device=dev)
-    t200 = torch.zeros(200, dtype=torch.float64, device=dev)
-    with pytest.raises(_lib.FdError) as ei:
-        mb.forward(t200, t200, t200, batch=1, algo="jsiia")
+    tree = synth.make_tree_robots([12], cfg=5)
+    mt = fdm.Model(tree, "f64", device=dev)
+    t12 = torch.zeros(12, dtype=torch.float64, device=dev)
+    with pytest.raises(_lib.FdError) as ei:                    # the CFA takes serial chains only
+        mt.forward(t12, t12, t12, batch=1, algo="cfa")
     assert ei.value.status == _lib.FD_ERR_UNSUPPORTED
 
 
@@ -314,13 +297,18 @@ def test_btd_solve6(fdm, dev, dtype):
                                max_len=int(lengths.max()))
     x = x.cpu().numpy().astype(np.float64)
     assert int(status.item()) == 0
-    for s in range(len(lengths)):
-        sl = slice(off[s], off[s + 1])
-        ref = dense.btd_solve_dense(d[sl], u[sl], r[sl])
-        cond = np.linalg.cond(dense.btd_assemble(d[sl], u[sl]))
-        bar = max(1e-11 if dtype == "f64" else 1e-4, 16.0 * cond * U[dtype])
-        rel = np.linalg.norm(x[sl] - ref) / np.linalg.norm(ref)
-        assert rel <= bar, (s, lengths[s], rel)
+    for s_ in range(len(lengths)):
+        sl = slice(off[s_], off[s_ + 1])
+        a = dense.btd_assemble(d[sl], u[sl])
+        # normwise backward error of the solve, a fixed multiple of u: odd-even
+        # elimination factors SPD blocks without pivoting, like a block Cholesky
+        eta = np.linalg.norm(a @ x[sl].reshape(-1) - r[sl].reshape(-1)) / (
+            np.linalg.norm(a, 2) * np.linalg.norm(x[sl]) + np.linalg.norm(r[sl]))
+        assert eta <= 256 * U[dtype], (s_, lengths[s_], eta / U[dtype])
+        if dtype == "f64" and np.linalg.cond(a) <= 1e6:   # where cond(A) u allows it: LAPACK's x within the cap
+            ref = dense.btd_solve_dense(d[sl], u[sl], r[sl])
+            rel = np.linalg.norm(x[sl] - ref) / np.linalg.norm(ref)
+            assert rel <= CAP[dtype], (s_, lengths[s_], rel)
 
 
 def test_btd_solve6_reports_non_spd(fdm, dev):
@@ -354,7 +342,7 @@ def test_length_bound_sizes_the_launch(fdm, dev, algo):
     rid, toff = torch.from_numpy(ids).to(dev), torch.from_numpy(off).to(dev)
     ref = oracle.fd(sub, q, qd, tau)
     got = model.forward(tq, tqd, ttau, batch=len(ids), algo=algo, robot_id=rid, offsets=toff, max_links=30)
-    _check(got.cpu().numpy(), ref, off, "f64", sub, q, f"{algo} bounded", algo)
+    _check(got.cpu().numpy(), ref, off, "f64", f"{algo} bounded", algo)
     if algo == "abia":
         free = model.forward(tq, tqd, ttau, batch=len(ids), algo=algo, robot_id=rid, offsets=toff)
         assert torch.equal(got, free)
@@ -369,76 +357,20 @@ def test_length_bound_sizes_the_launch(fdm, dev, algo):
     ok = sub.n_links <= 12
     keep = np.concatenate([np.arange(off[b], off[b + 1]) for b in np.nonzero(ok)[0]])
     sub_ok = sub.take(np.nonzero(ok)[0])
-    _check(short[keep], ref[keep], sub_ok.offsets, "f64", sub_ok, q[keep], f"{algo} short bound", algo)
+    _check(short[keep], ref[keep], sub_ok.offsets, "f64", f"{algo} short bound", algo)
     for bad in (-1, 257):
         with pytest.raises(_lib.FdError) as ei:
             model.forward(tq, tqd, ttau, batch=len(ids), algo=algo, robot_id=rid, offsets=toff, max_links=bad)
         assert ei.value.status == _lib.FD_ERR_INVALID_ARG
 
 
-def _skew_rows(v):
-    """Cross-product matrices of the rows of v: (k, 3) -> (k, 3, 3)."""
-    z = np.zeros(len(v))
-    return np.stack([np.stack([z, -v[:, 2], v[:, 1]], -1), np.stack([v[:, 2], z, -v[:, 0]], -1),
-                     np.stack([-v[:, 1], v[:, 0], z], -1)], 1)
-
-
-def _kappa_many(algo, rb, q, n, chains, chunk=1024):
-    """The error-model factor of `_kappa` for many chains of a uniform batch of n
-    links, chunk by chunk: cond_2(M), or for the CFA ||C||_2 ||M||_2 with C the
-    tri-diagonal S^T Phi S of `dense.cfa_c_matrix`, built for a whole chunk at once."""
-    out = []
-    for k0 in range(0, len(chains), chunk):
-        ch = chains[k0:k0 + chunk]
-        idx = (ch[:, None] * n + np.arange(n)).reshape(-1)
-        sub = rb.take(ch)
-        ms = np.stack(oracle.crba(sub, q[idx]))
-        ev = np.linalg.eigvalsh(ms)
-        if algo != "cfa":
-            out.append(ev[:, -1] / ev[:, 0])
-            continue
-        b = len(ch)
-        jinv, ad, s = [], [], []
-        for i in range(n):
-            li = ch * n + i
-            m = rb.mass[li][:, None, None]
-            it = rb.inertia[li]
-            ic = np.stack([np.stack([it[:, 0], it[:, 3], it[:, 4]], -1), np.stack([it[:, 3], it[:, 1], it[:, 5]], -1),
-                           np.stack([it[:, 4], it[:, 5], it[:, 2]], -1)], 1)
-            c = _skew_rows(rb.com[li])
-            j = np.zeros((b, 6, 6))
-            j[:, :3, :3] = ic - m * (c @ c)
-            j[:, :3, 3:] = m * c
-            j[:, 3:, :3] = -m * c
-            j[:, 3:, 3:] = m * np.eye(3)
-            jinv.append(np.linalg.inv(j))
-            kx = _skew_rows(rb.axis[li])
-            qq = q[li][:, None, None]
-            r = rb.home_rot[li].reshape(b, 3, 3) @ (np.eye(3) + np.sin(qq) * kx + (1.0 - np.cos(qq)) * (kx @ kx))
-            rt = r.transpose(0, 2, 1)
-            pt = -(rt @ rb.offset[li][:, :, None])[:, :, 0]
-            x = np.zeros((b, 6, 6))                  # Ad(T^-1) = ad_pose(R^T, -R^T p)
-            x[:, :3, :3] = rt
-            x[:, 3:, 3:] = rt
-            x[:, 3:, :3] = _skew_rows(pt) @ rt
-            ad.append(x)
-            s.append(np.concatenate([rb.axis[li], np.zeros((b, 3))], 1))
-        cm = np.zeros((b, n, n))
-        for i in range(n):
-            phi = jinv[i] + (ad[i] @ jinv[i - 1] @ ad[i].transpose(0, 2, 1) if i > 0 else 0.0)
-            cm[:, i, i] = np.einsum("bi,bij,bj->b", s[i], phi, s[i])
-            if i + 1 < n:
-                cm[:, i, i + 1] = cm[:, i + 1, i] = np.einsum("bi,bij,bj->b", s[i],
-                                                               -jinv[i] @ ad[i + 1].transpose(0, 2, 1), s[i + 1])
-        out.append(np.abs(np.linalg.eigvalsh(cm)).max(axis=1) * ev[:, -1])
-    return np.concatenate(out) if out else np.zeros(0)
-
-
 @pytest.mark.parametrize("n", [16, 32, 64, 128])
 def test_every_chain_at_65536(fdm, dev, n):
     """65536 chains of n links (16 .. 128), FP64: every chain of every algorithm
-    against the oracle (all host threads). The forward error bar is 1e-10, or
-    the factorisation's error model for the chains above it."""
+    against the oracle (all host threads), within the cap; the chains above the
+    target are counted and their error-model factor printed (diagnostics)."""
+    from _errmodel import kappa
+
     batch = 65536
     lengths = synth.uniform_lengths(batch, n)
     rb, q, qd, tau = _prep(lengths, "f64", cfg=2)
@@ -446,17 +378,14 @@ def test_every_chain_at_65536(fdm, dev, n):
     off = rb.offsets
     model = fdm.Model(rb, "f64", device=dev)
     for algo in ALGOS:
-        if n > model.max_links(algo):
-            continue
         got = _forward(fdm, dev, rb, q, qd, tau, "f64", algo, model=model)
         assert np.all(np.isfinite(got)), algo
-        err = oracle.relative_error(got, ref, off)
-        over = np.nonzero(err > TOL["f64"])[0]
-        print(f"{algo} n={n}: {len(over)} of {batch} chains above 1e-10, worst {err.max():.2e}", flush=True)
-        if len(over):                              # the error model, for those chains only
-            bar = np.maximum(TOL["f64"], COND_FACTOR[algo] * _kappa_many(algo, rb, q, n, over) * U["f64"])
-            bad = over[~(err[over] <= bar)]
-            assert len(bad) == 0, f"{algo} n={n}: {len(bad)} chains over the bar (chain {bad[:5]})"
+        err = _check(got, ref, off, "f64", f"{algo} n={n} b={batch}", algo)
+        over = np.nonzero(err > TARGET["f64"])[0]
+        if len(over):
+            k = kappa(algo, rb, q, n, over[:64])
+            print(f"  {algo} n={n}: error / (kappa u) of the chains above the target: max "
+                  f"{(err[over[:64]] / (k * U['f64'])).max():.2f}", flush=True)
 
 
 @pytest.mark.parametrize("algo", ALGOS)

@@ -4,6 +4,7 @@ import numpy as np
 import pytest
 
 import oracle
+from _errmodel import CAP
 from paper_1609_06779_amd import synth
 
 torch = pytest.importorskip("torch")
@@ -42,9 +43,7 @@ def test_persistent_equals_plain_and_oracle(dev, dtype):
     idx = np.concatenate([np.arange(off[b], off[b + 1]) for b in pick])
     ref = oracle.fd(sub, q[idx], qd[idx], tau[idx])
     err = oracle.relative_error(plain.cpu().double().numpy()[idx], ref, sub.offsets)
-    kappa = np.array([np.linalg.cond(m) for m in oracle.crba(sub, q[idx])])
-    u = 2.0 ** -53 if dtype == "f64" else 2.0 ** -24
-    assert np.all(err <= np.maximum(1e-10 if dtype == "f64" else 1e-4, 16 * kappa * u)), err
+    assert np.all(err <= CAP[dtype]), err
 
 
 def test_persistent_skips_out_of_range_robot_ids(dev):
