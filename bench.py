@@ -35,7 +35,7 @@ def fma_per_solve(algo: str, n: int) -> float:
     (canonical joint frames, S = e3; scans counted at their serial work, the
     odd-even elimination at its n log n work; transcendental calls excluded)."""
     rnea = 162.0 * n                                    # poses, velocity/acceleration/force sweeps
-    if algo == "abia":
+    if algo in ("abia", "abia_scan"):                  # the scan form does the same method's work
         return rnea + 360.0 * n + 30.0 * n              # articulated inertias + p sweep, a/qdd sweep
     if algo == "jsiia":
         return rnea + 94.0 * n + 3.0 * n * n + n ** 3 / 6.0 + n * n   # composite inertia, M, Cholesky, solves
@@ -78,7 +78,8 @@ def measured_traffic(kernel: str, workload: str):
     return None if k is None else k["bytes_per_launch"]
 
 
-KERNEL_PATTERNS = (("abia", r"k_abia<"), ("jsiia", r"k_jsiia"), ("cfa", r"k_cfa<"))
+KERNEL_PATTERNS = (("abia", r"k_abia<"), ("jsiia", r"k_jsiia"), ("cfa", r"k_cfa<"),
+                   ("abia_persistent", r"k_abia_persistent<"), ("abia_scan", r"k_abia_scan<"))
 COPY_CALIB_BYTES = 256 << 20
 
 
@@ -151,13 +152,13 @@ def summarize_pmc(fetch_dir: str, write_dir: str, workload: str, commands, summa
 def summarize_flops(p1_dir: str, p2_dir: str, workload: str, commands, summary_cmd: str, bench_log: str,
                     n: int, batch: int, dtype: str, p3_dir=None) -> str:
     """Write profiles/<workload>_valu_flops.md from two rocprofv3 --pmc passes:
-    SQ_INSTS_VALU_FLOPS_FP64 (FP64 flops per wave instruction: 2 per FMA, 1 per
-    add or multiply), then SQ_INSTS_MFMA, SQ_INSTS_VALU and the FP64 FMA / MUL /
-    ADD counts. Executed flops per launch = the flops counter x 64 lanes (masked
-    lanes included); the time per launch is bench.py's HIP-event average from
-    `bench_log` (an unprofiled or trace-only run of the same step). An optional
-    third pass (SQ_INSTS_LDS, SQ_LDS_BANK_CONFLICT, SQ_WAVES) adds the LDS
-    instructions per wave and the bank-conflict cycles per LDS instruction."""
+    SQ_INSTS_VALU_FLOPS_FP64 (FP32: _FP32; flops per wave instruction: 2 per FMA,
+    1 per add or multiply), then SQ_INSTS_MFMA, SQ_INSTS_VALU and the FMA / MUL /
+    ADD counts of that precision. Executed flops per launch = the flops counter x
+    64 lanes (masked lanes included); the time per launch is bench.py's HIP-event
+    average from `bench_log` (an unprofiled or trace-only run of the same step).
+    An optional third pass (SQ_INSTS_LDS, SQ_LDS_BANK_CONFLICT, SQ_WAVES) adds the
+    LDS instructions per wave and the bank-conflict cycles per LDS instruction."""
     import csv
     import glob
     import re
@@ -176,14 +177,16 @@ def summarize_flops(p1_dir: str, p2_dir: str, workload: str, commands, summary_c
         if line.startswith("{"):
             events = {a: v["ms_per_launch"] for a, v in json.loads(line).get("per_algo", {}).items()}
     peak = PEAK_FLOPS[dtype] / 1e12
+    P = "FP64" if dtype == "f64" else "FP32"
+    sfx = "F64" if dtype == "f64" else "F32"
     lds_rows = []
-    lines = [f"# FP64 VALU work per launch: {workload}", "", "Commands:", "", "```", *commands, summary_cmd, "```", "",
-             "Executed flops = `SQ_INSTS_VALU_FLOPS_FP64` x 64 lanes (it counts 2 per FMA and 1 per add or "
+    lines = [f"# {P} VALU work per launch: {workload}", "", "Commands:", "", "```", *commands, summary_cmd, "```", "",
+             f"Executed flops = `SQ_INSTS_VALU_FLOPS_{P}` x 64 lanes (it counts 2 per FMA and 1 per add or "
              "multiply, per wave instruction, so masked lanes are included). The algorithmic count is "
              "bench.py's `fma_per_solve` x 2 x batch. Times: the HIP-event average per launch of the "
              "bench log named above (an unprofiled bench.py run of the same workload).", "",
              "| algorithm | kernel | executed GFLOP / launch | algorithmic GFLOP / launch | ms / launch | "
-             "executed TFLOP/s | frac of peak | MFMA instructions | FP64 share of VALU instructions |",
+             f"executed TFLOP/s | frac of peak | MFMA instructions | {P} share of VALU instructions |",
              "|---|---|---|---|---|---|---|---|---|"]
     for algo, pat in KERNEL_PATTERNS:
         k1 = next((k for k in c1 if re.search(pat, k)), None)
@@ -191,10 +194,11 @@ def summarize_flops(p1_dir: str, p2_dir: str, workload: str, commands, summary_c
         if not k1 or not k2 or algo not in events:
             continue
         mean = lambda d, c: sum(d[c]) / len(d[c])
-        ex = mean(c1[k1], "SQ_INSTS_VALU_FLOPS_FP64") * 64
+        ex = mean(c1[k1], f"SQ_INSTS_VALU_FLOPS_{P}") * 64
         alg = 2.0 * fma_per_solve(algo, n) * batch
         ms = events[algo]
-        f64 = sum(mean(c2[k2], c) for c in ("SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_ADD_F64"))
+        f64 = sum(mean(c2[k2], c) for c in (f"SQ_INSTS_VALU_FMA_{sfx}", f"SQ_INSTS_VALU_MUL_{sfx}",
+                                             f"SQ_INSTS_VALU_ADD_{sfx}"))
         rate = ex / (ms * 1e-3) / 1e12
         lines.append(f"| {algo} | `{k1.split('(')[0].replace('void ', '')}` | {ex / 1e9:.2f} | {alg / 1e9:.2f} | "
                      f"{ms:.3f} | {rate:.1f} | {rate / peak:.2f} | {mean(c2[k2], 'SQ_INSTS_MFMA'):.0f} | "
@@ -335,7 +339,7 @@ def cpu_baseline_accuracy(ns=(16, 32, 64, 128), batch: int = 65536, sample: int 
             model = fd.Model(rb, dtype, device=dev)
             tq, tqd, tt = (torch.from_numpy(a).to(dev, tdt) for a in (q, qd, tau))
             cell = {}
-            for algo in ("abia", "jsiia", "cfa"):
+            for algo in ("abia", "jsiia", "cfa", "abia_scan"):
                 if n > model.max_links(algo):
                     continue
                 got = model.forward(tq, tqd, tt, batch=batch, algo=algo)[: sample * n].cpu().numpy().astype(np.float64)
@@ -358,7 +362,8 @@ def cpu_baseline_accuracy(ns=(16, 32, 64, 128), batch: int = 65536, sample: int 
 def serving_leg(dtype: str, requests: int = 30000):
     """Continuous batching over 32 resident robots (n ~ U{7..200}), requests of
     1..4096 chains (log-uniform), Poisson arrivals at 50%, 70% and 80% of the
-    saturation rate (all requests present at once); latency is arrival to
+    saturation rate (all requests present at once) and at the fixed rates of
+    5000 and 10000 requests/s; latency is arrival to
     result in host memory. Each round's batch takes the library's AUTO choice.
     Saturation reports where the time goes (copies in, kernels, copies out:
     GPU time summed over launches, which overlap on the streams; and the host
@@ -445,6 +450,12 @@ def serving_leg(dtype: str, requests: int = 30000):
         out[f"load_{int(load * 100)}pct"] = {"qps": qps, "p50_ms": st.p50 * 1e3, "p99_ms": st.p99 * 1e3,
                                              "solves_per_s": st.solves_per_s, "launches": st.launches,
                                              "max_inflight": st.max_inflight}
+    # fixed request rates, comparable from one build to the next whatever the saturation rate
+    for qps in (5000.0, 10000.0):
+        st, _, _ = run(qps, requests, 20 + int(qps // 1000))
+        out[f"qps_{int(qps)}"] = {"qps": qps, "p50_ms": st.p50 * 1e3, "p99_ms": st.p99 * 1e3,
+                                  "solves_per_s": st.solves_per_s, "launches": st.launches,
+                                  "max_inflight": st.max_inflight}
     model.close()
     return out
 
@@ -829,13 +840,16 @@ def experiments_leg(dtype: str, calls: int = 200):
     from paper_1609_06779_amd import tune
 
     rows = tune.experiments(dtype, calls=calls)
-    exp1, exp2 = {}, {}
+    exp1, exp1d, exp2, exp2d = {}, {}, {}, {}
     for r in rows:
         if r["exp"] == 1:
             exp1.setdefault(r["algo"], {})[str(r["n"])] = None if r["ms"] is None else r["ms"] * 1e3
+            exp1d.setdefault(r["algo"], {})[str(r["n"])] = None if r["device_ms"] is None else r["device_ms"] * 1e3
         else:
             exp2.setdefault(f"n{r['n']}", {}).setdefault(r["algo"], {})[str(r["groups"])] = r["ms"]
-    return {"calls": calls, "exp1_us_per_call": exp1, "exp2_ms_per_call": exp2}
+            exp2d.setdefault(f"n{r['n']}", {}).setdefault(r["algo"], {})[str(r["groups"])] = r["device_ms"]
+    return {"calls": calls, "exp1_us_per_call": exp1, "exp1_device_us": exp1d, "exp2_ms_per_call": exp2,
+            "exp2_device_ms": exp2d}
 
 
 TREE_WORKLOADS = ("tree-shared-n64-b65536", "tree-n64-b65536")
@@ -921,6 +935,8 @@ def main():
     ap.add_argument("--only-step", action="store_true",
                     help="time the step alone: no legs and no CPU baseline (the profiled command)")
     ap.add_argument("--only-trees", action="store_true", help="run the branched-robot leg alone")
+    ap.add_argument("--only-ragged", action="store_true",
+                    help="run the ragged-batch leg alone (per_algo: the persistent launch's event time)")
     ap.add_argument("--tree-workloads", default=",".join(TREE_WORKLOADS))
     ap.add_argument("--workload", help="with --trace-summary or --pmc-summary: the workload name to file under")
     ap.add_argument("--copy-calib", action="store_true",
@@ -965,6 +981,15 @@ def main():
         sys.exit(2)
 
     tree_keys = [k for k in args.tree_workloads.split(",") if k]
+    if args.only_ragged:
+        print(f"[bench] ragged leg alone: {args.dtype}", file=sys.stderr, flush=True)
+        if args.copy_calib:
+            import torch
+            copy_calibration(torch.device("cuda:0"))
+        rg = ragged_leg(args.dtype)
+        print(json.dumps({"ragged": rg, "dtype": args.dtype,
+                          "per_algo": {"abia_persistent": {"ms_per_launch": rg["persistent_ms"]}}}), flush=True)
+        return
     if args.only_trees:
         print(f"[bench] tree leg alone: {tree_keys} {args.dtype}", file=sys.stderr, flush=True)
         if args.copy_calib:
@@ -1080,6 +1105,7 @@ def main():
         result["serving"] = serving_leg(args.dtype)
         l80 = result["serving"]["load_80pct"]
         result["p99_latency_ms_at_80pct_load"] = l80["p99_ms"]
+        result["p99_latency_ms_at_5000_qps"] = result["serving"]["qps_5000"]["p99_ms"]
     if not args.no_cpu and args.dtype == "f64":
         print("[bench] cpu baseline leg", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(rb, q, qd, tau, min(args.cpu_chains, args.batch))

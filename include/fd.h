@@ -24,7 +24,7 @@
  * fd_forward_persistent, fd_backward). The lane-per-link paths (FD_ALGO_JSIIA,
  * fd_inverse, fd_joint_inertia) need the links of each robot numbered
  * depth-first, so that every subtree is a run of consecutive links. The CFA
- * takes serial chains only. A path that does not take the model returns
+ * (both forms) and FD_ALGO_ABIA_SCAN take serial chains only. A path that does not take the model returns
  * FD_ERR_UNSUPPORTED; FD_ALGO_AUTO picks one that does.
  * Gravity acts as a base acceleration (the "const." terms of eq. (EOM-full));
  * there is no force at the end effector. SI units, angles in radians.
@@ -63,7 +63,24 @@ typedef enum {
     FD_ERR_WORKSPACE = -5      /* workspace missing or smaller than fd_workspace_size */
 } fd_status_t;
 
-typedef enum { FD_ALGO_ABIA = 0, FD_ALGO_JSIIA = 1, FD_ALGO_CFA = 2, FD_ALGO_AUTO = 3 } fd_algo_t;
+/* FD_ALGO_ABIA runs one chain per lane (three serial sweeps; for large batches).
+ * FD_ALGO_ABIA_SCAN is the same algorithm with a group of lanes per chain: the
+ * serial articulated-inertia recursion spread over the 6x6 entries, then its
+ * two bi-diagonal systems by the parallel scan (Sec. II-C, Sec. II-B); for
+ * small batches (one robot: latency). FD_ALGO_CFA_PROJ is the constraint force
+ * algorithm without a basis W of the constraint forces (Sec. III-B; Sec. VI
+ * leaves the choice of W open): the projectors P_i = I - S_i S_i^T in its
+ * place give a 6x6 block tri-diagonal system P Phi P + S S^T, solved by the
+ * same odd-even elimination, whose solution is W F_c for every W. Both take
+ * serial chains only. */
+typedef enum {
+    FD_ALGO_ABIA = 0,
+    FD_ALGO_JSIIA = 1,
+    FD_ALGO_CFA = 2,
+    FD_ALGO_AUTO = 3,
+    FD_ALGO_ABIA_SCAN = 4,
+    FD_ALGO_CFA_PROJ = 5
+} fd_algo_t;
 typedef enum { FD_F64 = 0, FD_F32 = 1 } fd_dtype_t;
 
 typedef struct fd_model fd_model_t; /* opaque, device resident, owned by the library */
@@ -141,9 +158,10 @@ fd_status_t fd_forward(const fd_model_t* model, const fd_batch_t* batch, const v
  * then `grid` resident wavefronts take 64-chain tiles of that order from an
  * atomic counter until none is left, so each tile holds chains of nearly
  * equal length and the longest go first. grid = 0 picks the number of
- * wavefronts the GPU holds at once. Results equal fd_forward(...,
+ * wavefronts the GPU holds at once; either way the launch takes at most one
+ * wavefront per 64-chain tile of the batch. Results equal fd_forward(...,
  * FD_ALGO_ABIA, ...) bit for bit. The workspace must hold
- * fd_persistent_workspace_size bytes for the same grid. Asynchronous. */
+ * fd_persistent_workspace_size bytes for the same batch and grid. Asynchronous. */
 fd_status_t fd_persistent_workspace_size(const fd_model_t* model, const fd_batch_t* batch, int32_t grid,
                                          size_t* bytes);
 fd_status_t fd_forward_persistent(const fd_model_t* model, const fd_batch_t* batch, const void* q, const void* qd,
@@ -218,7 +236,7 @@ fd_status_t fd_btd_solve6(fd_dtype_t dtype, int32_t segments, const int64_t* off
                           const void* d, const void* u, const void* r, void* x, int* status, void* hip_stream);
 
 /* Choice table for FD_ALGO_AUTO, per precision: table[n * 21 + k] (n = 1..256,
- * k = 0..20) is the algorithm (FD_ALGO_ABIA/JSIIA/CFA) for batches whose
+ * k = 0..20) is the algorithm (any but FD_ALGO_AUTO) for batches whose
  * longest chain has n links and whose size rounds to 2^k chains; produced by
  * the autotuner from measured launch times. Host pointer, 257 * 21 bytes,
  * copied. NULL restores the built-in choice. Not safe to call while another

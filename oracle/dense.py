@@ -303,6 +303,23 @@ def cfa_qdd(ch: Chain, q, tau_delta):
     return c @ tau_delta + b.T @ fc
 
 
+def cfa_proj_qdd(ch: Chain, q, tau_delta):
+    """The CFA without a basis W (Sec. III, with the choice of W that Sec. VI
+    leaves open replaced by projectors): P = diag(I - S_i S_i^T / |S_i|^2) and
+    A^ = P Phi P + S S^T (6n x 6n), X = A^-1 (-P Phi S tau_delta), F = S tau_delta + X,
+    qdd = S^T Phi F. Returns (qdd, X)."""
+    phi, _, s, _, _, _ = cfa_matrices(ch, q)
+    n = ch.n
+    proj = np.eye(6 * n)
+    for i in range(n):
+        si = s[6 * i:6 * i + 6, i]
+        proj[6 * i:6 * i + 6, 6 * i:6 * i + 6] -= np.outer(si, si) / (si @ si)
+    ahat = proj @ phi @ proj + s @ s.T
+    x = np.linalg.solve(ahat, -proj @ phi @ s @ tau_delta)
+    f = s @ tau_delta + x
+    return s.T @ phi @ f, x
+
+
 def cfa_c_matrix(ch: Chain, q):
     """C = S^T Phi S (n x n, tri-diagonal) from the blocks of Phi:
     Phi_ii = J_i^-1 + Ad_i J_{i-1}^-1 Ad_i^T, Phi_{i,i+1} = -J_i^-1 Ad_{i+1}^T.

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfd.so")
 
 FD_OK, FD_ERR_INVALID_ARG, FD_ERR_UNSUPPORTED, FD_ERR_OUT_OF_MEMORY, FD_ERR_DEVICE, FD_ERR_WORKSPACE = 0, -1, -2, -3, -4, -5
-ALGOS = {"abia": 0, "jsiia": 1, "cfa": 2, "auto": 3}
+ALGOS = {"abia": 0, "jsiia": 1, "cfa": 2, "auto": 3, "abia_scan": 4, "cfa_proj": 5}
 DTYPES = {"f64": 0, "f32": 1}
 
 # C-ABI entry points declared in include/fd.h

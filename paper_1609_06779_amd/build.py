@@ -26,7 +26,7 @@ FLAGS = [
     "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
 ]
 
-SOURCES = ["fd_api.cpp", "k_model.hip", "k_inverse.hip", "k_cfa.hip", "k_jsiia.hip", "k_abia.hip", "k_blocks.hip", "k_adjoint.hip"]
+SOURCES = ["fd_api.cpp", "k_model.hip", "k_inverse.hip", "k_cfa.hip", "k_jsiia.hip", "k_abia.hip", "k_abia_scan.hip", "k_blocks.hip", "k_adjoint.hip"]
 
 
 def _compile(src: str) -> str:

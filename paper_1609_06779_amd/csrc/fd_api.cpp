@@ -177,7 +177,9 @@ fd_algo_t pick_algo(const fd_model* m, int nmax, int batch) {
     fd_algo_t a = FD_ALGO_ABIA;
     if (!t.empty() && nmax >= 1 && nmax <= kMaxLinks) a = (fd_algo_t)t[nmax * 21 + log2_bucket(batch)];
     // branched robots: the CFA is built for serial chains, JSIIA for depth-first numbering
-    if (m->tree && (a == FD_ALGO_CFA || (a == FD_ALGO_JSIIA && !m->depth_first))) a = FD_ALGO_ABIA;
+    if (m->tree && (a == FD_ALGO_CFA || a == FD_ALGO_CFA_PROJ || a == FD_ALGO_ABIA_SCAN ||
+                    (a == FD_ALGO_JSIIA && !m->depth_first)))
+        a = FD_ALGO_ABIA;
     // Robots of different topologies in one wavefront make the lane-per-chain
     // ABIA diverge at every branch point of any of its lanes (65536 trees of 64
     // links: 2.1 ms, against 0.66 ms with one shared topology); JSIIA puts one
@@ -197,7 +199,8 @@ bool auto_persistent(const fd_batch_t* b, fd_algo_t picked) { return b->offsets 
 // algorithm does not take this model or chain length.
 template <typename T> fd_status_t lane_path_check(const fd_model* m, fd_algo_t algo, int np) {
     if (algo == FD_ALGO_JSIIA && ((m->tree && !m->depth_first) || np > fdk::jsiia_max_np<T>())) return FD_ERR_UNSUPPORTED;
-    if (algo == FD_ALGO_CFA && m->tree) return FD_ERR_UNSUPPORTED;
+    if ((algo == FD_ALGO_CFA || algo == FD_ALGO_CFA_PROJ || algo == FD_ALGO_ABIA_SCAN) && m->tree)
+        return FD_ERR_UNSUPPORTED;
     return FD_OK;
 }
 
@@ -213,6 +216,7 @@ fd_status_t forward_t(const fd_model* m, const BatchPlan& p, const void* q, cons
     const int np = pow2_lanes(p.nmax);
     const fd_status_t ok = lane_path_check<T>(m, algo, np);
     if (ok != FD_OK) return ok;
+    if (!out && !o.aux) return FD_ERR_INVALID_ARG;   // the kernels need somewhere to put qdd
     switch (algo) {
         case FD_ALGO_ABIA: {
             size_t need = fdk::abia_workspace_elems(p.cm.batch, p.nmax, m->tree) * sizeof(T);
@@ -223,7 +227,10 @@ fd_status_t forward_t(const fd_model* m, const BatchPlan& p, const void* q, cons
         case FD_ALGO_JSIIA:
             return from_hip(fdk::launch_jsiia<T>(np, v, p.cm, tq, tqd, tt, out, nullptr, o, st));
         case FD_ALGO_CFA:
-            return from_hip(fdk::launch_cfa<T>(np, v, p.cm, tq, tqd, tt, out, nullptr, o, st));
+        case FD_ALGO_CFA_PROJ:
+            return from_hip(fdk::launch_cfa<T>(np, v, p.cm, tq, tqd, tt, out, nullptr, o, algo == FD_ALGO_CFA_PROJ, st));
+        case FD_ALGO_ABIA_SCAN:
+            return from_hip(fdk::launch_abia_scan<T>(np, v, p.cm, tq, tqd, tt, out, o, st));
         default:
             return FD_ERR_INVALID_ARG;
     }
@@ -465,7 +472,9 @@ fd_dtype_t fd_model_dtype(const fd_model_t* m) { return m ? m->dtype : FD_F64; }
 
 int32_t fd_max_links(const fd_model_t* m, fd_algo_t algo) {
     if (!m) return 0;
-    if (m->tree && (algo == FD_ALGO_CFA || (algo == FD_ALGO_JSIIA && !m->depth_first))) return 0;
+    if (m->tree && (algo == FD_ALGO_CFA || algo == FD_ALGO_CFA_PROJ || algo == FD_ALGO_ABIA_SCAN ||
+                    (algo == FD_ALGO_JSIIA && !m->depth_first)))
+        return 0;
     if (algo == FD_ALGO_JSIIA) return m->dtype == FD_F64 ? fdk::jsiia_max_np<double>() : fdk::jsiia_max_np<float>();
     return kMaxLinks;
 }
@@ -499,7 +508,7 @@ fd_status_t fd_forward(const fd_model_t* m, const fd_batch_t* b, const void* q, 
     BatchPlan p;
     fd_status_t s = plan_batch(m, b, &p);
     if (s != FD_OK) return s;
-    if (algo < FD_ALGO_ABIA || algo > FD_ALGO_AUTO) return FD_ERR_INVALID_ARG;
+    if (algo < FD_ALGO_ABIA || algo > FD_ALGO_CFA_PROJ) return FD_ERR_INVALID_ARG;
     if (b->batch == 0) return FD_OK;
     if (!q || !qd || !tau || !qdd) return FD_ERR_INVALID_ARG;
     if (algo == FD_ALGO_AUTO) {
@@ -511,13 +520,20 @@ fd_status_t fd_forward(const fd_model_t* m, const fd_batch_t* b, const void* q, 
     return forward_t<float>(m, p, q, qd, tau, qdd, algo, ws, ws_bytes, st);
 }
 
-int persistent_grid(fd_dtype_t dtype, int32_t grid) {
-    if (grid > 0) return grid;
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    // one 64-thread workgroup per SIMD per wave slot the kernel's registers allow
-    const int per_cu = dtype == FD_F64 ? 4 : 12;
-    return cus * per_cu;
+// Wavefronts of a persistent launch: the caller's grid, or (grid 0) as many as
+// the GPU holds at once; never more than the batch has 64-chain tiles, since a
+// wavefront without a tile only exits (and each one holds workspace).
+int persistent_grid(fd_dtype_t dtype, int32_t grid, int32_t batch) {
+    int g = grid;
+    if (g <= 0) {
+        int dev = 0, cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        // one 64-thread workgroup per SIMD per wave slot the kernel's registers allow
+        const int per_cu = dtype == FD_F64 ? 4 : 12;
+        g = cus * per_cu;
+    }
+    const int tiles = (std::max(batch, 1) + 63) / 64;
+    return std::min(g, tiles);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -528,7 +544,7 @@ fd_status_t fd_persistent_workspace_size(const fd_model_t* m, const fd_batch_t* 
     fd_status_t s = plan_batch(m, b, &p);
     if (s != FD_OK) return s;
     const size_t esz = m->dtype == FD_F64 ? sizeof(double) : sizeof(float);
-    const int g = persistent_grid(m->dtype, grid);
+    const int g = persistent_grid(m->dtype, grid, b->batch);
     *bytes = align256(fdk::persistent_plan_bytes(b->batch)) + fdk::abia_persistent_workspace_elems(g, p.nmax, m->tree) * esz;
     return FD_OK;
 }
@@ -543,7 +559,7 @@ fd_status_t fd_forward_persistent(const fd_model_t* m, const fd_batch_t* b, cons
     if (b->batch == 0) return FD_OK;
     if (!q || !qd || !tau || !qdd) return FD_ERR_INVALID_ARG;
     const size_t esz = m->dtype == FD_F64 ? sizeof(double) : sizeof(float);
-    const int g = persistent_grid(m->dtype, grid);
+    const int g = persistent_grid(m->dtype, grid, b->batch);
     const size_t plan = align256(fdk::persistent_plan_bytes(b->batch));
     if (!ws || ws_bytes < plan + fdk::abia_persistent_workspace_elems(g, p.nmax, m->tree) * esz)
         return FD_ERR_WORKSPACE;
@@ -570,7 +586,7 @@ fd_status_t fd_backward_workspace_size(const fd_model_t* m, const fd_batch_t* b,
     BatchPlan p;
     fd_status_t s = plan_batch(m, b, &p);
     if (s != FD_OK) return s;
-    if (algo < FD_ALGO_ABIA || algo > FD_ALGO_AUTO) return FD_ERR_INVALID_ARG;
+    if (algo < FD_ALGO_ABIA || algo > FD_ALGO_CFA_PROJ) return FD_ERR_INVALID_ARG;
     algo = backward_algo(m, p, b->batch, algo);
     *bytes = m->dtype == FD_F64 ? backward_bytes<double>(m, p, algo) : backward_bytes<float>(m, p, algo);
     return FD_OK;
@@ -582,7 +598,7 @@ fd_status_t fd_backward(const fd_model_t* m, const fd_batch_t* b, const void* q,
     BatchPlan p;
     fd_status_t s = plan_batch(m, b, &p);
     if (s != FD_OK) return s;
-    if (algo < FD_ALGO_ABIA || algo > FD_ALGO_AUTO) return FD_ERR_INVALID_ARG;
+    if (algo < FD_ALGO_ABIA || algo > FD_ALGO_CFA_PROJ) return FD_ERR_INVALID_ARG;
     if (b->batch == 0) return FD_OK;
     if (!q || !qd || (!qdd && !tau) || !gqdd || !gq || !gqd || !gtau) return FD_ERR_INVALID_ARG;
     algo = backward_algo(m, p, b->batch, algo);
@@ -691,7 +707,7 @@ fd_status_t fd_set_auto_table(fd_dtype_t dtype, const int8_t* table) {
     for (int n = 1; n <= kMaxLinks; ++n)
         for (int k = 0; k < 21; ++k) {
             int a = next[n * 21 + k];
-            if (a < FD_ALGO_ABIA || a > FD_ALGO_CFA) return FD_ERR_INVALID_ARG;
+            if (a < FD_ALGO_ABIA || a > FD_ALGO_CFA_PROJ || a == FD_ALGO_AUTO) return FD_ERR_INVALID_ARG;
             if (a == FD_ALGO_JSIIA && pow2_lanes(n) > jmax) return FD_ERR_INVALID_ARG;
         }
     t.swap(next);

@@ -301,7 +301,7 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
         t[2] += x;
 #pragma unroll
         for (int c = 0; c < 6; ++c) acc[c] = t[c];
-        qdd[st] = x;
+        o.put(qdd, st, b, i, x);                      // qdd may be null when the reverse mode takes it in aux
         if constexpr (TREE) {
             if (code & TREE_BRANCH) {
 #pragma unroll

@@ -25,13 +25,18 @@ hipError_t launch_inverse(int np, const ModelView<T>& m, const ChainMap& cm, con
 template <typename T>
 hipError_t launch_mass(int np, const ModelView<T>& m, const ChainMap& cm, const T* q, T* mass_out,
                        hipStream_t st);
+// proj: the basis-free form (projectors instead of W, 6x6 blocks)
 template <typename T>
 hipError_t launch_cfa(int np, const ModelView<T>& m, const ChainMap& cm, const T* q, const T* qd,
-                      const T* tau, T* qdd, int* status, const FdOut<T>& o, hipStream_t st);
+                      const T* tau, T* qdd, int* status, const FdOut<T>& o, bool proj, hipStream_t st);
 template <typename T>
 hipError_t launch_jsiia(int np, const ModelView<T>& m, const ChainMap& cm, const T* q, const T* qd,
                         const T* tau, T* qdd, int* status, const FdOut<T>& o, hipStream_t st);
 template <typename T> int jsiia_max_np();
+// articulated-body algorithm, one chain per workgroup of max(64, np) lanes
+template <typename T>
+hipError_t launch_abia_scan(int np, const ModelView<T>& m, const ChainMap& cm, const T* q, const T* qd,
+                            const T* tau, T* qdd, const FdOut<T>& o, hipStream_t st);
 // lane-per-chain kernel
 // stream_model: non-temporal model and workspace accesses (for launches whose
 // footprint outgrows the last-level cache; see stream_footprint)

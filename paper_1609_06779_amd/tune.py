@@ -24,7 +24,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_TABLE = os.path.join(HERE, "tuning_gfx950.json")
-ALGOS = ("abia", "jsiia", "cfa")
+ALGOS = ("abia", "jsiia", "cfa", "abia_scan")
+CODES = {"abia": 0, "jsiia": 1, "cfa": 2, "abia_scan": 4, "cfa_proj": 5}   # fd_algo_t
+NAMES = {v: k for k, v in CODES.items()}
 N_GRID = (4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256)
 BATCH_GRID = (1, 16, 256, 4096, 65536)
 
@@ -107,7 +109,7 @@ def table_array(entry):
     (nearest measured grid point, lengths rounded up, batches in log scale)."""
     ns = entry["n"]
     bs = entry["batch"]
-    codes = {"abia": 0, "jsiia": 1, "cfa": 2, None: 0}
+    codes = {**CODES, None: 0}
     arr = np.zeros((257, 21), dtype=np.int8)
     for n in range(1, 257):
         i = next((k for k, v in enumerate(ns) if v >= n), len(ns) - 1)
@@ -131,7 +133,7 @@ def best_algo(dtype: str, n: int, batch: int, path=DEFAULT_TABLE) -> str:
     arr = _TABLES[key]
     if arr is None:
         return "abia"
-    return ALGOS[int(arr[min(256, max(1, n)), batch_bucket(batch)])]
+    return NAMES[int(arr[min(256, max(1, n)), batch_bucket(batch)])]
 
 
 def batch_bucket(batch: int) -> int:
@@ -194,8 +196,11 @@ EXP2_GROUPS = (1, 10, 100, 1000, 10000, 100000)
 
 
 def _time_calls(model, tq, tqd, ttau, n, batch, algo, calls):
-    """Mean ms of one fd_forward call over ``calls`` back-to-back calls, each on its
-    own slice of pre-drawn random inputs (launch overhead included)."""
+    """(ms per call, ms on the device per call) of fd_forward over ``calls``
+    back-to-back calls, each on its own slice of pre-drawn random inputs. The
+    first is the paper's measure (launch overhead included: the binding and the
+    launch); the second brackets each launch with its own pair of HIP events,
+    so the time the host takes to issue the next call is left out."""
     import torch
 
     out = torch.empty(batch * n, dtype=tq.dtype, device=tq.device)
@@ -218,7 +223,15 @@ def _time_calls(model, tq, tqd, ttau, n, batch, algo, calls):
         call(k)
     b.record(stream)
     torch.cuda.synchronize()
-    return a.elapsed_time(b) / calls
+    wall = a.elapsed_time(b) / calls
+    reps = min(calls, 50)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for k in range(reps):
+        ev[k][0].record(stream)
+        call(k)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    return wall, float(np.median([x.elapsed_time(y) for x, y in ev]))
 
 
 def experiments(dtype="f64", calls=1000, log=None):
@@ -244,9 +257,9 @@ def experiments(dtype="f64", calls=1000, log=None):
         for algo in ALGOS:
             row = {"exp": exp, "n": n, "groups": batch, "algo": algo, "dtype": dtype}
             if n > model.max_links(algo):
-                row["ms"] = None                                    # longer than this algorithm's kernels take
+                row["ms"] = row["device_ms"] = None                 # longer than this algorithm's kernels take
             else:
-                row["ms"] = _time_calls(model, tq, tqd, ttau, n, batch, algo, reps)
+                row["ms"], row["device_ms"] = _time_calls(model, tq, tqd, ttau, n, batch, algo, reps)
             rows.append(row)
             if log:
                 print(json.dumps(row), file=log, flush=True)

@@ -83,3 +83,31 @@ def test_auto_on_a_ragged_batch_takes_the_persistent_launch(dev):
         assert model.workspace_size(batch, "auto", offsets=toff) == model.persistent_workspace(batch, 0, offsets=toff).numel()
     ref = model.forward(tq, tqd, ttau, batch=batch, algo=picked, offsets=toff)
     assert torch.equal(auto, ref), picked
+
+
+def test_full_size_ragged_batch_sampled(dev):
+    """The ragged workload at full size (100000 chains, n ~ U{4..256}, each its own
+    robot) in the launch the benchmark times (AUTO: the persistent length-sorted
+    launch): 600 chains spread over every length band against the oracle, within
+    the FP64 cap, and every output finite."""
+    from paper_1609_06779_amd import fd
+
+    lengths = synth.ragged_lengths(100000, 4, 256, cfg=3)
+    rb = synth.make_robots(lengths, cfg=3)
+    q, qd, tau = synth.make_state(lengths, cfg=3)
+    off = rb.offsets
+    model = fd.Model(rb, "f64", device=dev)
+    tq, tqd, ttau = (torch.from_numpy(a).to(dev) for a in (q, qd, tau))
+    toff = torch.from_numpy(off).to(dev)
+    out = model.forward(tq, tqd, ttau, batch=len(lengths), algo="auto", offsets=toff).cpu().numpy()
+    assert np.all(np.isfinite(out))
+    rng = np.random.default_rng(31)
+    order = np.argsort(lengths, kind="stable")
+    pick = np.unique(np.concatenate([order[np.linspace(0, len(order) - 1, 300).astype(int)],
+                                     rng.choice(len(lengths), 300, replace=False)]))
+    sub = rb.take(pick)
+    idx = np.concatenate([np.arange(off[b], off[b + 1]) for b in pick])
+    ref = oracle.fd(sub, q[idx], qd[idx], tau[idx])
+    err = oracle.relative_error(out[idx], ref, sub.offsets)
+    print(f"ragged 100000 sampled {len(pick)}: worst {err.max():.2e}", flush=True)
+    assert np.all(err <= CAP["f64"]), err.max()

@@ -353,6 +353,42 @@ def test_cfa_result_does_not_depend_on_the_constraint_basis(n):
     assert np.abs(c - b3.T @ np.linalg.solve(a3, b3) - minv1).max() > 1e-6
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 6])
+def test_cfa_projector_form_equals_the_definition(n):
+    """The basis-free constraint system A^ = P Phi P + S S^T (projectors in place of
+    W) gives the oracle's qdd, its solution X has no component along any S_i, and
+    X = W F_c with F_c = -A^-1 B tau_delta of the W-form (x^T A^ x = a^T A a + |b|^2
+    for x = W a + S b)."""
+    rb = synth.make_robots([n], seed=95, random_home=True)
+    q, qd, tau = synth.make_state([n], seed=95)
+    ch = dense.Chain(rb, 0, n)
+    td = tau - oracle.rnea(rb, q, qd)
+    qdd, x = dense.cfa_proj_qdd(ch, q, td)
+    np.testing.assert_allclose(qdd, oracle.fd(rb, q, qd, tau), rtol=1e-9, atol=1e-9)
+    _, w, s, a, b, _ = dense.cfa_matrices(ch, q)
+    np.testing.assert_allclose(s.T @ x, 0, atol=1e-12 * max(1.0, np.abs(x).max()))
+    fc = -np.linalg.solve(a, b @ td)
+    np.testing.assert_allclose(x, w @ fc, rtol=1e-9, atol=1e-10 * max(1.0, np.abs(x).max()))
+
+
+def test_cfa_projector_form_needs_the_s_block():
+    """Without the S S^T term the projected system P Phi P is singular (its null
+    space holds every S_i): the term is what makes it solvable, not a regulariser
+    that changes the answer."""
+    n = 3
+    rb = synth.make_robots([n], seed=96)
+    q, _, _ = synth.make_state([n], seed=96)
+    ch = dense.Chain(rb, 0, n)
+    phi, _, s, _, _, _ = dense.cfa_matrices(ch, q)
+    proj = np.eye(6 * n)
+    for i in range(n):
+        si = s[6 * i:6 * i + 6, i]
+        proj[6 * i:6 * i + 6, 6 * i:6 * i + 6] -= np.outer(si, si) / (si @ si)
+    ev = np.linalg.eigvalsh(proj @ phi @ proj)
+    assert np.sum(np.abs(ev) < 1e-12 * ev.max()) == n
+    assert np.linalg.eigvalsh(proj @ phi @ proj + s @ s.T).min() > 0
+
+
 def test_abia_single_link_is_axis_inertia():
     rb = synth.make_robots([1], seed=92)
     ch = dense.Chain(rb, 0, 1)
