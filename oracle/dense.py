@@ -277,6 +277,45 @@ def abia_qdd(ch: Chain, q, tau_delta):
     return qdd
 
 
+def abia_scan_qdd(ch: Chain, q, tau_delta):
+    """ABIA with its two linear recursions written as the bi-diagonal systems of
+    Sec. II-C and solved by the scan of Sec. II-B (serial chains). After the
+    articulated-inertia recursion (h_i, D_i), with Ad_i the (i, i-1) block of
+    Gamma:
+      backward  p_{i-1} = B_i p_i + c_i,  B_i = Ad_i^T (I - h_i S_i^T / D_i),
+                c_i = Ad_i^T h_i tau_delta_i / D_i,  p_{n-1} = 0;
+      forward   a_i = B'_i a_{i-1} + c'_i,  B'_i = (I - S_i h_i^T / D_i) Ad_i,
+                c'_i = S_i u_i / D_i,  u_i = tau_delta_i - S_i^T p_i,  a_{-1} = 0;
+      qdd_i = (u_i - h_i^T Ad_i a_{i-1}) / D_i.
+    Each system is solved by scan_homogeneous (the all-prefix product of the
+    homogeneous elements)."""
+    n = ch.n
+    assert all(ch.parent[i] == i - 1 for i in range(n)), "serial chains only"
+    ad = [ch.ad_link(i, q[i]) for i in range(n)]
+    s = [ch.screw(i) for i in range(n)]
+    jhat = [inertia6(ch.mass[i], ch.com[i], ch.inertia[i]) for i in range(n)]
+    h, dd = [None] * n, np.zeros(n)
+    for i in range(n - 1, -1, -1):
+        h[i] = jhat[i] @ s[i]
+        dd[i] = s[i] @ h[i]
+        if i > 0:
+            jhat[i - 1] = jhat[i - 1] + ad[i].T @ (jhat[i] - np.outer(h[i], h[i]) / dd[i]) @ ad[i]
+    # backward system: element k of the reversed sequence carries link n-1-k's map into p_{n-2-k}
+    bb = np.stack([ad[i].T @ (np.eye(6) - np.outer(h[i], s[i]) / dd[i]) for i in range(n)])
+    cc = np.stack([ad[i].T @ h[i] * tau_delta[i] / dd[i] for i in range(n)])
+    incl = scan_homogeneous(bb, cc, reverse=True)       # incl[i] = E_i(E_{i+1}(... E_{n-1}(0)))
+    p = [incl[i + 1] if i + 1 < n else np.zeros(6) for i in range(n)]
+    u = np.array([tau_delta[i] - s[i] @ p[i] for i in range(n)])
+    bf = np.stack([(np.eye(6) - np.outer(s[i], h[i]) / dd[i]) @ ad[i] for i in range(n)])
+    cf = np.stack([s[i] * u[i] / dd[i] for i in range(n)])
+    acc = scan_homogeneous(bf, cf)                      # acc[i] = a_i
+    qdd = np.zeros(n)
+    for i in range(n):
+        a_prev = acc[i - 1] if i > 0 else np.zeros(6)
+        qdd[i] = (u[i] - h[i] @ (ad[i] @ a_prev)) / dd[i]
+    return qdd
+
+
 def constraint_basis(s):
     """W_i: an orthonormal basis (6 x 5) of the complement of S_i (W_i^T S_i = 0)."""
     _, _, vt = np.linalg.svd(s.reshape(1, 6))

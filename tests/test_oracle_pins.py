@@ -389,6 +389,20 @@ def test_cfa_projector_form_needs_the_s_block():
     assert np.linalg.eigvalsh(proj @ phi @ proj + s @ s.T).min() > 0
 
 
+@pytest.mark.parametrize("n", [1, 2, 7, 16])
+def test_abia_by_scans_equals_the_definition(n):
+    """The ABIA's two bi-diagonal systems solved by the scan (Sec. II-B, II-C):
+    the backward elements (Ad^T (I - h S^T / D), Ad^T h tau_delta / D) and the
+    forward ones ((I - S h^T / D) Ad, S u / D) give the oracle's q-ddot."""
+    rb = synth.make_robots([n], seed=97, random_home=True)
+    q, qd, tau = synth.make_state([n], seed=97)
+    ch = dense.Chain(rb, 0, n)
+    td = tau - oracle.rnea(rb, q, qd)
+    ref = oracle.fd(rb, q, qd, tau)
+    np.testing.assert_allclose(dense.abia_scan_qdd(ch, q, td), ref, rtol=1e-9, atol=1e-9)
+    np.testing.assert_allclose(dense.abia_scan_qdd(ch, q, td), dense.abia_qdd(ch, q, td), rtol=1e-10, atol=1e-10)
+
+
 def test_abia_single_link_is_axis_inertia():
     rb = synth.make_robots([1], seed=92)
     ch = dense.Chain(rb, 0, 1)
