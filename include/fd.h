@@ -152,6 +152,23 @@ fd_status_t fd_forward(const fd_model_t* model, const fd_batch_t* batch, const v
                        const void* tau, void* qdd, fd_algo_t algo, void* workspace, size_t ws_bytes,
                        void* hip_stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. The same
+ * computation as fd_forward (same kernels, same results bit for bit), with
+ * the workspace taken from a scratch array of FD_NOALLOC_SCRATCH_BYTES that
+ * the library holds on each GPU from its first fd_init on that GPU until the
+ * process ends. No call allocates or frees memory. FD_ERR_WORKSPACE when the
+ * batch needs more than FD_NOALLOC_SCRATCH_BYTES (fd_workspace_size with the
+ * same arguments tells in advance); the algorithms without a workspace
+ * (JSIIA, CFA) have no such limit. Every call on one GPU shares that GPU's
+ * array, so calls that overlap on one GPU (concurrent streams, or threads)
+ * race and give wrong results: serialise them. What must start at zero (the
+ * persistent launch's tile counter and length histogram) is cleared by a
+ * kernel inside each call, never by a memset. Asynchronous. */
+#define FD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+fd_status_t fd_forward_noalloc(const fd_model_t* model, const fd_batch_t* batch, const void* q, const void* qd,
+                               const void* tau, void* qdd, fd_algo_t algo, void* hip_stream);
+
 /* Forward dynamics of a batch, typically ragged, in one persistent launch of the
  * articulated-body algorithm (Sec. II-C). Small planning kernels first sort the
  * batch's chains on the device by decreasing length (into the workspace);

@@ -16,7 +16,8 @@ EXPORTS = ("fd_init", "fd_destroy", "fd_model_dtype", "fd_max_links", "fd_worksp
            "fd_persistent_workspace_size", "fd_forward_persistent",
            "fd_backward_workspace_size", "fd_backward", "fd_euler_step", "fd_euler_step_backward",
            "fd_inverse", "fd_joint_inertia", "fd_scan6", "fd_btd_solve6", "fd_set_auto_table", "fd_status_string",
-           "fd_auto_algo")
+           "fd_auto_algo", "fd_forward_noalloc")
+NOALLOC_SCRATCH_BYTES = 64 << 20          # FD_NOALLOC_SCRATCH_BYTES
 
 
 class ModelDesc(ctypes.Structure):
@@ -73,6 +74,8 @@ def load() -> ctypes.CDLL:
     lib.fd_workspace_size.restype = ctypes.c_int
     lib.fd_forward.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, vp, vp, ctypes.c_int, vp, sz, vp]
     lib.fd_forward.restype = ctypes.c_int
+    lib.fd_forward_noalloc.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, vp, vp, ctypes.c_int, vp]
+    lib.fd_forward_noalloc.restype = ctypes.c_int
     lib.fd_persistent_workspace_size.argtypes = [vp, ctypes.POINTER(Batch), i32, ctypes.POINTER(sz)]
     lib.fd_persistent_workspace_size.restype = ctypes.c_int
     lib.fd_forward_persistent.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, vp, vp, i32, vp, sz, vp]

@@ -6,11 +6,18 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
 #include "../../include/fd.h"
 #include "kernels.h"
+
+// Scratch memory of fd_forward_noalloc: one copy per GPU, held from the
+// library's load until the process ends. In host code `scratch` names a
+// host-side stand-in, never the device copy: host code only ever uses the
+// address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[FD_NOALLOC_SCRATCH_BYTES];
 
 struct fd_model {
     fd_dtype_t dtype = FD_F64;
@@ -281,6 +288,25 @@ fd_status_t backward_t(const fd_model* m, const BatchPlan& p, const void* q, con
                                           stream_model(m, p.cm.batch, p.nmax), st));
 }
 
+// The device address of the current GPU's copy of `scratch`, looked up once
+// per device (with that device current) and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+fd_status_t scratch_address(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return FD_ERR_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return FD_ERR_DEVICE;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return FD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -448,6 +474,8 @@ fd_status_t fd_init(const fd_model_desc_t* d, fd_dtype_t dtype, fd_model_t** out
     if (d_raw) (void)hipFree(d_raw);
     if (d_parent) (void)hipFree(d_parent);
     if (d_ri) (void)hipFree(d_ri);
+    void* scratch_ptr = nullptr;             // set-up of fd_forward_noalloc on this device
+    if (st == FD_OK) st = scratch_address(&scratch_ptr);
     if (st != FD_OK) {
         fd_destroy(m);
         return st;
@@ -518,6 +546,17 @@ fd_status_t fd_forward(const fd_model_t* m, const fd_batch_t* b, const void* q, 
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     if (m->dtype == FD_F64) return forward_t<double>(m, p, q, qd, tau, qdd, algo, ws, ws_bytes, st);
     return forward_t<float>(m, p, q, qd, tau, qdd, algo, ws, ws_bytes, st);
+}
+
+fd_status_t fd_forward_noalloc(const fd_model_t* m, const fd_batch_t* b, const void* q, const void* qd,
+                               const void* tau, void* qdd, fd_algo_t algo, void* hip_stream) {
+    size_t need = 0;
+    fd_status_t s = fd_workspace_size(m, b, algo, &need);
+    if (s != FD_OK) return s;
+    if (need > FD_NOALLOC_SCRATCH_BYTES) return FD_ERR_WORKSPACE;
+    void* ws = nullptr;
+    if (need > 0 && (s = scratch_address(&ws)) != FD_OK) return s;
+    return fd_forward(m, b, q, qd, tau, qdd, algo, ws, need > 0 ? FD_NOALLOC_SCRATCH_BYTES : 0, hip_stream);
 }
 
 // Wavefronts of a persistent launch: the caller's grid, or (grid 0) as many as

@@ -208,6 +208,20 @@ class Model:
                    "fd_forward")
         return out
 
+    def forward_noalloc(self, q, qd, tau, out, batch: int, algo: str = "auto", robot_id=None, offsets=None,
+                        stream=None, max_links: int = 0):
+        """fd_forward_noalloc: forward() with the library's own per-GPU scratch
+        array as the workspace, so the call allocates nothing (out is required).
+        Calls that overlap on one GPU share that array and race."""
+        dt = self.torch_dtype
+        for name, t in (("q", q), ("qd", qd), ("tau", tau), ("out", out)):
+            _dev_tensor(t, dt, self.device, name)
+        b = self._batch(batch, robot_id, offsets, max_links,
+                        state=(("q", q), ("qd", qd), ("tau", tau), ("out", out)))
+        _lib.check(_lib.load().fd_forward_noalloc(self._h, ctypes.byref(b), _ptr(q), _ptr(qd), _ptr(tau), _ptr(out),
+                                                  _lib.ALGOS[algo], _stream(stream)), "fd_forward_noalloc")
+        return out
+
     def persistent_workspace(self, batch: int, grid: int = 0, robot_id=None, offsets=None):
         n = ctypes.c_size_t()
         b = self._batch(batch, robot_id, offsets)
