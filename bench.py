@@ -184,7 +184,8 @@ def summarize_flops(p1_dir: str, p2_dir: str, workload: str, commands, summary_c
              f"Executed flops = `SQ_INSTS_VALU_FLOPS_{P}` x 64 lanes (it counts 2 per FMA and 1 per add or "
              "multiply, per wave instruction, so masked lanes are included). The algorithmic count is "
              "bench.py's `fma_per_solve` x 2 x batch. Times: the HIP-event average per launch of the "
-             "bench log named above (an unprofiled bench.py run of the same workload).", "",
+             "bench log named above (a bench.py run of the same workload, unprofiled or under the kernel "
+             "trace only).", "",
              "| algorithm | kernel | executed GFLOP / launch | algorithmic GFLOP / launch | ms / launch | "
              f"executed TFLOP/s | frac of peak | MFMA instructions | {P} share of VALU instructions |",
              "|---|---|---|---|---|---|---|---|---|"]
@@ -224,6 +225,7 @@ def summarize_trace(trace_dir: str, workload: str, commands, summary_cmd: str, b
     with ``bench_log`` (the profiled bench.py's output) its own HIP-event averages go beside."""
     import csv
     import glob
+    import re
 
     events = {}
     if bench_log:
@@ -250,7 +252,7 @@ def summarize_trace(trace_dir: str, workload: str, commands, summary_cmd: str, b
         name = r["Name"].split("(")[0].replace("void ", "")
         if "fdk::" not in name:
             continue
-        algo = next((a for a, pat in KERNEL_PATTERNS if pat.rstrip("<") in name), None)
+        algo = next((a for a, pat in KERNEL_PATTERNS if re.search(pat, name)), None)
         ev = f"{events[algo]:.1f}" if algo in events else "-"
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} "
                      f"| {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f}% | {ev} |")
