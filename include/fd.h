@@ -174,9 +174,10 @@ fd_status_t fd_forward_noalloc(const fd_model_t* model, const fd_batch_t* batch,
  * batch's chains on the device by decreasing length (into the workspace);
  * then `grid` resident wavefronts take 64-chain tiles of that order from an
  * atomic counter until none is left, so each tile holds chains of nearly
- * equal length and the longest go first. grid = 0 picks the number of
- * wavefronts the GPU holds at once; either way the launch takes at most one
- * wavefront per 64-chain tile of the batch. Results equal fd_forward(...,
+ * equal length and the longest go first. grid = 0 takes the default set by
+ * fd_set_persistent_grid, or without one the number of wavefronts the GPU
+ * holds at once; either way the launch takes at most one wavefront per
+ * 64-chain tile of the batch. Results equal fd_forward(...,
  * FD_ALGO_ABIA, ...) bit for bit. The workspace must hold
  * fd_persistent_workspace_size bytes for the same batch and grid. Asynchronous. */
 fd_status_t fd_persistent_workspace_size(const fd_model_t* model, const fd_batch_t* batch, int32_t grid,
@@ -259,6 +260,12 @@ fd_status_t fd_btd_solve6(fd_dtype_t dtype, int32_t segments, const int64_t* off
  * copied. NULL restores the built-in choice. Not safe to call while another
  * thread is inside fd_forward. FD_ERR_INVALID_ARG for a bad dtype or entry. */
 fd_status_t fd_set_auto_table(fd_dtype_t dtype, const int8_t* table);
+
+/* Default grid of persistent launches (fd_forward_persistent with grid 0, and
+ * the persistent launch AUTO takes), per precision; produced by the autotuner.
+ * 0 restores the resident capacity. Not safe to call while another thread is
+ * inside fd_forward. FD_ERR_INVALID_ARG for a bad dtype or a negative grid. */
+fd_status_t fd_set_persistent_grid(fd_dtype_t dtype, int32_t grid);
 
 const char* fd_status_string(fd_status_t status);
 

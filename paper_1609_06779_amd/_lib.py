@@ -16,7 +16,7 @@ EXPORTS = ("fd_init", "fd_destroy", "fd_model_dtype", "fd_max_links", "fd_worksp
            "fd_persistent_workspace_size", "fd_forward_persistent",
            "fd_backward_workspace_size", "fd_backward", "fd_euler_step", "fd_euler_step_backward",
            "fd_inverse", "fd_joint_inertia", "fd_scan6", "fd_btd_solve6", "fd_set_auto_table", "fd_status_string",
-           "fd_auto_algo", "fd_forward_noalloc")
+           "fd_auto_algo", "fd_forward_noalloc", "fd_set_persistent_grid")
 NOALLOC_SCRATCH_BYTES = 64 << 20          # FD_NOALLOC_SCRATCH_BYTES
 
 
@@ -99,6 +99,8 @@ def load() -> ctypes.CDLL:
     lib.fd_btd_solve6.restype = ctypes.c_int
     lib.fd_set_auto_table.argtypes = [ctypes.c_int, vp]
     lib.fd_set_auto_table.restype = ctypes.c_int
+    lib.fd_set_persistent_grid.argtypes = [ctypes.c_int, i32]
+    lib.fd_set_persistent_grid.restype = ctypes.c_int
     lib.fd_auto_algo.argtypes = [vp, ctypes.POINTER(Batch), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     lib.fd_auto_algo.restype = ctypes.c_int
     lib.fd_status_string.argtypes = [ctypes.c_int]

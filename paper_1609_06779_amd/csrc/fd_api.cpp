@@ -559,11 +559,16 @@ fd_status_t fd_forward_noalloc(const fd_model_t* m, const fd_batch_t* b, const v
     return fd_forward(m, b, q, qd, tau, qdd, algo, ws, need > 0 ? FD_NOALLOC_SCRATCH_BYTES : 0, hip_stream);
 }
 
-// Wavefronts of a persistent launch: the caller's grid, or (grid 0) as many as
-// the GPU holds at once; never more than the batch has 64-chain tiles, since a
-// wavefront without a tile only exits (and each one holds workspace).
+// Default grid of persistent launches per precision (fd_set_persistent_grid; 0:
+// the resident capacity).
+int32_t g_persistent_grid[2] = {0, 0};
+
+// Wavefronts of a persistent launch: the caller's grid, else (grid 0) the
+// default set for the precision, else as many as the GPU holds at once; never
+// more than the batch has 64-chain tiles, since a wavefront without a tile only
+// exits (and each one holds workspace).
 int persistent_grid(fd_dtype_t dtype, int32_t grid, int32_t batch) {
-    int g = grid;
+    int g = grid > 0 ? grid : g_persistent_grid[dtype == FD_F64 ? 0 : 1];
     if (g <= 0) {
         int dev = 0, cus = 256;
         if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -750,6 +755,12 @@ fd_status_t fd_set_auto_table(fd_dtype_t dtype, const int8_t* table) {
             if (a == FD_ALGO_JSIIA && pow2_lanes(n) > jmax) return FD_ERR_INVALID_ARG;
         }
     t.swap(next);
+    return FD_OK;
+}
+
+fd_status_t fd_set_persistent_grid(fd_dtype_t dtype, int32_t grid) {
+    if ((dtype != FD_F64 && dtype != FD_F32) || grid < 0) return FD_ERR_INVALID_ARG;
+    g_persistent_grid[dtype == FD_F64 ? 0 : 1] = grid;
     return FD_OK;
 }
 

@@ -78,6 +78,8 @@ class Model:
         self.torch_dtype = _TORCH_DTYPE[dtype]
         self.device = torch.device(device if device is not None else "cuda")
         self.n_links = _c(robots.n_links, np.int32)
+        # the common length when every robot has the same one (0 otherwise), for the size checks
+        self._uniform_n = int(self.n_links[0]) if len(self.n_links) and np.all(self.n_links == self.n_links[0]) else 0
         self._keep = dict(axis=_c(robots.axis), home=_c(robots.home_rot), off=_c(robots.offset),
                           mass=_c(robots.mass), com=_c(robots.com), inertia=_c(robots.inertia))
         par = getattr(robots, "parent", None)
@@ -129,12 +131,14 @@ class Model:
             raise ValueError(f"robot_id has {robot_id.numel()} entries for a batch of {batch}")
         if offsets is not None and offsets.numel() < batch + 1:
             raise ValueError(f"offsets has {offsets.numel()} entries for a batch of {batch} (needs batch + 1)")
-        if offsets is None and len(self.n_links) and np.all(self.n_links == self.n_links[0]):
-            need = int(batch) * int(self.n_links[0])
+        uni = getattr(self, "_uniform_n", None)
+        if uni is None:
+            uni = int(self.n_links[0]) if len(self.n_links) and np.all(self.n_links == self.n_links[0]) else 0
+        if offsets is None and uni:
+            need = int(batch) * uni
             for name, t in state:
                 if t is not None and t.numel() < need:
-                    raise ValueError(f"{name} has {t.numel()} entries; {batch} chains of {self.n_links[0]} "
-                                     f"links need {need}")
+                    raise ValueError(f"{name} has {t.numel()} entries; {batch} chains of {uni} links need {need}")
         b = _lib.Batch()
         b.batch = int(batch)
         b.max_links = int(max_links)
@@ -195,7 +199,8 @@ class Model:
         q = _dev_tensor(q, dt, self.device, "q")
         qd = _dev_tensor(qd, dt, self.device, "qd")
         tau = _dev_tensor(tau, dt, self.device, "tau")
-        with _alloc_on(stream):
+        # enter the stream's context only to allocate (it costs microseconds per call)
+        with _alloc_on(stream) if (out is None or workspace is None) else contextlib.nullcontext():
             if out is None:
                 out = torch.empty_like(q)
             _dev_tensor(out, dt, self.device, "out")

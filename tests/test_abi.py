@@ -141,3 +141,21 @@ def test_binding_checks_array_sizes_before_any_launch():
     # robots of two lengths: the chain starts come from device offsets, so the
     # binding has no size to check and leaves the batch to the library
     assert _Stub([8, 5])._batch(2, state=(("q", torch.empty(1)),)).batch == 2
+
+
+def test_choice_setters_check_their_arguments(lib):
+    """The AUTO table and the default persistent grid are host-side settings:
+    bad precisions, negative grids and table entries that name no algorithm
+    (or AUTO itself) are refused; 0 and NULL restore the built-in choices."""
+    assert lib.fd_set_persistent_grid(7, 0) == _lib.FD_ERR_INVALID_ARG
+    assert lib.fd_set_persistent_grid(0, -1) == _lib.FD_ERR_INVALID_ARG
+    assert lib.fd_set_persistent_grid(1, 512) == _lib.FD_OK
+    assert lib.fd_set_persistent_grid(1, 0) == _lib.FD_OK
+    table = np.zeros(257 * 21, np.int8)
+    for bad in (_lib.ALGOS["auto"], 6, -1):
+        table[300] = bad
+        assert lib.fd_set_auto_table(0, table.ctypes.data_as(ctypes.c_void_p)) == _lib.FD_ERR_INVALID_ARG
+    for good in (_lib.ALGOS["abia_scan"], _lib.ALGOS["cfa_proj"]):
+        table[300] = good
+        assert lib.fd_set_auto_table(0, table.ctypes.data_as(ctypes.c_void_p)) == _lib.FD_OK
+    assert lib.fd_set_auto_table(0, None) == _lib.FD_OK
