@@ -32,25 +32,35 @@
 
 namespace fdk {
 
-// Entry (r, c) of the 6x6 spatial inertia J = [[Ibar, [h]], [-[h], m 1]]
-// from its 10 parameters in LDS (m, h, Ibar; component f of link i at rec[f * np + i]).
-template <typename T>
-__device__ __forceinline__ T inertia_entry(const T* rec, int np, int i, int r, int c) {
-    const T m = rec[12 * np + i];
-    if (r >= 3 && c >= 3) return r == c ? m : T(0);
-    if (r < 3 && c < 3) {
-        const int k = r == c ? r : (r + c == 1 ? 3 : (r + c == 2 ? 4 : 5));   // xx yy zz xy xz yz
-        return rec[(16 + k) * np + i];
+// Per-link record of the recursion in LDS, field f of link i at rec[f * NP + i]:
+// the two 3x3 blocks of X_i = Ad_i^T = [[R, [p] R], [0, R]] (wrench_to_parent),
+// the body inertia, and a field of zeros.
+constexpr int F_R = 0, F_PR = 9, F_M = 18, F_H = 19, F_I = 22, F_ZERO = 28, F_COUNT = 29;
+
+// Field of entry (a, k) of X.
+__device__ __forceinline__ int x_entry_field(int a, int k) {
+    if (a < 3) return k < 3 ? F_R + 3 * a + k : F_PR + 3 * a + (k - 3);
+    return k < 3 ? F_ZERO : F_R + 3 * (a - 3) + (k - 3);
+}
+
+// Where entry (r, c) of the 6x6 spatial inertia J = [[Ibar, [h]], [-[h], m 1]]
+// comes from among its parameters (Ibar as xx yy zz xy xz yz): the field and a
+// sign in {-1, 0, 1}, fixed per lane, so the recursion reads it without branching.
+__device__ __forceinline__ void inertia_entry_source(int r, int c, int* field, int* sign) {
+    if (r >= 3 && c >= 3) {
+        *field = F_M;
+        *sign = r == c ? 1 : 0;
+    } else if (r < 3 && c < 3) {
+        *field = F_I + (r == c ? r : (r + c == 1 ? 3 : (r + c == 2 ? 4 : 5)));
+        *sign = 1;
+    } else {
+        // [h] in the upper right block, -[h] in the lower left: entry (a, b) of [h],
+        // [h]_{ab} = -eps_{abk} h_k
+        const int a = r < 3 ? r : r - 3, b = r < 3 ? c - 3 : c;
+        const bool even = (a == 0 && b == 1) || (a == 1 && b == 2) || (a == 2 && b == 0);
+        *field = F_H + (a == b ? 0 : 3 - a - b);
+        *sign = a == b ? 0 : ((even ? -1 : 1) * (r < 3 ? 1 : -1));
     }
-    // [h] in the upper right block, -[h] in the lower left: entry (a, b) of [h]
-    const int a = r < 3 ? r : r - 3, b = r < 3 ? c - 3 : c;
-    if (a == b) return T(0);
-    const int k = 3 - a - b;                                 // the component not in {a, b}
-    const T hk = rec[(13 + k) * np + i];
-    // [h]_{ab} = -eps_{abk} h_k
-    const bool even = (a == 0 && b == 1) || (a == 1 && b == 2) || (a == 2 && b == 0);
-    const T s = even ? -hk : hk;
-    return r < 3 ? s : -s;
 }
 
 // (B, c) <- (B, c) o (B', c') = (B B', B c' + c) for affine 6x6 elements held
@@ -81,11 +91,10 @@ __global__ __launch_bounds__(NP) void k_abia_scan(ModelView<T> m, ChainMap cm, c
                                                   const T* __restrict__ qd, const T* __restrict__ tau,
                                                   T* __restrict__ qdd, FdOut<T> o) {
     static_assert(NP >= 64 && NP <= 256, "one chain per workgroup of 64..256 lanes");
-    // per-link records for the recursion (pose 12, inertia 10) and, for groups of
-    // several wavefronts, the scans' exchange: never live at the same time
-    constexpr int REC = 22;
+    // per-link records for the recursion and, for groups of several wavefronts,
+    // the scans' exchange: never live at the same time
     constexpr int XCH = NP > 64 ? 42 * NP : 0;
-    __shared__ T lds[REC * NP > XCH ? REC * NP : XCH];
+    __shared__ T lds[F_COUNT * NP > XCH ? F_COUNT * NP : XCH];
     __shared__ T hd[7 * NP];      // h_i (6), D_i per link
     __shared__ T ex[2][36];       // the recursion's exchanges
     T* xbuf = lds;
@@ -107,51 +116,72 @@ __global__ __launch_bounds__(NP) void k_abia_scan(ModelView<T> m, ChainMap cm, c
     block_sync<NP>();                              // the inverse dynamics is done with the exchange buffer
     if (active) {
 #pragma unroll
-        for (int c = 0; c < 9; ++c) rec[c * NP + li] = k.tl.r[c];
+        for (int c = 0; c < 3; ++c) {              // column c of [p] R is p x (column c of R)
+            const T rc[3] = {k.tl.r[c], k.tl.r[3 + c], k.tl.r[6 + c]};
+            T pc[3];
+            cross3(k.tl.p, rc, pc);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) rec[(9 + c) * NP + li] = k.tl.p[c];
-        rec[12 * NP + li] = k.jb.m;
+            for (int a = 0; a < 3; ++a) rec[(F_PR + 3 * a + c) * NP + li] = pc[a];
+        }
 #pragma unroll
-        for (int c = 0; c < 3; ++c) rec[(13 + c) * NP + li] = k.jb.h[c];
+        for (int c = 0; c < 9; ++c) rec[(F_R + c) * NP + li] = k.tl.r[c];
+        rec[F_M * NP + li] = k.jb.m;
 #pragma unroll
-        for (int c = 0; c < 6; ++c) rec[(16 + c) * NP + li] = k.jb.ib[c];
+        for (int c = 0; c < 3; ++c) rec[(F_H + c) * NP + li] = k.jb.h[c];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) rec[(F_I + c) * NP + li] = k.jb.ib[c];
     }
+    rec[F_ZERO * NP + li] = T(0);
     block_sync<NP>();
     if (li < 64) {
+        // Lane 6 er + ec (36 lanes) carries entry (er, ec). With X = Ad^T of the
+        // link after i and Pi its articulated inertia less the joint's share,
+        //   (Pi X^T)_{er,ec} = row er of Pi . row ec of X,
+        //   (X Pi X^T)_{er,ec} = row er of X . column ec of Pi X^T,
+        // so a lane reads two rows of X (fields fixed per lane) and forms each
+        // exchanged entry with one 6-term dot product.
         const bool ent = li < 36;
         const int er = ent ? li / 6 : 0, ec = ent ? li % 6 : 0;
-        T cprev = T(0);                            // (Ad^T Pi Ad)_{er,ec} of the link after i
+        int jfield, jsign;
+        inertia_entry_source(er, ec, &jfield, &jsign);
+        const T* jsrc = rec + jfield * NP;
+        int fe[6], fr[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            fe[c] = x_entry_field(ec, c) * NP;
+            fr[c] = x_entry_field(er, c) * NP;
+        }
+        T cprev = T(0);                            // (X Pi X^T)_{er,ec} of the link after i
 #pragma unroll 1
         for (int i = n - 1; i >= 0; --i) {
-            const T jh = inertia_entry(rec, NP, i, er, ec) + cprev;
+            // reads that do not depend on the exchange go first
+            const T jh = T(jsign) * jsrc[i] + cprev;
+            T xe[6], xr[6];                        // rows ec and er of X_i
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                xe[c] = rec[fe[c] + i];
+                xr[c] = rec[fr[c] + i];
+            }
             if (ent) ex[0][li] = jh;
             block_sync<64>();
             const T dd = ex[0][14];
             if (li < 6) hd[li * NP + i] = ex[0][6 * li + 2];
             if (li == 6) hd[6 * NP + i] = dd;
             if (i == 0) break;
-            // row er of Pi = Jh - h h^T / D, from row er and column 2 of Jh
-            const T hr = ex[0][6 * er + 2] * rcp_refined(dd);
-            T col[6], w[6];
+            // row er of Pi = Jh - h h^T / D with h = column 2 of Jh: its product
+            // with row ec of X is (row er of Jh) . xe - (h_er / D) (h . xe)
+            T a0 = T(0), a1 = T(0);
 #pragma unroll
-            for (int k = 0; k < 6; ++k) col[k] = ex[0][6 * er + k] - hr * ex[0][6 * k + 2];
-            Pose<T> tl;
-#pragma unroll
-            for (int c = 0; c < 9; ++c) tl.r[c] = rec[c * NP + i];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) tl.p[c] = rec[(9 + c) * NP + i];
-            wrench_to_parent(tl, col, w);
-            T pe = w[0];                                               // (Pi Ad)_{er,ec} = (Ad^T Pi e_er)_ec
-#pragma unroll
-            for (int c = 1; c < 6; ++c) pe = ec == c ? w[c] : pe;
+            for (int c = 0; c < 6; ++c) {
+                a0 += ex[0][6 * er + c] * xe[c];
+                a1 += ex[0][6 * c + 2] * xe[c];
+            }
+            const T pe = a0 - ex[0][6 * er + 2] * rcp_refined(dd) * a1;
             if (ent) ex[1][li] = pe;
             block_sync<64>();
+            T ce = T(0);
 #pragma unroll
-            for (int r = 0; r < 6; ++r) col[r] = ex[1][6 * r + ec];   // column ec of Pi Ad
-            wrench_to_parent(tl, col, w);
-            T ce = w[0];                                               // (Ad^T Pi Ad)_{er,ec}
-#pragma unroll
-            for (int c = 1; c < 6; ++c) ce = er == c ? w[c] : ce;
+            for (int c = 0; c < 6; ++c) ce += xr[c] * ex[1][6 * c + ec];
             cprev = ce;
         }
     }
@@ -182,8 +212,11 @@ __global__ __launch_bounds__(NP) void k_abia_scan(ModelView<T> m, ChainMap cm, c
 #pragma unroll
         for (int c = 0; c < 42; ++c) el[c] = T(0);
     }
+    // Levels with s >= n pair every link only with lanes past the tip, whose
+    // zero elements leave c as it is: they are not run (n is the same on every
+    // lane of the workgroup, so every lane takes the same barriers).
 #pragma unroll 1
-    for (int s = 1; s < NP; s <<= 1) {
+    for (int s = 1; s < NP && s < n; s <<= 1) {
         shift_down<NP>(el, ot, 42, s, xbuf);
         if (li + s < NP) affine_compose(el, ot);
     }
@@ -212,7 +245,7 @@ __global__ __launch_bounds__(NP) void k_abia_scan(ModelView<T> m, ChainMap cm, c
         for (int c = 0; c < 42; ++c) el[c] = T(0);
     }
 #pragma unroll 1
-    for (int s = 1; s < NP; s <<= 1) {
+    for (int s = 1; s < NP && s < n; s <<= 1) {    // s >= n: no partner at or after the base
         shift_up<NP>(el, ot, 42, s, xbuf);
         if (li >= s) affine_compose(el, ot);
     }
