@@ -63,6 +63,35 @@ __device__ __forceinline__ Pose<T> link_pose_at(const ModelView<T>& m, int i, in
     return joint_pose(rh, p, q);
 }
 
+// Per-link inputs of a forward sweep, loaded ahead of their use: the home
+// pose (quaternion, origin) and the joint state; with `ws`, sweep 3 also
+// takes the link's 7 workspace values.
+template <typename T, bool WS> struct LinkIn {
+    T qt[4], p[3], q, qd;
+    T w[WS ? ABIA_WS_FIELDS : 1];
+};
+template <bool NT, bool WS, typename T>
+__device__ __forceinline__ LinkIn<T, WS> link_in(const ModelView<T>& m, int i, int slot, const T* q, const T* qd,
+                                                 int64_t st, const T* wsi) {
+    LinkIn<T, WS> r;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r.qt[k] = m.template at_il<NT>(IL_QUAT + k, i, slot);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) r.p[k] = m.template at_il<NT>(IL_POS + k, i, slot);
+    r.q = q[st];
+    r.qd = WS ? T(0) : qd[st];                     // sweep 3 needs no joint rate
+    if constexpr (WS) {
+#pragma unroll
+        for (int f = 0; f < ABIA_WS_FIELDS; ++f) r.w[f] = ld_ws<NT>(wsi + (size_t)f * 64);
+    }
+    return r;
+}
+template <typename T, bool WS> __device__ __forceinline__ Pose<T> link_in_pose(const LinkIn<T, WS>& r) {
+    T rh[9];
+    quat_to_rot(r.qt, rh);
+    return joint_pose(rh, r.p, r.q);
+}
+
 // Y = X^T P X for X = Ad(T^-1) and symmetric P (full 6x6, row-major):
 // columns of X^T P are wrench_to_parent of the columns of P; then the same on the rows.
 template <typename T> __device__ __forceinline__ void congruence_to_parent(const Pose<T>& t, const T p[36], T y[36]) {
@@ -94,12 +123,20 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
     const int n = ci.n;
     auto wsp = [&](int i, int f) -> T* { return &wsb[((size_t)i * abia_fields<TREE>() + f) * 64]; };
 
-    // sweep 1
+    // sweep 1. The light forward sweeps wait on memory, not on arithmetic: each
+    // step starts the loads of the link two ahead, so two links' inputs are in
+    // flight while one is computed.
     T v[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
     T a[6] = {T(0), T(0), T(0), -m.g[0], -m.g[1], -m.g[2]};
-#pragma unroll 2   // loads of two links in flight
+    LinkIn<T, false> in0, in1;
+    if (n > 0) in0 = link_in<NT, false>(m, 0, ci.slot, q, qd, ci.state0, wsb);
+    if (n > 1) in1 = link_in<NT, false>(m, 1, ci.slot, q, qd, ci.state0 + 1, wsb);
+#pragma unroll 2
     for (int i = 0; i < n; ++i) {
         const int64_t st = ci.state0 + i;
+        const LinkIn<T, false> cur = in0;
+        in0 = in1;
+        if (i + 2 < n) in1 = link_in<NT, false>(m, i + 2, ci.slot, q, qd, st + 2, wsb);
         int32_t code = 0;
         if constexpr (TREE) {
             code = m.template tree_il<NT>(i, ci.slot);
@@ -112,8 +149,8 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
                 }
             }
         }
-        const Pose<T> tl = link_pose_at<NT>(m, i, ci.slot, q[st]);
-        const T qdi = qd[st];
+        const Pose<T> tl = link_in_pose(cur);
+        const T qdi = cur.qd;
         T t[6];
         ad_inv_apply(tl, v, t);
         t[2] += qdi;
@@ -278,11 +315,17 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
         }
     }
 
-    // sweep 3
+    // sweep 3, with the loads of the link two ahead started at each step
     T acc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-#pragma unroll 2   // loads of two links in flight
+    LinkIn<T, true> wn0, wn1;
+    if (n > 0) wn0 = link_in<NT, true>(m, 0, ci.slot, q, q, ci.state0, wsp(0, 0));
+    if (n > 1) wn1 = link_in<NT, true>(m, 1, ci.slot, q, q, ci.state0 + 1, wsp(1, 0));
+#pragma unroll 2
     for (int i = 0; i < n; ++i) {
         const int64_t st = ci.state0 + i;
+        const LinkIn<T, true> cur = wn0;
+        wn0 = wn1;
+        if (i + 2 < n) wn1 = link_in<NT, true>(m, i + 2, ci.slot, q, q, st + 2, wsp(i + 2, 0));
         int32_t code = 0;
         if constexpr (TREE) {
             code = m.template tree_il<NT>(i, ci.slot);
@@ -292,12 +335,12 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
                 for (int c = 0; c < 6; ++c) acc[c] = p < 0 ? T(0) : ld_ws<NT && ABIA_BRANCH_NT>(wsp(p, ABIA_WB + c));
             }
         }
-        const Pose<T> tl = link_pose_at<NT>(m, i, ci.slot, q[st]);
+        const Pose<T> tl = link_in_pose(cur);
         T t[6];
         ad_inv_apply(tl, acc, t);
-        T x = ld_ws<NT>(wsp(i, 6));
+        T x = cur.w[6];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) x -= ld_ws<NT>(wsp(i, c)) * t[c];
+        for (int c = 0; c < 6; ++c) x -= cur.w[c] * t[c];
         t[2] += x;
 #pragma unroll
         for (int c = 0; c < 6; ++c) acc[c] = t[c];
