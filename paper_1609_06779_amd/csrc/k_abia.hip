@@ -92,21 +92,51 @@ template <typename T, bool WS> __device__ __forceinline__ Pose<T> link_in_pose(c
     return joint_pose(rh, r.p, r.q);
 }
 
-// Y = X^T P X for X = Ad(T^-1) and symmetric P (full 6x6, row-major):
-// columns of X^T P are wrench_to_parent of the columns of P; then the same on the rows.
+// wrench_to_parent for a wrench whose component 2 (the joint axis of the
+// child's canonical frame) is zero: y = X f with X = [[R, [p] R], [0, R]].
+template <typename T> __device__ __forceinline__ void wrench_to_parent_z2(const Pose<T>& t, const T f[6], T y[6]) {
+    T rn[3], rf[3], pc[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) rn[i] = t.r[3 * i] * f[0] + t.r[3 * i + 1] * f[1];
+    matvec3(t.r, f + 3, rf);
+    cross3(t.p, rf, pc);
+    y[0] = rn[0] + pc[0]; y[1] = rn[1] + pc[1]; y[2] = rn[2] + pc[2];
+    y[3] = rf[0]; y[4] = rf[1]; y[5] = rf[2];
+}
+
+// Y = X P X^T (X = Ad(T^-1)^T, moving the child's terms to the parent's
+// frame) for a symmetric P whose row and column 2 are zero: the articulated
+// inertia less the joint's share, P = Jh - h h^T / D with h = Jh e3, D = h_2,
+// has P e3 = 0. Columns of X P are X applied to the columns of P (column 2 is
+// zero), then row r of Y is X applied to row r of X P. Only the lower
+// triangle of Y is formed (the rest of each row is left to dead-code
+// elimination) and mirrored.
 template <typename T> __device__ __forceinline__ void congruence_to_parent(const Pose<T>& t, const T p[36], T y[36]) {
     T w[36];
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
+        if (c == 2) {
+#pragma unroll
+            for (int r = 0; r < 6; ++r) w[6 * r + 2] = T(0);
+            continue;
+        }
         T col[6], out[6];
 #pragma unroll
-        for (int r = 0; r < 6; ++r) col[r] = p[6 * r + c];
-        wrench_to_parent(t, col, out);
+        for (int r = 0; r < 6; ++r) col[r] = r == 2 ? T(0) : p[6 * r + c];
+        wrench_to_parent_z2(t, col, out);
 #pragma unroll
         for (int r = 0; r < 6; ++r) w[6 * r + c] = out[r];
     }
 #pragma unroll
-    for (int r = 0; r < 6; ++r) wrench_to_parent(t, w + 6 * r, y + 6 * r);
+    for (int r = 0; r < 6; ++r) {
+        T out[6];
+        wrench_to_parent_z2(t, w + 6 * r, out);
+#pragma unroll
+        for (int c = 0; c <= r; ++c) {
+            y[6 * r + c] = out[c];
+            y[6 * c + r] = out[c];
+        }
+    }
 }
 
 // One chain (or tree) on one lane. wsb: this lane's workspace column, field f
@@ -189,11 +219,28 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
     Pose<T> tn = pose_identity<T>();                   // T_{i,i+1}
     T qdn = T(0);                                      // chains: qd_{i+1}
     bool carry = false;                                // trees: registers hold link i+1's terms for link i
-#pragma unroll 2   // loads of two links in flight
+    // each step starts the loads of the link before it (the step's arithmetic
+    // outlasts a memory round trip)
+    Inertia<T> jn;
+    LinkIn<T, false> pn;
+    T taun = T(0);
+    if (n > 0) {
+        jn = m.template inertia_il<NT>(n - 1, ci.slot);
+        pn = link_in<NT, false>(m, n - 1, ci.slot, q, qd, ci.state0 + n - 1, wsb);
+        taun = tau[ci.state0 + n - 1];
+    }
+#pragma unroll 2
     for (int i = n - 1; i >= 0; --i) {
         const int64_t st = ci.state0 + i;
         T f[6], fp[6], pp[6], jh[36];
-        const Inertia<T> ji = m.template inertia_il<NT>(i, ci.slot);
+        const Inertia<T> ji = jn;
+        const LinkIn<T, false> pcur = pn;
+        const T taui = taun;
+        if (i > 0) {
+            jn = m.template inertia_il<NT>(i - 1, ci.slot);
+            pn = link_in<NT, false>(m, i - 1, ci.slot, q, qd, st - 1, wsb);
+            taun = tau[st - 1];
+        }
         if constexpr (TREE) {
 #pragma unroll
             for (int c = 0; c < 6; ++c) f[c] = ld_ws<NT>(wsp(i, c));
@@ -258,26 +305,36 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
                     }
             }
         }
-        const T td = tau[st] - f[2];
+        const T td = taui - f[2];
         const T dinv = rcp_refined(jh[14]);
         const T u = td - pp[2];
         T h[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) h[c] = jh[6 * c + 2];
+        T hd[6];                                        // h / D
 #pragma unroll
-        for (int c = 0; c < 6; ++c) st_ws<NT>(h[c] * dinv, wsp(i, c));
+        for (int c = 0; c < 6; ++c) {
+            hd[c] = h[c] * dinv;
+            st_ws<NT>(hd[c], wsp(i, c));
+        }
         st_ws<NT>(u * dinv, wsp(i, 6));
+        // Pi = Jh - h h^T / D, symmetric, with row and column 2 exactly zero
+        // (they are zero in exact arithmetic: Pi e3 = h - h D / D)
 #pragma unroll
         for (int r = 0; r < 6; ++r)
 #pragma unroll
-            for (int c = 0; c < 6; ++c) pi[6 * r + c] = jh[6 * r + c] - h[r] * h[c] * dinv;
+            for (int c = 0; c <= r; ++c) {
+                const T x = (r == 2 || c == 2) ? T(0) : jh[6 * r + c] - h[r] * hd[c];
+                pi[6 * r + c] = x;
+                pi[6 * c + r] = x;
+            }
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-            pc[c] = pp[c] + h[c] * u * dinv;
+            pc[c] = pp[c] + hd[c] * u;
             fc[c] = f[c];
         }
-        tn = link_pose_at<NT>(m, i, ci.slot, q[st]);
-        if constexpr (!TREE) qdn = qd[st];
+        tn = link_in_pose(pcur);
+        if constexpr (!TREE) qdn = pcur.qd;
         if constexpr (TREE) {
             // Move the terms into the parent's frame here, once per link, on
             // every lane: the parent takes them from registers (chain step) or

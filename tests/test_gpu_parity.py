@@ -108,7 +108,7 @@ FP32_OVER_CAP = {
     ("cfa", 24): 2.5e-3, ("cfa", 32): 3.9e-3, ("cfa", 33): 2.2e-3, ("cfa", 50): 3.5e-3, ("cfa", 64): 1.0e-2,
     ("cfa", 100): 3.3e-2, ("cfa", 128): 9.8e-3, ("cfa", 200): 9.7e-2, ("cfa", 256): 8.1e-2,
     ("jsiia", 100): 1.2e-3, ("jsiia", 128): 2.0e-3, ("jsiia", 200): 3.6e-3, ("jsiia", 256): 1.6e-2,
-    ("abia_scan", 200): 1.7e-3, ("abia_scan", 256): 2.6e-3,
+    ("abia_scan", 200): 1.7e-3, ("abia_scan", 256): 2.6e-3, ("abia", 256): 1.2e-3,
 }
 
 
