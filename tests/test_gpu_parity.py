@@ -479,3 +479,20 @@ def test_non_finite_inputs_stay_in_their_chain(fdm, dev, algo):
             assert not np.all(np.isfinite(dirty[sl])), b
         else:
             np.testing.assert_array_equal(dirty[sl], clean[sl])
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("dtype,scale", [("f64", 1e2), ("f64", 1e5), ("f64", 1e7), ("f32", 50.0), ("f32", 1e5)])
+def test_large_joint_angles(fdm, dev, algo, dtype, scale):
+    """Joint angles far from zero (up to 1e7 rad, where the sine and cosine
+    need a long argument reduction): every chain stays within the cap of the
+    oracle, which evaluates the C library's sin and cos at the same angles."""
+    lengths = np.full(29, 12, np.int32)
+    rb, q, qd, tau = _prep(lengths, dtype, cfg=5)
+    rng = np.random.default_rng(1609)
+    q = q + scale * rng.uniform(-1.0, 1.0, q.shape)
+    if dtype == "f32":
+        q = q.astype(np.float32).astype(np.float64)
+    ref = oracle.fd(rb, q, qd, tau)
+    got = _forward(fdm, dev, rb, q, qd, tau, dtype, algo)
+    _check(got, ref, rb.offsets, dtype, f"{algo} {dtype} |q| ~ {scale:g}", algo)
