@@ -35,7 +35,7 @@ def _alloc_on(stream):
 def _dev_tensor(x, dtype, device, name):
     if not isinstance(x, torch.Tensor):
         raise TypeError(f"{name} must be a torch tensor on the GPU")
-    if x.device.type != "cuda":
+    if not x.is_cuda:
         raise ValueError(f"{name} must live on the GPU (got {x.device})")
     if x.dtype != dtype:
         raise TypeError(f"{name} must be {dtype} (got {x.dtype})")
