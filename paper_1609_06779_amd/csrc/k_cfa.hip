@@ -64,7 +64,10 @@ __global__ __launch_bounds__(Geo<NP>::threads, (PROJ && sizeof(T) == 8) ? 1 : 2)
     // (taken from lane li - 1) moved into frame i.
     T ip[10], iq[10];
     if (active) {
-        m.inertia_inv_params(link, ip);
+        // FP64: from the inertia the inverse dynamics read (ten fewer loads per
+        // link); FP32 reads the parameters formed from the FP64 input at upload
+        if constexpr (sizeof(T) == 8) inv_params_of(k.jb, ip);
+        else m.inertia_inv_params(link, ip);
     } else {
 #pragma unroll
         for (int c = 0; c < 10; ++c) ip[c] = (c < 3 || c == 9) ? T(1) : T(0);
