@@ -302,7 +302,8 @@ ACCURACY_CAP = {"f64": 1e-9, "f32": 1e-3}
 
 
 def cpu_baseline_accuracy(ns=(16, 32, 64, 128), batch: int = 65536, sample: int = 8192, eta_sample: int = 512):
-    """Part of the CPU-baseline leg: the oracle's reference q-ddot on a sample of
+    """Part of the CPU-baseline leg: the oracle's reference q-ddot (evaluated in
+    long double, so that its own rounding is not counted) on a sample of
     each uniform 65536-chain workload (n = 16..128; the first `sample` chains),
     FP64 and FP32 (robots and states rounded to FP32 first, the oracle in FP64 on
     the rounded values), against the library's q-ddot for the whole batch.
@@ -332,7 +333,7 @@ def cpu_baseline_accuracy(ns=(16, 32, 64, 128), batch: int = 65536, sample: int 
                 q, qd, tau = (a.astype(np.float32).astype(np.float64) for a in (q, qd, tau))
             sub = rb.take(np.arange(sample))
             sl = slice(0, sample * n)
-            ref = oracle.fd(sub, q[sl], qd[sl], tau[sl], threads=0)
+            ref = oracle.fd_exact(sub, q[sl], qd[sl], tau[sl], threads=0)   # the oracle in long double
             es = slice(0, eta_sample * n)
             esub = rb.take(np.arange(eta_sample))
             ms = oracle.crba(esub, q[es], threads=0)

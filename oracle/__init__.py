@@ -23,7 +23,8 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRCS = [os.path.join(_HERE, f) for f in ("fd_oracle.c", "fd_oracle_cx.c", "fd_core.inc", "fd_chain.h")]
+_SRCS = [os.path.join(_HERE, f) for f in ("fd_oracle.c", "fd_oracle_cx.c", "fd_oracle_ld.c", "fd_core.inc",
+                                          "fd_chain.h")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -38,7 +39,7 @@ def build(force: bool = False) -> str:
     if force or stale:
         tmp = _LIB + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
-               "-std=c11", "-Wall", "-Wno-unused-function", "-o", tmp, _SRCS[0], _SRCS[1], "-lm"]
+               "-std=c11", "-Wall", "-Wno-unused-function", "-o", tmp, _SRCS[0], _SRCS[1], _SRCS[2], "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -53,6 +54,8 @@ def _load():
         lib.oracle_rnea_batch.argtypes = [ctypes.c_int, _i64, _i64] + model + [_d, _d, _d, ctypes.c_int, _d, ctypes.c_int]
         lib.oracle_crba_batch.argtypes = [ctypes.c_int, _i64, _i64] + model + [_d, _i64, _d, ctypes.c_int]
         lib.oracle_fd_batch.argtypes = [ctypes.c_int, _i64, _i64] + model + [_d, _d, _d, _d, ctypes.c_int]
+        lib.oracle_fd_ld_batch.argtypes = [ctypes.c_int, _i64, _i64] + model + [_d, _d, _d, _d, ctypes.c_int]
+        lib.oracle_fd_ld_batch.restype = ctypes.c_int
         lib.oracle_fk_batch.argtypes = [ctypes.c_int, _i64, _i64] + model + [_d, _d, _d, ctypes.c_int]
         lib.oracle_energy_batch.argtypes = [ctypes.c_int, _i64, _i64] + model + [_d, _d, _d, _d, ctypes.c_int]
         lib.oracle_link_rotation.argtypes = [_d, _d, ctypes.c_double, _d]
@@ -125,6 +128,22 @@ def fd(robots, q, qd, tau, offsets=None, model_start=None, threads: int = 0):
     ms = None if model_start is None else _c(model_start, np.int64)
     lib.oracle_fd_batch(len(off) - 1, _p(off, np.int64), None if ms is None else _p(ms, np.int64),
                         *m.args(), _p(q), _p(qd), _p(tau), _p(out), int(threads))
+    return out
+
+
+def fd_exact(robots, q, qd, tau, offsets=None, model_start=None, threads: int = 0):
+    """``fd`` evaluated in long double (64-bit significand) from the same double
+    inputs, rounded to double at the end: the forward-dynamics value to within
+    about one unit in the last place of double wherever cond(M) stays below
+    2^11, so a result compared with it is charged with its own error only."""
+    lib = _load()
+    off = _offsets(robots, offsets)
+    m = _Model(robots)
+    q, qd, tau = _c(q), _c(qd), _c(tau)
+    out = np.empty_like(q)
+    ms = None if model_start is None else _c(model_start, np.int64)
+    lib.oracle_fd_ld_batch(len(off) - 1, _p(off, np.int64), None if ms is None else _p(ms, np.int64),
+                           *m.args(), _p(q), _p(qd), _p(tau), _p(out), int(threads))
     return out
 
 

@@ -41,7 +41,7 @@ def test_persistent_equals_plain_and_oracle(dev, dtype):
     pick = np.array([0, 1, 2, 3, 100, 1000, 3000])
     sub = rb.take(pick)
     idx = np.concatenate([np.arange(off[b], off[b + 1]) for b in pick])
-    ref = oracle.fd(sub, q[idx], qd[idx], tau[idx])
+    ref = oracle.fd_exact(sub, q[idx], qd[idx], tau[idx])
     err = oracle.relative_error(plain.cpu().double().numpy()[idx], ref, sub.offsets)
     assert np.all(err <= CAP[dtype]), err
 
@@ -107,7 +107,7 @@ def test_full_size_ragged_batch_sampled(dev):
                                      rng.choice(len(lengths), 300, replace=False)]))
     sub = rb.take(pick)
     idx = np.concatenate([np.arange(off[b], off[b + 1]) for b in pick])
-    ref = oracle.fd(sub, q[idx], qd[idx], tau[idx])
+    ref = oracle.fd_exact(sub, q[idx], qd[idx], tau[idx])
     err = oracle.relative_error(out[idx], ref, sub.offsets)
     print(f"ragged 100000 sampled {len(pick)}: worst {err.max():.2e}", flush=True)
     assert np.all(err <= CAP["f64"]), err.max()

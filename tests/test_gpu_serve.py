@@ -38,7 +38,7 @@ def test_served_results_equal_alone_and_oracle(dev):
                               offsets=offsets).cpu()
         assert torch.equal(alone, r.out), r.rid
         per_chain = robots.take(np.full(r.chains, r.robot))
-        ref = oracle.fd(per_chain, r.q.numpy(), r.qd.numpy(), r.tau.numpy())
+        ref = oracle.fd_exact(per_chain, r.q.numpy(), r.qd.numpy(), r.tau.numpy())
         err = oracle.relative_error(r.out.numpy(), ref, per_chain.offsets)
         assert np.all(err <= CAP["f64"]), (r.rid, err.max())
 
@@ -110,7 +110,7 @@ def test_rounds_with_several_algorithms_match_the_oracle(dev, mode):
         sub = robots.take(np.full(len(pick), r.robot))
         idx = np.concatenate([np.arange(r.n * b, r.n * b + r.n) for b in pick])
         q, qd, tau = (x.numpy()[idx] for x in (r.q, r.qd, r.tau))
-        ref = oracle.fd(sub, q, qd, tau)
+        ref = oracle.fd_exact(sub, q, qd, tau)
         err = oracle.relative_error(r.out.numpy()[idx], ref, sub.offsets)
         assert np.all(err <= CAP["f64"]), (r.rid, r.algo, r.n, err.max())
 
@@ -135,5 +135,5 @@ def test_serving_branched_robots_runs_the_tree_kernels(dev):
         sub = robots.take(np.full(len(pick), r.robot))
         idx = np.concatenate([np.arange(r.n * b, r.n * b + r.n) for b in pick])
         q, qd, tau = (x.numpy()[idx] for x in (r.q, r.qd, r.tau))
-        err = oracle.relative_error(r.out.numpy()[idx], oracle.fd(sub, q, qd, tau), sub.offsets)
+        err = oracle.relative_error(r.out.numpy()[idx], oracle.fd_exact(sub, q, qd, tau), sub.offsets)
         assert np.all(err <= CAP["f64"]), (r.rid, err.max())

@@ -49,7 +49,7 @@ def _t(a, dtype, dev):
 
 
 def _check(got, rb, q, qd, tau, off, dtype, what, backward=True):
-    ref = oracle.fd(rb, q, qd, tau, offsets=off)
+    ref = oracle.fd_exact(rb, q, qd, tau, offsets=off)
     err = oracle.relative_error(got, ref, off)
     ms = oracle.crba(rb, q, offsets=off)
     if len(err):
