@@ -938,6 +938,8 @@ def main():
     ap.add_argument("--only-step", action="store_true",
                     help="time the step alone: no legs and no CPU baseline (the profiled command)")
     ap.add_argument("--only-trees", action="store_true", help="run the branched-robot leg alone")
+    ap.add_argument("--only-adjoint", action="store_true",
+                    help="run the reverse-mode leg alone (VJPs and the differentiation workload)")
     ap.add_argument("--only-ragged", action="store_true",
                     help="run the ragged-batch leg alone (per_algo: the persistent launch's event time)")
     ap.add_argument("--tree-workloads", default=",".join(TREE_WORKLOADS))
@@ -992,6 +994,10 @@ def main():
         rg = ragged_leg(args.dtype)
         print(json.dumps({"ragged": rg, "dtype": args.dtype,
                           "per_algo": {"abia_persistent": {"ms_per_launch": rg["persistent_ms"]}}}), flush=True)
+        return
+    if args.only_adjoint:
+        print(f"[bench] reverse-mode leg alone: {args.dtype}", file=sys.stderr, flush=True)
+        print(json.dumps({"adjoint": adjoint_leg(args.dtype), "dtype": args.dtype}), flush=True)
         return
     if args.only_trees:
         print(f"[bench] tree leg alone: {tree_keys} {args.dtype}", file=sys.stderr, flush=True)

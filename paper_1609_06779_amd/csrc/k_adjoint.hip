@@ -214,10 +214,39 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
         T fb[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
         T v[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
         T a[6] = {T(0), T(0), T(0), -m.g[0], -m.g[1], -m.g[2]};
+        // each step starts the loads of the link after it: the link's own inputs
+        // (pose, joint state, qdd, lambda, h / D, inertia) do not depend on the
+        // recursion, and the loads would otherwise wait a memory round trip per link
+        struct In {
+            T qt[4], p[3], q, qd, qdd, lam, hd[6];
+            Inertia<T> j;
+        };
+        auto load = [&](int i) {
+            In r;
+            const int64_t st = ci.state0 + i;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) r.qt[k] = m.template at_il<NT>(IL_QUAT + k, i, sl);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) r.p[k] = m.template at_il<NT>(IL_POS + k, i, sl);
+            r.q = q[st];
+            r.qd = qd[st];
+            r.qdd = qdd ? qdd[st] : ldw(i, VJP_A);   // read before this sweep overwrites it
+            r.lam = ldw(i, VJP_UD);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) r.hd[c] = lam_in ? T(0) : ldw(i, VJP_HD + c);
+            r.j = m.template inertia_il<NT>(i, sl);
+            return r;
+        };
+        // (serial chains; trees load each link's inputs at its own step: there the
+        // extra registers cost more than the overlap gains)
+        In nx;
+        if (!TREE && n > 0) nx = load(0);
         for (int i = 0; i < n; ++i) {
             const int64_t st = ci.state0 + i;
             const int32_t code = code_of(i);
-            const T qddi = qdd ? qdd[st] : ldw(i, VJP_A);
+            const In cur = TREE ? load(i) : nx;
+            if (!TREE && i + 1 < n) nx = load(i + 1);
+            const T qddi = cur.qdd;
             if constexpr (TREE) {
                 if (!(code & TREE_CHAIN)) {            // the parent's terms, not link i-1's
                     const int p = tree_parent(code);
@@ -230,13 +259,15 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
                     }
                 }
             }
-            const Pose<T> tl = pose_il<NT>(m, i, sl, q[st]);
+            T rh[9];
+            quat_to_rot(cur.qt, rh);
+            const Pose<T> tl = joint_pose(rh, cur.p, cur.q);
             T t[6];
-            T lam = ldw(i, VJP_UD);
+            T lam = cur.lam;
             if (!lam_in) {                             // the a recursion of the M^-1 g solve
                 ad_inv_apply(tl, acc, t);
 #pragma unroll
-                for (int c = 0; c < 6; ++c) lam -= ldw(i, VJP_HD + c) * t[c];
+                for (int c = 0; c < 6; ++c) lam -= cur.hd[c] * t[c];
                 t[2] += lam;
 #pragma unroll
                 for (int c = 0; c < 6; ++c) acc[c] = t[c];
@@ -256,7 +287,7 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
                 }
             }
 
-            const T qdi = qd[st];
+            const T qdi = cur.qd;
             ad_inv_apply(tl, v, t);
             t[2] += qdi;
 #pragma unroll
@@ -268,7 +299,7 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
 #pragma unroll
             for (int c = 0; c < 6; ++c) a[c] = t[c];
             T f[6];
-            link_force(m.template inertia_il<NT>(i, sl), v, a, f);
+            link_force(cur.j, v, a, f);
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
                 stw(i, VJP_V + c, v[c]);
@@ -286,17 +317,46 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
         T vb[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
         Pose<T> tn = pose_identity<T>();
         bool carry = false;
+        // each step of a serial chain starts the loads of the link before it
+        // (trees load each link's inputs at its own step)
+        struct In {
+            Inertia<T> j;
+            T f[6], fb[6], v[6], a[6], qt[4], p[3], q, qd;
+        };
+        auto load = [&](int i) {
+            In r;
+            const int64_t st = ci.state0 + i;
+            r.j = m.template inertia_il<NT>(i, sl);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                r.f[c] = ldw(i, VJP_F + c);
+                r.fb[c] = ldw(i, VJP_FB + c);
+                r.v[c] = ldw(i, VJP_V + c);
+                r.a[c] = ldw(i, VJP_A + c);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) r.qt[k] = m.template at_il<NT>(IL_QUAT + k, i, sl);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) r.p[k] = m.template at_il<NT>(IL_POS + k, i, sl);
+            r.q = q[st];
+            r.qd = qd[st];
+            return r;
+        };
+        In nx;
+        if (!TREE && n > 0) nx = load(n - 1);
         for (int i = n - 1; i >= 0; --i) {
             const int64_t st = ci.state0 + i;
             const int32_t code = code_of(i);
-            const Inertia<T> j = m.template inertia_il<NT>(i, sl);
+            const In cur = TREE ? load(i) : nx;
+            if (!TREE && i > 0) nx = load(i - 1);
+            const Inertia<T> j = cur.j;
             T f[6], fb[6], v[6], a[6], na[6], nv[6];
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
-                f[c] = ldw(i, VJP_F + c);
-                fb[c] = ldw(i, VJP_FB + c);
-                v[c] = ldw(i, VJP_V + c);
-                a[c] = ldw(i, VJP_A + c);
+                f[c] = cur.f[c];
+                fb[c] = cur.fb[c];
+                v[c] = cur.v[c];
+                a[c] = cur.a[c];
             }
             if (TREE && carry) {                       // terms already in this link's frame
 #pragma unroll
@@ -325,14 +385,18 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
                     }
                 }
             }
-            tn = pose_il<NT>(m, i, sl, q[st]);             // A_i
+            {
+                T rh[9];
+                quat_to_rot(cur.qt, rh);
+                tn = joint_pose(rh, cur.p, cur.q);         // A_i
+            }
             // force term of q_bar: -(ad_S A_i Fb_p(i)) . F_i
             const int p = TREE ? tree_parent(code) : i - 1;
             T gq_id = T(0);
             if (p >= 0) {
                 T fbp[6], t[6], z[6];
 #pragma unroll
-                for (int c = 0; c < 6; ++c) fbp[c] = ldw(p, VJP_FB + c);
+                for (int c = 0; c < 6; ++c) fbp[c] = TREE ? ldw(p, VJP_FB + c) : nx.fb[c];   // chains: p = i - 1
                 ad_inv_apply(tn, fbp, t);
                 ad_z(t, z);
 #pragma unroll
@@ -347,7 +411,7 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
             ad_twist_T(fb, jv, t1);
             ad_twist(v, fb, avf);
             inertia_apply(j, avf, t2);
-            const T qdi = qd[st];
+            const T qdi = cur.qd;
             // -ad_{S qd}^T ab = (z qd x ab_w; z qd x ab_v)
             const T sa[6] = {-qdi * ab[1], qdi * ab[0], T(0), -qdi * ab[4], qdi * ab[3], T(0)};
 #pragma unroll
