@@ -56,13 +56,7 @@ size_t abia_workspace_elems(int batch, int nmax, bool tree) {
 
 // Model reads go through the robot-interleaved copy: lanes hold consecutive
 // chains, so field f of link i is one contiguous read across the wavefront.
-template <bool NT, typename T>
-__device__ __forceinline__ Pose<T> link_pose_at(const ModelView<T>& m, int i, int slot, T q) {
-    T rh[9], p[3];
-    m.template home_il<NT>(i, slot, rh, p);
-    return joint_pose(rh, p, q);
-}
-
+//
 // Per-link inputs of a forward sweep, loaded ahead of their use: the home
 // pose (quaternion, origin) and the joint state; with `ws`, sweep 3 also
 // takes the link's 7 workspace values.

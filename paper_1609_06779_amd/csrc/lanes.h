@@ -193,11 +193,6 @@ template <typename T> struct ModelView {
         for (int k = 0; k < 3; ++k) p[6 + k] = at(MF_COM + k, l);
         p[9] = at(MF_MINV, l);
     }
-    __device__ __forceinline__ void inertia_inv(int64_t l, T m[36]) const {
-        T p[10];
-        inertia_inv_params(l, p);
-        inv_inertia6(p, m);
-    }
 };
 
 // The inverse-inertia parameters (Ic^-1 as xx yy zz xy xz yz, c, 1/m; see
