@@ -8,8 +8,12 @@
 //   E_i = U_i D_{i+s}^-1,  K_i = U_{i-s}^T D_{i-s}^-1  (SPD solves, not inverses)
 //   D_i <- D_i - E_i U_i^T - K_i U_{i-s}
 //   R_i <- R_i - E_i R_{i+s} - K_i R_{i-s}
-//   U_i <- -E_i U_{i+s}             (zero once i + 2s is past the last row)
+//   U_i <- -E_i U_{i+s}
 // After ceil(log2 n) levels the system is block diagonal and x_i = D_i^-1 R_i.
+// A U_i whose partner row i + s is past the last row is the zero block; the
+// code never clears it, because no value that reaches the solution reads it:
+// its row's K-part goes to row i + s, which does not exist, and its W only
+// forms the next level's U_{i-s}, whose partner i + s is past the end as well.
 // Every D is factored once per level, by its own row, which publishes through
 // LDS what its neighbours need (two phases per level, see oee_solve_rows).
 #pragma once
@@ -160,9 +164,8 @@ __device__ bool oee_solve_rows(T d[K * K], T u[K * K], T r[K], int i, int n, boo
                 for (int c = 0; c < K; ++c) sv[(b * K + c) * NP + i] = w[b][c];
         }
         block_sync<(NP < 64 ? 64 : NP)>();
-        if (has_e) {
+        if (has_e) {                               // rows without a partner keep a U nothing reads
             const int j = i + s;
-            const bool keep_u = i + 2 * s < n;
 #pragma unroll
             for (int b = 0; b < K; ++b) {
                 T wb[K];                           // W_{i+s}, column b of U_{i+s}
@@ -170,15 +173,12 @@ __device__ bool oee_solve_rows(T d[K * K], T u[K * K], T r[K], int i, int n, boo
                 for (int c = 0; c < K; ++c) wb[c] = sv[(b * K + c) * NP + j];
 #pragma unroll
                 for (int a = 0; a < K; ++a) {
-                    T v = T(0);
+                    T v = T(0);                    // accumulates -(T^T W), the sign inside each product
 #pragma unroll
-                    for (int c = 0; c < K; ++c) v += t[a][c] * wb[c];
-                    u[a * K + b] = keep_u ? -v : T(0);
+                    for (int c = 0; c < K; ++c) v -= t[a][c] * wb[c];
+                    u[a * K + b] = v;
                 }
             }
-        } else if (active) {
-#pragma unroll
-            for (int c = 0; c < K * K; ++c) u[c] = T(0);
         }
         block_sync<(NP < 64 ? 64 : NP)>();        // phase B reads done before the next level's writes
     }
