@@ -37,8 +37,10 @@
 
 namespace fdk {
 
-constexpr int ABIA_WS_FIELDS = 7;   // sweep 2: h / D (6), u / D (1); trees: sweep 1 f (6) first
-// Trees add a branch-point record after those 7 fields: sweep 1 velocity (6)
+// sweep 2: h / D without its joint-axis entry, which is h_3 / D = 1 (D = h_3),
+// so 5 values, then u / D; trees: sweep 1 f (6) first
+constexpr int ABIA_WS_FIELDS = 6;
+// Trees add a branch-point record after those 6 fields: sweep 1 velocity (6)
 // and bias acceleration (6); sweep 2 accumulator of the children's F (6), p (6)
 // and Jh - h h^T / D (21, upper triangle by rows); sweep 3 acceleration (6).
 constexpr int ABIA_WB = ABIA_WS_FIELDS;
@@ -59,7 +61,7 @@ size_t abia_workspace_elems(int batch, int nmax, bool tree) {
 //
 // Per-link inputs of a forward sweep, loaded ahead of their use: the home
 // pose (quaternion, origin) and the joint state; with `ws`, sweep 3 also
-// takes the link's 7 workspace values.
+// takes the link's 6 workspace values.
 template <typename T, bool WS> struct LinkIn {
     T qt[4], p[3], q, qd;
     T w[WS ? ABIA_WS_FIELDS : 1];
@@ -309,9 +311,9 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
             hd[c] = h[c] * dinv;
-            st_ws<NT>(hd[c], wsp(i, c));
+            if (c != 2) st_ws<NT>(hd[c], wsp(i, c < 2 ? c : c - 1));
         }
-        st_ws<NT>(u * dinv, wsp(i, 6));
+        st_ws<NT>(u * dinv, wsp(i, 5));
         // Pi = Jh - h h^T / D, symmetric, with row and column 2 exactly zero
         // (they are zero in exact arithmetic: Pi e3 = h - h D / D)
 #pragma unroll
@@ -389,10 +391,13 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
         const Pose<T> tl = link_in_pose(cur);
         T t[6];
         ad_inv_apply(tl, acc, t);
-        T x = cur.w[6];
+        // qdd = u/D - (h/D)^T t with (h/D)_3 = 1: the new axis component of the
+        // acceleration, t_3 + qdd, is s below, and qdd = s - t_3
+        T s = cur.w[5];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) x -= cur.w[c] * t[c];
-        t[2] += x;
+        for (int c = 0; c < 5; ++c) s -= cur.w[c] * t[c < 2 ? c : c + 1];
+        const T x = s - t[2];
+        t[2] = s;
 #pragma unroll
         for (int c = 0; c < 6; ++c) acc[c] = t[c];
         o.put(qdd, st, b, i, x);                      // qdd may be null when the reverse mode takes it in aux
