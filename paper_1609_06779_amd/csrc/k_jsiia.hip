@@ -102,15 +102,21 @@ __global__ __launch_bounds__(64) void k_jsiia_gj(ModelView<T> m, ChainMap cm, co
 // Unknowns of one row block of L^T x = z (rows t = T .. 0 of the block, last
 // first), column by column: lane c of a row group holds z_c, reduced by
 // (1 / d_c) m_tc x_t as each later unknown x_t is found; once every later
-// unknown is in, z_t is x_t, broadcast from lane t to its group. wrow: the
-// block's published rows (row t at wrow[t * ws], its column c at + c); yout
-// takes x_t on the lanes of row group t.
+// unknown is in, z_t is x_t. Every row group runs this solve on the same
+// values, so lane t of the wavefront (group 0, column t) holds x_t for all of
+// them, and one readlane hands it to every lane without an LDS round trip.
+// wrow: the block's published rows (row t at wrow[t * ws], its column c at
+// + c); yout takes x_t on the lanes of row group t.
 template <int G, int T, typename R>
 __device__ __forceinline__ void block_back_solve(R& zc, R& yout, const R* wrow, int ws, int c, int r, R rbc) {
-    const R xt = xlane::group_bcast<G, T>(zc);
+    static_assert(T < G && G <= 64, "column t of a group is wavefront lane t");
+    R w = R(0);
+    if constexpr (T > 0) w = wrow[T * ws + c];   // read before x_t is known; used where c < T
+    const R xt = dpp::read<T>(zc);
     if (r == T) yout = xt;
     if constexpr (T > 0) {
-        if (c < T) zc -= rbc * wrow[T * ws + c] * xt;
+        const R z = zc - rbc * w * xt;
+        zc = c < T ? z : zc;
         block_back_solve<G, T - 1>(zc, yout, wrow, ws, c, r, rbc);
     }
 }

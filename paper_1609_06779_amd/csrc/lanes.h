@@ -581,21 +581,6 @@ __device__ __forceinline__ float bperm(float v, int addr) {
 }
 __device__ __forceinline__ int bperm(int v, int addr) { return __builtin_amdgcn_ds_bpermute(addr, v); }
 
-// Lane T of every group of G consecutive lanes (G = 8 or 16) to all lanes of
-// the group, by ds_swizzle in bit mode: within each 32-lane half, lane l reads
-// lane (l & and_mask) | T, and_mask keeping the group bits.
-template <int G, int T> __device__ __forceinline__ double group_bcast(double v) {
-    static_assert((G == 8 || G == 16 || G == 32) && T >= 0 && T < G, "a lane of a group of 8, 16 or 32");
-    constexpr int pattern = (32 - G) | (T << 5);
-    const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), pattern);
-    const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), pattern);
-    return __hiloint2double(hi, lo);
-}
-template <int G, int T> __device__ __forceinline__ float group_bcast(float v) {
-    static_assert((G == 8 || G == 16 || G == 32) && T >= 0 && T < G, "a lane of a group of 8, 16 or 32");
-    constexpr int pattern = (32 - G) | (T << 5);
-    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), pattern));
-}
 }  // namespace xlane
 
 template <int NP, int W, typename T>
