@@ -213,15 +213,25 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> 
                 const T v = mb[a * (a + 1) / 2 + jb];
                 cj[r + G * a] = (a > jb || r > jr) ? v : T(0);
             }
-            if (r == jr) {
+            if (TH > 64 && r == jr) {
                 cj[NP] = y[jb];
                 cj[NP + 1] = mb[jb * (jb + 1) / 2 + jb];
             }
         }
+        // The pivot m_jj and b_j are in lane (jr, jr). In one wavefront a
+        // readlane takes them there, so the reciprocal overlaps the column's
+        // LDS round trip; larger grids read them from LDS with the column.
+        T piv, yj;
+        if constexpr (TH == 64) {
+            piv = dpp::read_at(mb[jb * (jb + 1) / 2 + jb], (G + 1) * jr);
+            yj = dpp::read_at(y[jb], (G + 1) * jr);
+        }
         block_sync<TH>();
-        const T piv = cj[NP + 1];
+        if constexpr (TH > 64) {
+            piv = cj[NP + 1];
+            yj = cj[NP];
+        }
         const T rp = rcp_refined(piv);
-        const T yj = cj[NP];
         if (r == jr) {
             if constexpr (LEAN) {
                 if (c == jr) rdbuf[G * jb + jr] = rp;

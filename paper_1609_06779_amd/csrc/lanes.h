@@ -338,6 +338,16 @@ template <int LANE> __device__ __forceinline__ double read(double v) {
 template <int LANE> __device__ __forceinline__ float read(float v) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), LANE));
 }
+// value of wavefront lane `lane`, a lane index the same in every lane of the
+// wavefront (a loop counter, say), in every lane
+__device__ __forceinline__ double read_at(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float read_at(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
 // Lane l ^ 16 (the same place in the other 16-lane row of its 32-lane half),
 // by ds_swizzle in bit mode (and mask 0x1f, xor mask 0x10).
 __device__ __forceinline__ double swizzle_xor16(double v) {
