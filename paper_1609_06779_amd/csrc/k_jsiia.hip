@@ -106,18 +106,16 @@ __global__ __launch_bounds__(64) void k_jsiia_gj(ModelView<T> m, ChainMap cm, co
 // values, so lane t of the wavefront (group 0, column t) holds x_t for all of
 // them, and one readlane hands it to every lane without an LDS round trip.
 // wrow: the block's published rows (row t at wrow[t * ws], its column c at
-// + c); yout takes x_t on the lanes of row group t.
+// + c), zero on and above the diagonal, so lanes c >= t subtract an exact zero
+// and the step needs no select. On return lane c holds x_c.
 template <int G, int T, typename R>
-__device__ __forceinline__ void block_back_solve(R& zc, R& yout, const R* wrow, int ws, int c, int r, R rbc) {
+__device__ __forceinline__ void block_back_solve(R& zc, const R* wrow, int ws, int c, R rbc) {
     static_assert(T < G && G <= 64, "column t of a group is wavefront lane t");
-    R w = R(0);
-    if constexpr (T > 0) w = wrow[T * ws + c];   // read before x_t is known; used where c < T
-    const R xt = dpp::read<T>(zc);
-    if (r == T) yout = xt;
     if constexpr (T > 0) {
-        const R z = zc - rbc * w * xt;
-        zc = c < T ? z : zc;
-        block_back_solve<G, T - 1>(zc, yout, wrow, ws, c, r, rbc);
+        const R w = wrow[T * ws + c];                 // read before x_t is known
+        const R xt = dpp::read<T>(zc);
+        zc -= rbc * w * xt;
+        block_back_solve<G, T - 1>(zc, wrow, ws, c, rbc);
     }
 }
 
@@ -274,7 +272,8 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> 
     for (int jb = 7; jb >= 0; --jb) {
         block_sync<TH>();                                    // earlier reads of the buffer are done
 #pragma unroll
-        for (int bb = 0; bb <= jb; ++bb) wbuf[r * WS + c + G * bb] = mb[jb * (jb + 1) / 2 + bb];
+        for (int bb = 0; bb <= jb; ++bb)                     // the diagonal block strictly below its diagonal
+            wbuf[r * WS + c + G * bb] = (bb < jb || c < r) ? mb[jb * (jb + 1) / 2 + bb] : T(0);
         if (c == 0) {
             zb[r] = y[jb];
             rb[r] = rd_of(jb);
@@ -282,7 +281,8 @@ __global__ __launch_bounds__((NP / 8) * (NP / 8)) void k_jsiia_ldl(ModelView<T> 
         block_sync<TH>();
         // x_t = z_t - (1 / d_t) sum_{u > t} m_ut x_u within the block; lane c ends with x_c
         T xc = zb[c];
-        block_back_solve<G, G - 1>(xc, y[jb], wbuf + G * jb, WS, c, r, rb[c]);
+        block_back_solve<G, G - 1>(xc, wbuf + G * jb, WS, c, rb[c]);
+        y[jb] = xlane::bperm(xc, 4 * r);                     // x of row r of the block: wavefront lane r has c = r
         // rows k above the block: z_k -= (1 / d_k) sum_t m_tk x_t
 #pragma unroll
         for (int a = 0; a < jb; ++a) y[a] -= dpp::group_sum<G>(wbuf[c * WS + r + G * a] * xc) * rd_of(a);
