@@ -182,31 +182,38 @@ template <typename T> __device__ __forceinline__ void inertia_to_mat6(const Iner
 
 // ---------------- small dense SPD factor / solves (registers) ----------------
 
-// In-place lower Cholesky of a K x K SPD matrix stored row-major in a[K*K];
-// only the lower triangle is read and written. Returns false on a non-positive pivot.
 // 1/p and 1/sqrt(p) to full precision for p > 0 (normal): the hardware
-// estimate refined by Newton steps, in place of the division and square-root
-// expansions. For p <= 0 the result is meaningless; callers check p > 0.
+// estimate refined, in place of the division and square-root expansions. For
+// p <= 0 the result is meaningless; callers check p > 0.
+// FP64: the estimate is good to about 5e-8, so one third-order step takes it
+// below the rounding of a double (error of order 5e-8 cubed): with
+// e = 1 - p r, 1/p = r / (1 - e) = r (1 + e + e^2 + ...), and with
+// e = 1 - p y^2, 1/sqrt(p) = y (1 - e)^(-1/2) = y (1 + e/2 + 3e^2/8 + ...).
+// Three and five operations against four and eight for two Newton steps,
+// with shorter dependency chains and the same rounding error (a CPU emulation
+// over 2e4 values: at most 0.50 and 0.96 ulp).
 __device__ __forceinline__ double rcp_refined(double p) {
-    double r = __builtin_amdgcn_rcp(p);
-    r = __builtin_fma(r, __builtin_fma(-p, r, 1.0), r);
-    return __builtin_fma(r, __builtin_fma(-p, r, 1.0), r);
+    const double r = __builtin_amdgcn_rcp(p);
+    const double e = __builtin_fma(-p, r, 1.0);
+    return __builtin_fma(r, __builtin_fma(e, e, e), r);
 }
 __device__ __forceinline__ float rcp_refined(float p) {
     float r = __builtin_amdgcn_rcpf(p);
     return __builtin_fmaf(r, __builtin_fmaf(-p, r, 1.0f), r);
 }
-// y <- y + (y / 2)(1 - p y^2)
 __device__ __forceinline__ double rsqrt_refined(double p) {
-    double y = __builtin_amdgcn_rsq(p);
-    y = __builtin_fma(0.5 * y, __builtin_fma(-p * y, y, 1.0), y);
-    return __builtin_fma(0.5 * y, __builtin_fma(-p * y, y, 1.0), y);
+    const double y = __builtin_amdgcn_rsq(p);
+    const double e = __builtin_fma(-p * y, y, 1.0);
+    return __builtin_fma(y * e, __builtin_fma(e, 0.375, 0.5), y);
 }
+// FP32: one Newton step, y <- y + (y / 2)(1 - p y^2), on the hardware estimate
 __device__ __forceinline__ float rsqrt_refined(float p) {
     float y = __builtin_amdgcn_rsqf(p);
     return __builtin_fmaf(0.5f * y, __builtin_fmaf(-p * y, y, 1.0f), y);
 }
 
+// In-place lower Cholesky of a K x K SPD matrix stored row-major in a[K*K];
+// only the lower triangle is read and written. Returns false on a non-positive pivot.
 template <typename T, int K> __device__ __forceinline__ bool chol_inplace(T a[K * K]) {
     bool ok = true;
 #pragma unroll
