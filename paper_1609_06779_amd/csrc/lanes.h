@@ -200,7 +200,7 @@ template <typename T> struct ModelView {
 // h = m c, Ibar = Ic - m [c][c]): Ic = Ibar + m [c][c] = Ibar + m (c c^T - |c|^2 1),
 // inverted by cofactors. Evaluated in FP64 whatever T is.
 template <typename T> __device__ __forceinline__ void inv_params_of(const Inertia<T>& j, T p[10]) {
-    const double m = j.m, mi = 1.0 / m;
+    const double m = j.m, mi = rcp_refined(m);        // m > 0 and det > 0: the inertia is SPD
     const double c[3] = {double(j.h[0]) * mi, double(j.h[1]) * mi, double(j.h[2]) * mi};
     const double a00 = double(j.ib[0]) - m * (c[1] * c[1] + c[2] * c[2]);
     const double a11 = double(j.ib[1]) - m * (c[0] * c[0] + c[2] * c[2]);
@@ -210,7 +210,7 @@ template <typename T> __device__ __forceinline__ void inv_params_of(const Inerti
     const double a12 = double(j.ib[5]) + m * c[1] * c[2];
     const double k00 = a11 * a22 - a12 * a12, k01 = a02 * a12 - a01 * a22, k02 = a01 * a12 - a02 * a11;
     const double k11 = a00 * a22 - a02 * a02, k12 = a01 * a02 - a00 * a12, k22 = a00 * a11 - a01 * a01;
-    const double idet = 1.0 / (a00 * k00 + a01 * k01 + a02 * k02);
+    const double idet = rcp_refined(a00 * k00 + a01 * k01 + a02 * k02);
     p[0] = T(k00 * idet); p[1] = T(k11 * idet); p[2] = T(k22 * idet);
     p[3] = T(k01 * idet); p[4] = T(k02 * idet); p[5] = T(k12 * idet);
     p[6] = T(c[0]); p[7] = T(c[1]); p[8] = T(c[2]);
