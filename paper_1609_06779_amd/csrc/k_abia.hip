@@ -59,23 +59,85 @@ size_t abia_workspace_elems(int batch, int nmax, bool tree) {
 // Model reads go through the robot-interleaved copy: lanes hold consecutive
 // chains, so field f of link i is one contiguous read across the wavefront.
 //
+// Joint state through LDS. q, qd, tau and qdd are packed per chain (entry
+// state0 + i), so one lane per chain would touch a cache line per lane with
+// every access. Each sweep moves them instead in tiles of ST_L sweep positions
+// by the wavefront's 64 chains: a tile is loaded with consecutive lanes on
+// consecutive entries of one chain (ST_L * sizeof(T) bytes per chain),
+// transposed through LDS, and each lane reads its chain's entry per step.
+// Position k of a sweep is link k (forward sweeps) or link n - 1 - k (the
+// backward sweep). Tiles are committed to LDS one tile ahead of use and loaded
+// into registers two ahead, so their memory latency overlaps the steps.
+constexpr int ST_L = 8;                 // sweep positions per tile
+constexpr int ST_W = 64 + 8;            // LDS row stride: commits hit every bank pair equally
+
+template <typename T, int NA> struct StateStage {
+    T* s;                               // [2 slots][NA][ST_L][ST_W], this wavefront's
+    const int64_t* base;                // [64] first state entry of each lane's chain
+    const int* len;                     // [64] its length (0: no chain)
+    int lane;
+    T reg[NA][ST_L];                    // the tile in flight
+    // Loads tile t of arrays a[0..NA) into registers: lane l takes entry
+    // l % ST_L of chain (k * 64 + l) / ST_L in its k-th load.
+    template <bool FWD> __device__ __forceinline__ void load(const T* const (&a)[NA], int t) {
+#pragma unroll
+        for (int k = 0; k < ST_L; ++k) {
+            const int c = (k * 64 + lane) / ST_L, j = lane % ST_L;
+            const int pos = t * ST_L + j, n = len[c];
+            const int64_t e = FWD ? base[c] + pos : base[c] + (n - 1 - pos);
+#pragma unroll
+            for (int v = 0; v < NA; ++v) reg[v][k] = pos < n ? a[v][e] : T(0);
+        }
+    }
+    __device__ __forceinline__ void commit(int t) {
+        T* d = s + (t & 1) * NA * ST_L * ST_W;
+#pragma unroll
+        for (int k = 0; k < ST_L; ++k) {
+            const int c = (k * 64 + lane) / ST_L, j = lane % ST_L;
+#pragma unroll
+            for (int v = 0; v < NA; ++v) d[(v * ST_L + j) * ST_W + c] = reg[v][k];
+        }
+    }
+    // array v at sweep position pos (its tile committed), for this lane's chain
+    __device__ __forceinline__ T get(int v, int pos) const {
+        return s[(((pos / ST_L) & 1) * NA + v) * ST_L * ST_W + (pos % ST_L) * ST_W + lane];
+    }
+    // Before the loop: tiles 0 and 1 committed, tile 2 in flight.
+    template <bool FWD> __device__ __forceinline__ void start(const T* const (&a)[NA]) {
+        load<FWD>(a, 0);
+        commit(0);
+        load<FWD>(a, 1);
+        commit(1);
+        load<FWD>(a, 2);
+    }
+    // At position k of the loop (every lane, every k): at the first position of
+    // tile t >= 1 the registers (tile t + 1) go to LDS over tile t - 1, whose
+    // last entry was read two positions earlier, and tile t + 2 is loaded.
+    template <bool FWD> __device__ __forceinline__ void step(const T* const (&a)[NA], int k) {
+        if (k > 0 && k % ST_L == 0) {
+            const int t = k / ST_L;
+            commit(t + 1);
+            load<FWD>(a, t + 2);
+        }
+    }
+};
+
 // Per-link inputs of a forward sweep, loaded ahead of their use: the home
-// pose (quaternion, origin) and the joint state; with `ws`, sweep 3 also
-// takes the link's 6 workspace values.
+// pose (quaternion, origin) and the joint state (from the LDS stage); with
+// `ws`, sweep 3 also takes the link's 6 workspace values.
 template <typename T, bool WS> struct LinkIn {
     T qt[4], p[3], q, qd;
     T w[WS ? ABIA_WS_FIELDS : 1];
 };
 template <bool NT, bool WS, typename T>
-__device__ __forceinline__ LinkIn<T, WS> link_in(const ModelView<T>& m, int i, int slot, const T* q, const T* qd,
-                                                 int64_t st, const T* wsi) {
+__device__ __forceinline__ LinkIn<T, WS> link_in(const ModelView<T>& m, int i, int slot, T qv, T qdv, const T* wsi) {
     LinkIn<T, WS> r;
 #pragma unroll
     for (int k = 0; k < 4; ++k) r.qt[k] = m.template at_il<NT>(IL_QUAT + k, i, slot);
 #pragma unroll
     for (int k = 0; k < 3; ++k) r.p[k] = m.template at_il<NT>(IL_POS + k, i, slot);
-    r.q = q[st];
-    r.qd = WS ? T(0) : qd[st];                     // sweep 3 needs no joint rate
+    r.q = qv;
+    r.qd = qdv;
     if constexpr (WS) {
 #pragma unroll
         for (int f = 0; f < ABIA_WS_FIELDS; ++f) r.w[f] = ld_ws<NT>(wsi + (size_t)f * 64);
@@ -135,34 +197,56 @@ template <typename T> __device__ __forceinline__ void congruence_to_parent(const
     }
 }
 
-// One chain (or tree) on one lane. wsb: this lane's workspace column, field f
-// of link i at wsb[(i * abia_fields<TREE>() + f) * 64]. NT: model and
-// workspace streamed with non-temporal accesses (see ModelView::at_il).
+// LDS of one wavefront for the state stage: the largest stage (sweep 2: q,
+// qd, tau; 2 slots) also holds sweep 3's q slots and its output tile.
+constexpr int ABIA_STAGE = 2 * 3 * ST_L * ST_W;
+static_assert(2 * 1 * ST_L * ST_W + ST_L * ST_W <= ABIA_STAGE, "sweep 3's stage and output tile fit");
+
+// One chain (or tree) on one lane; every lane of the wavefront calls it (a
+// lane without a chain with ci.n = 0), since the state stage is loaded by all
+// of them. wsb: this lane's workspace column, field f of link i at
+// wsb[(i * abia_fields<TREE>() + f) * 64]. NT: model and workspace streamed
+// with non-temporal accesses (see ModelView::at_il). stg, sbase, slen: the
+// wavefront's LDS (ABIA_STAGE values, 64 + 64 entries).
 template <bool NT, bool TREE, typename T>
-__device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInfo& ci, const T* __restrict__ q,
+__device__ __forceinline__ void abia_chain(const ModelView<T>& m, ChainInfo ci, const T* __restrict__ q,
                                            const T* __restrict__ qd, const T* __restrict__ tau,
-                                           T* __restrict__ qdd, T* __restrict__ wsb, int b, const FdOut<T>& o) {
+                                           T* __restrict__ qdd, T* __restrict__ wsb, int b, const FdOut<T>& o,
+                                           T* stg, int64_t* sbase, int* slen) {
     if (ci.unsolved) {                                 // longer than the workspace is sized for
         if (qdd) fill_unsolved(qdd, ci.state0, ci.unsolved, 0, 1);
-        return;
+        ci.n = 0;
     }
     const int n = ci.n;
+    const int lane = threadIdx.x & 63;
     auto wsp = [&](int i, int f) -> T* { return &wsb[((size_t)i * abia_fields<TREE>() + f) * 64]; };
+    block_sync<64>();                                  // earlier readers of the chain table are done
+    sbase[lane] = ci.state0;
+    slen[lane] = n;
+    block_sync<64>();
+    int nw = n;                                        // the wavefront's longest chain: the loops' bound
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) nw = max(nw, __shfl_xor(nw, d, 64));
 
     // sweep 1. The light forward sweeps wait on memory, not on arithmetic: each
     // step starts the loads of the link two ahead, so two links' inputs are in
     // flight while one is computed.
     T v[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
     T a[6] = {T(0), T(0), T(0), -m.g[0], -m.g[1], -m.g[2]};
+    StateStage<T, 2> s1{stg, sbase, slen, lane};
+    const T* const st1[2] = {q, qd};
+    s1.template start<true>(st1);
+    block_sync<64>();
     LinkIn<T, false> in0, in1;
-    if (n > 0) in0 = link_in<NT, false>(m, 0, ci.slot, q, qd, ci.state0, wsb);
-    if (n > 1) in1 = link_in<NT, false>(m, 1, ci.slot, q, qd, ci.state0 + 1, wsb);
-#pragma unroll 2
-    for (int i = 0; i < n; ++i) {
-        const int64_t st = ci.state0 + i;
+    if (n > 0) in0 = link_in<NT, false>(m, 0, ci.slot, s1.get(0, 0), s1.get(1, 0), wsb);
+    if (n > 1) in1 = link_in<NT, false>(m, 1, ci.slot, s1.get(0, 1), s1.get(1, 1), wsb);
+    for (int i = 0; i < nw; ++i) {
+        s1.template step<true>(st1, i);
+        block_sync<64>();
+        if (i >= n) continue;
         const LinkIn<T, false> cur = in0;
         in0 = in1;
-        if (i + 2 < n) in1 = link_in<NT, false>(m, i + 2, ci.slot, q, qd, st + 2, wsb);
+        if (i + 2 < n) in1 = link_in<NT, false>(m, i + 2, ci.slot, s1.get(0, i + 2), s1.get(1, i + 2), wsb);
         int32_t code = 0;
         if constexpr (TREE) {
             code = m.template tree_il<NT>(i, ci.slot);
@@ -217,25 +301,33 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
     bool carry = false;                                // trees: registers hold link i+1's terms for link i
     // each step starts the loads of the link before it (the step's arithmetic
     // outlasts a memory round trip)
+    // the state stage runs backward here: position k is link n - 1 - k
+    StateStage<T, 3> s2{stg, sbase, slen, lane};
+    const T* const st2[3] = {q, qd, tau};
+    block_sync<64>();                                  // sweep 1's reads of the stage are done
+    s2.template start<false>(st2);
+    block_sync<64>();
     Inertia<T> jn;
     LinkIn<T, false> pn;
     T taun = T(0);
     if (n > 0) {
         jn = m.template inertia_il<NT>(n - 1, ci.slot);
-        pn = link_in<NT, false>(m, n - 1, ci.slot, q, qd, ci.state0 + n - 1, wsb);
-        taun = tau[ci.state0 + n - 1];
+        pn = link_in<NT, false>(m, n - 1, ci.slot, s2.get(0, 0), s2.get(1, 0), wsb);
+        taun = s2.get(2, 0);
     }
-#pragma unroll 2
-    for (int i = n - 1; i >= 0; --i) {
-        const int64_t st = ci.state0 + i;
+    for (int k = 0; k < nw; ++k) {
+        s2.template step<false>(st2, k);
+        block_sync<64>();
+        if (k >= n) continue;
+        const int i = n - 1 - k;
         T f[6], fp[6], pp[6], jh[36];
         const Inertia<T> ji = jn;
         const LinkIn<T, false> pcur = pn;
         const T taui = taun;
         if (i > 0) {
             jn = m.template inertia_il<NT>(i - 1, ci.slot);
-            pn = link_in<NT, false>(m, i - 1, ci.slot, q, qd, st - 1, wsb);
-            taun = tau[st - 1];
+            pn = link_in<NT, false>(m, i - 1, ci.slot, s2.get(0, k + 1), s2.get(1, k + 1), wsb);
+            taun = s2.get(2, k + 1);
         }
         if constexpr (TREE) {
 #pragma unroll
@@ -370,15 +462,22 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
 
     // sweep 3, with the loads of the link two ahead started at each step
     T acc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+    StateStage<T, 1> s3{stg, sbase, slen, lane};
+    const T* const st3[1] = {q};
+    T* const otile = stg + 2 * ST_L * ST_W;            // qdd of the current tile, [ST_L][ST_W]
+    block_sync<64>();                                  // sweep 2's reads of the stage are done
+    s3.template start<true>(st3);
+    block_sync<64>();
     LinkIn<T, true> wn0, wn1;
-    if (n > 0) wn0 = link_in<NT, true>(m, 0, ci.slot, q, q, ci.state0, wsp(0, 0));
-    if (n > 1) wn1 = link_in<NT, true>(m, 1, ci.slot, q, q, ci.state0 + 1, wsp(1, 0));
-#pragma unroll 2
-    for (int i = 0; i < n; ++i) {
-        const int64_t st = ci.state0 + i;
+    if (n > 0) wn0 = link_in<NT, true>(m, 0, ci.slot, s3.get(0, 0), T(0), wsp(0, 0));
+    if (n > 1) wn1 = link_in<NT, true>(m, 1, ci.slot, s3.get(0, 1), T(0), wsp(1, 0));
+    for (int i = 0; i < nw; ++i) {
+        s3.template step<true>(st3, i);
+        block_sync<64>();
+        if (i < n) {
         const LinkIn<T, true> cur = wn0;
         wn0 = wn1;
-        if (i + 2 < n) wn1 = link_in<NT, true>(m, i + 2, ci.slot, q, q, st + 2, wsp(i + 2, 0));
+        if (i + 2 < n) wn1 = link_in<NT, true>(m, i + 2, ci.slot, s3.get(0, i + 2), T(0), wsp(i + 2, 0));
         int32_t code = 0;
         if constexpr (TREE) {
             code = m.template tree_il<NT>(i, ci.slot);
@@ -400,12 +499,30 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, const ChainInf
         t[2] = s;
 #pragma unroll
         for (int c = 0; c < 6; ++c) acc[c] = t[c];
-        o.put(qdd, st, b, i, x);                      // qdd may be null when the reverse mode takes it in aux
+        otile[(i % ST_L) * ST_W + lane] = x;
+        o.put_aux(b, i, x);                            // qdd may be null when the reverse mode takes it in aux
         if constexpr (TREE) {
             if (code & TREE_BRANCH) {
 #pragma unroll
                 for (int c = 0; c < 6; ++c) st_ws<NT && ABIA_BRANCH_NT>(acc[c], wsp(i, ABIA_WB + c));
             }
+        }
+        }
+        // the tile's qdd out, chain by chain (every lane, after a tile's last step)
+        if (i % ST_L == ST_L - 1 || i == nw - 1) {
+            block_sync<64>();
+            const int t = i / ST_L;
+#pragma unroll
+            for (int kk = 0; kk < ST_L; ++kk) {
+                const int c = (kk * 64 + lane) / ST_L, j = lane % ST_L;
+                const int pos = t * ST_L + j;
+                if (qdd && pos < slen[c]) {
+                    const int64_t e = sbase[c] + pos;
+                    const T v = otile[j * ST_W + c];
+                    qdd[e] = o.accumulate ? qdd[e] + v : v;
+                }
+            }
+            block_sync<64>();                          // read before the next tile's steps write
         }
     }
 }
@@ -414,12 +531,16 @@ template <typename T, bool NT, bool TREE>
 __global__ __launch_bounds__(64) void k_abia(ModelView<T> m, ChainMap cm, int nmax, const T* __restrict__ q,
                                              const T* __restrict__ qd, const T* __restrict__ tau,
                                              T* __restrict__ qdd, T* __restrict__ ws, FdOut<T> o) {
+    __shared__ T stg[ABIA_STAGE];
+    __shared__ int64_t sbase[64];
+    __shared__ int slen[64];
     const int lane = threadIdx.x;
     const int b = blockIdx.x * 64 + lane;
-    if (b >= cm.batch) return;
+    ChainInfo ci{0, 0, 0, 0, 0};                      // lanes past the batch take part with no chain
+    if (b < cm.batch) ci = chain_info(m, cm, b);
     // workspace: [block][link][field][lane]
-    abia_chain<NT, TREE>(m, chain_info(m, cm, b), q, qd, tau, qdd,
-                         ws + (size_t)blockIdx.x * nmax * abia_fields<TREE>() * 64 + lane, b, o);
+    abia_chain<NT, TREE>(m, ci, q, qd, tau, qdd, ws + (size_t)blockIdx.x * nmax * abia_fields<TREE>() * 64 + lane,
+                         b, o, stg, sbase, slen);
 }
 
 // Persistent form for ragged batches: each wavefront takes 64-entry tiles of
@@ -435,6 +556,9 @@ __global__ __launch_bounds__(64) void k_abia_persistent(ModelView<T> m, ChainMap
                                                         const T* __restrict__ qd, const T* __restrict__ tau,
                                                         T* __restrict__ qdd, T* __restrict__ ws) {
     __shared__ int tile_s;
+    __shared__ T stg[ABIA_STAGE];
+    __shared__ int64_t sbase[64];
+    __shared__ int slen[64];
     const int lane = threadIdx.x;
     T* wsb = ws + (size_t)blockIdx.x * nmax * abia_fields<TREE>() * 64 + lane;
     for (;;) {
@@ -445,7 +569,9 @@ __global__ __launch_bounds__(64) void k_abia_persistent(ModelView<T> m, ChainMap
         if ((int64_t)tile * 64 >= count) break;
         const int k = tile * 64 + lane;
         const int b = k < count ? (order ? order[k] : k) : cm.batch;
-        if (b < cm.batch) abia_chain<NT, TREE>(m, chain_info(m, cm, b), q, qd, tau, qdd, wsb, b, FdOut<T>{});
+        ChainInfo ci{0, 0, 0, 0, 0};                  // entries past the batch: no chain, but the lane takes part
+        if (b < cm.batch) ci = chain_info(m, cm, b);
+        abia_chain<NT, TREE>(m, ci, q, qd, tau, qdd, wsb, b, FdOut<T>{}, stg, sbase, slen);
     }
 }
 

@@ -272,6 +272,10 @@ template <typename T> struct FdOut {
     int aux_nmax = 0, aux_fields = 0, aux_field = 0;
     __device__ __forceinline__ void put(T* out, int64_t st, int b, int i, T v) const {
         if (out) out[st] = accumulate ? out[st] + v : v;
+        put_aux(b, i, v);
+    }
+    // the aux copy alone (for kernels that write `out` themselves)
+    __device__ __forceinline__ void put_aux(int b, int i, T v) const {
         if (aux) aux[(((size_t)(b >> 6) * aux_nmax + i) * aux_fields + aux_field) * 64 + (b & 63)] = v;
     }
 };
