@@ -59,69 +59,6 @@ size_t abia_workspace_elems(int batch, int nmax, bool tree) {
 // Model reads go through the robot-interleaved copy: lanes hold consecutive
 // chains, so field f of link i is one contiguous read across the wavefront.
 //
-// Joint state through LDS. q, qd, tau and qdd are packed per chain (entry
-// state0 + i), so one lane per chain would touch a cache line per lane with
-// every access. Each sweep moves them instead in tiles of ST_L sweep positions
-// by the wavefront's 64 chains: a tile is loaded with consecutive lanes on
-// consecutive entries of one chain (ST_L * sizeof(T) bytes per chain),
-// transposed through LDS, and each lane reads its chain's entry per step.
-// Position k of a sweep is link k (forward sweeps) or link n - 1 - k (the
-// backward sweep). Tiles are committed to LDS one tile ahead of use and loaded
-// into registers two ahead, so their memory latency overlaps the steps.
-constexpr int ST_L = 8;                 // sweep positions per tile
-constexpr int ST_W = 64 + 8;            // LDS row stride: commits hit every bank pair equally
-
-template <typename T, int NA> struct StateStage {
-    T* s;                               // [2 slots][NA][ST_L][ST_W], this wavefront's
-    const int64_t* base;                // [64] first state entry of each lane's chain
-    const int* len;                     // [64] its length (0: no chain)
-    int lane;
-    T reg[NA][ST_L];                    // the tile in flight
-    // Loads tile t of arrays a[0..NA) into registers: lane l takes entry
-    // l % ST_L of chain (k * 64 + l) / ST_L in its k-th load.
-    template <bool FWD> __device__ __forceinline__ void load(const T* const (&a)[NA], int t) {
-#pragma unroll
-        for (int k = 0; k < ST_L; ++k) {
-            const int c = (k * 64 + lane) / ST_L, j = lane % ST_L;
-            const int pos = t * ST_L + j, n = len[c];
-            const int64_t e = FWD ? base[c] + pos : base[c] + (n - 1 - pos);
-#pragma unroll
-            for (int v = 0; v < NA; ++v) reg[v][k] = pos < n ? a[v][e] : T(0);
-        }
-    }
-    __device__ __forceinline__ void commit(int t) {
-        T* d = s + (t & 1) * NA * ST_L * ST_W;
-#pragma unroll
-        for (int k = 0; k < ST_L; ++k) {
-            const int c = (k * 64 + lane) / ST_L, j = lane % ST_L;
-#pragma unroll
-            for (int v = 0; v < NA; ++v) d[(v * ST_L + j) * ST_W + c] = reg[v][k];
-        }
-    }
-    // array v at sweep position pos (its tile committed), for this lane's chain
-    __device__ __forceinline__ T get(int v, int pos) const {
-        return s[(((pos / ST_L) & 1) * NA + v) * ST_L * ST_W + (pos % ST_L) * ST_W + lane];
-    }
-    // Before the loop: tiles 0 and 1 committed, tile 2 in flight.
-    template <bool FWD> __device__ __forceinline__ void start(const T* const (&a)[NA]) {
-        load<FWD>(a, 0);
-        commit(0);
-        load<FWD>(a, 1);
-        commit(1);
-        load<FWD>(a, 2);
-    }
-    // At position k of the loop (every lane, every k): at the first position of
-    // tile t >= 1 the registers (tile t + 1) go to LDS over tile t - 1, whose
-    // last entry was read two positions earlier, and tile t + 2 is loaded.
-    template <bool FWD> __device__ __forceinline__ void step(const T* const (&a)[NA], int k) {
-        if (k > 0 && k % ST_L == 0) {
-            const int t = k / ST_L;
-            commit(t + 1);
-            load<FWD>(a, t + 2);
-        }
-    }
-};
-
 // Per-link inputs of a forward sweep, loaded ahead of their use: the home
 // pose (quaternion, origin) and the joint state (from the LDS stage); with
 // `ws`, sweep 3 also takes the link's 6 workspace values.
@@ -220,13 +157,7 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, ChainInfo ci, 
     const int n = ci.n;
     const int lane = threadIdx.x & 63;
     auto wsp = [&](int i, int f) -> T* { return &wsb[((size_t)i * abia_fields<TREE>() + f) * 64]; };
-    block_sync<64>();                                  // earlier readers of the chain table are done
-    sbase[lane] = ci.state0;
-    slen[lane] = n;
-    block_sync<64>();
-    int nw = n;                                        // the wavefront's longest chain: the loops' bound
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) nw = max(nw, __shfl_xor(nw, d, 64));
+    const int nw = stage_chains(sbase, slen, ci.state0, n, lane);   // the loops run to the longest chain
 
     // sweep 1. The light forward sweeps wait on memory, not on arithmetic: each
     // step starts the loads of the link two ahead, so two links' inputs are in
@@ -464,7 +395,8 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, ChainInfo ci, 
     T acc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
     StateStage<T, 1> s3{stg, sbase, slen, lane};
     const T* const st3[1] = {q};
-    T* const otile = stg + 2 * ST_L * ST_W;            // qdd of the current tile, [ST_L][ST_W]
+    OutTile<T, 1> o3{stg + 2 * ST_L * ST_W, sbase, slen, lane};   // qdd of the current tile
+    T* const out3[1] = {qdd};
     block_sync<64>();                                  // sweep 2's reads of the stage are done
     s3.template start<true>(st3);
     block_sync<64>();
@@ -499,7 +431,7 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, ChainInfo ci, 
         t[2] = s;
 #pragma unroll
         for (int c = 0; c < 6; ++c) acc[c] = t[c];
-        otile[(i % ST_L) * ST_W + lane] = x;
+        o3.put(0, i, x);
         o.put_aux(b, i, x);                            // qdd may be null when the reverse mode takes it in aux
         if constexpr (TREE) {
             if (code & TREE_BRANCH) {
@@ -508,22 +440,7 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, ChainInfo ci, 
             }
         }
         }
-        // the tile's qdd out, chain by chain (every lane, after a tile's last step)
-        if (i % ST_L == ST_L - 1 || i == nw - 1) {
-            block_sync<64>();
-            const int t = i / ST_L;
-#pragma unroll
-            for (int kk = 0; kk < ST_L; ++kk) {
-                const int c = (kk * 64 + lane) / ST_L, j = lane % ST_L;
-                const int pos = t * ST_L + j;
-                if (qdd && pos < slen[c]) {
-                    const int64_t e = sbase[c] + pos;
-                    const T v = otile[j * ST_W + c];
-                    qdd[e] = o.accumulate ? qdd[e] + v : v;
-                }
-            }
-            block_sync<64>();                          // read before the next tile's steps write
-        }
+        o3.template flush<true>(out3, i, nw, o.accumulate);
     }
 }
 

@@ -308,6 +308,139 @@ template <int THREADS> __device__ __forceinline__ void block_sync() {
     else __builtin_amdgcn_wave_barrier();
 }
 
+// Joint state through LDS. q, qd, tau and qdd are packed per chain (entry
+// state0 + i), so one lane per chain would touch a cache line per lane with
+// every access. Each sweep moves them instead in tiles of ST_L sweep positions
+// by the wavefront's 64 chains: a tile is loaded with consecutive lanes on
+// consecutive entries of one chain (ST_L * sizeof(T) bytes per chain),
+// transposed through LDS, and each lane reads its chain's entry per step.
+// Position k of a sweep is link k (forward sweeps) or link n - 1 - k (the
+// backward sweep). Tiles are committed to LDS one tile ahead of use and loaded
+// into registers two ahead, so their memory latency overlaps the steps.
+constexpr int ST_L = 8;                 // sweep positions per tile
+constexpr int ST_W = 64 + 8;            // LDS row stride: commits hit every bank pair equally
+
+template <typename T, int NA> struct StateStage {
+    T* s;                               // [2 slots][NA][ST_L][ST_W], this wavefront's
+    const int64_t* base;                // [64] first state entry of each lane's chain
+    const int* len;                     // [64] its length (0: no chain)
+    int lane;
+    T reg[NA][ST_L];                    // the tile in flight
+    // Loads tile t of arrays a[0..NA) into registers: lane l takes entry
+    // l % ST_L of chain (k * 64 + l) / ST_L in its k-th load.
+    template <bool FWD> __device__ __forceinline__ void load(const T* const (&a)[NA], int t) {
+#pragma unroll
+        for (int k = 0; k < ST_L; ++k) {
+            const int c = (k * 64 + lane) / ST_L, j = lane % ST_L;
+            const int pos = t * ST_L + j, n = len[c];
+            const int64_t e = FWD ? base[c] + pos : base[c] + (n - 1 - pos);
+#pragma unroll
+            for (int v = 0; v < NA; ++v) reg[v][k] = pos < n ? a[v][e] : T(0);
+        }
+    }
+    __device__ __forceinline__ void commit(int t) {
+        T* d = s + (t & 1) * NA * ST_L * ST_W;
+#pragma unroll
+        for (int k = 0; k < ST_L; ++k) {
+            const int c = (k * 64 + lane) / ST_L, j = lane % ST_L;
+#pragma unroll
+            for (int v = 0; v < NA; ++v) d[(v * ST_L + j) * ST_W + c] = reg[v][k];
+        }
+    }
+    // array v at sweep position pos (its tile committed), for this lane's chain
+    __device__ __forceinline__ T get(int v, int pos) const {
+        return s[(((pos / ST_L) & 1) * NA + v) * ST_L * ST_W + (pos % ST_L) * ST_W + lane];
+    }
+    // Before the loop: tiles 0 and 1 committed, tile 2 in flight. (The caller
+    // separates the commits from the first reads with block_sync<64>.)
+    template <bool FWD> __device__ __forceinline__ void start(const T* const (&a)[NA]) {
+        load<FWD>(a, 0);
+        commit(0);
+        load<FWD>(a, 1);
+        commit(1);
+        load<FWD>(a, 2);
+    }
+    // At position k of the loop (every lane, every k): at the first position of
+    // tile t >= 1 the registers (tile t + 1) go to LDS over tile t - 1, whose
+    // last entry was read two positions earlier, and tile t + 2 is loaded.
+    template <bool FWD> __device__ __forceinline__ void step(const T* const (&a)[NA], int k) {
+        if (k > 0 && k % ST_L == 0) {
+            const int t = k / ST_L;
+            commit(t + 1);
+            load<FWD>(a, t + 2);
+        }
+    }
+};
+
+// Per-lane outputs of a sweep, staged like StateStage's inputs: put() writes
+// this lane's value at sweep position pos, and after a tile's last position
+// flush() stores the tile chain by chain (consecutive lanes on consecutive
+// entries of one chain), adding to what is there when accumulating.
+template <typename T, int NO> struct OutTile {
+    T* s;                               // [NO][ST_L][ST_W]
+    const int64_t* base;
+    const int* len;
+    int lane;
+    __device__ __forceinline__ void put(int o, int pos, T v) { s[(o * ST_L + pos % ST_L) * ST_W + lane] = v; }
+    // Every lane at every position k of a loop over nw positions; acts after
+    // the last position of each tile. Null outputs are skipped.
+    template <bool FWD>
+    __device__ __forceinline__ void flush(T* const (&out)[NO], int k, int nw, int accumulate) {
+        if (k % ST_L != ST_L - 1 && k != nw - 1) return;
+        block_sync<64>();
+        const int t = k / ST_L;
+        if (accumulate) {
+            // the values to add to are all loaded first, so that they are in
+            // flight together (a store may alias a later entry, so the compiler
+            // keeps the written order), then the sums are stored
+            T prev[ST_L][NO];
+#pragma unroll
+            for (int kk = 0; kk < ST_L; ++kk) {
+                const int c = (kk * 64 + lane) / ST_L, j = lane % ST_L;
+                const int pos = t * ST_L + j, n = len[c];
+                const int64_t e = FWD ? base[c] + pos : base[c] + (n - 1 - pos);
+#pragma unroll
+                for (int o = 0; o < NO; ++o) prev[kk][o] = out[o] && pos < n ? out[o][e] : T(0);
+            }
+#pragma unroll
+            for (int kk = 0; kk < ST_L; ++kk) {
+                const int c = (kk * 64 + lane) / ST_L, j = lane % ST_L;
+                const int pos = t * ST_L + j, n = len[c];
+                const int64_t e = FWD ? base[c] + pos : base[c] + (n - 1 - pos);
+#pragma unroll
+                for (int o = 0; o < NO; ++o)
+                    if (out[o] && pos < n) out[o][e] = prev[kk][o] + s[(o * ST_L + j) * ST_W + c];
+            }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < ST_L; ++kk) {
+                const int c = (kk * 64 + lane) / ST_L, j = lane % ST_L;
+                const int pos = t * ST_L + j, n = len[c];
+                const int64_t e = FWD ? base[c] + pos : base[c] + (n - 1 - pos);
+#pragma unroll
+                for (int o = 0; o < NO; ++o)
+                    if (out[o] && pos < n) out[o][e] = s[(o * ST_L + j) * ST_W + c];
+            }
+        }
+        block_sync<64>();                       // read before the next tile's puts
+    }
+};
+
+// The chain table of a wavefront for StateStage / OutTile: each lane enters
+// its chain (first state entry, length; 0 for none). Returns the longest
+// length in the wavefront, the bound of the sweep loops (every lane runs them,
+// each lane's body guarded by its own length).
+__device__ __forceinline__ int stage_chains(int64_t* base, int* len, int64_t state0, int n, int lane) {
+    block_sync<64>();                           // earlier readers of the table are done
+    base[lane] = state0;
+    len[lane] = n;
+    block_sync<64>();
+    int nw = n;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) nw = max(nw, __shfl_xor(nw, d, 64));
+    return nw;
+}
+
 // ---------------- lane-group exchange ----------------
 // Groups of NP <= 64 lanes live in one wavefront and exchange values through
 // DPP (data-parallel primitives: a VALU operand read from another lane, no LDS
