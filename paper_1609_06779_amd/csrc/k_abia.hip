@@ -141,7 +141,8 @@ static_assert(2 * 1 * ST_L * ST_W + ST_L * ST_W <= ABIA_STAGE, "sweep 3's stage 
 
 // One chain (or tree) on one lane; every lane of the wavefront calls it (a
 // lane without a chain with ci.n = 0), since the state stage is loaded by all
-// of them. wsb: this lane's workspace column, field f of link i at
+// of them. Serial chains stage the joint state; trees read it lane by lane
+// (measured: the stage costs the divergent tree sweeps a third more time). wsb: this lane's workspace column, field f of link i at
 // wsb[(i * abia_fields<TREE>() + f) * 64]. NT: model and workspace streamed
 // with non-temporal accesses (see ModelView::at_il). stg, sbase, slen: the
 // wavefront's LDS (ABIA_STAGE values, 64 + 64 entries).
@@ -157,7 +158,11 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, ChainInfo ci, 
     const int n = ci.n;
     const int lane = threadIdx.x & 63;
     auto wsp = [&](int i, int f) -> T* { return &wsb[((size_t)i * abia_fields<TREE>() + f) * 64]; };
-    const int nw = stage_chains(sbase, slen, ci.state0, n, lane);   // the loops run to the longest chain
+    constexpr bool ST = !TREE;                         // the state goes through the LDS stage
+    int nw = n;                                        // loop bound: each lane's own length, or with the
+    if constexpr (ST) nw = stage_chains(sbase, slen, ci.state0, n, lane);   // stage the longest in the wavefront
+    // state entry of array a at link i, read directly (trees)
+    auto at = [&](const T* a, int i) -> T { return a[ci.state0 + i]; };
 
     // sweep 1. The light forward sweeps wait on memory, not on arithmetic: each
     // step starts the loads of the link two ahead, so two links' inputs are in
@@ -166,18 +171,25 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, ChainInfo ci, 
     T a[6] = {T(0), T(0), T(0), -m.g[0], -m.g[1], -m.g[2]};
     StateStage<T, 2> s1{stg, sbase, slen, lane};
     const T* const st1[2] = {q, qd};
-    s1.template start<true>(st1);
-    block_sync<64>();
-    LinkIn<T, false> in0, in1;
-    if (n > 0) in0 = link_in<NT, false>(m, 0, ci.slot, s1.get(0, 0), s1.get(1, 0), wsb);
-    if (n > 1) in1 = link_in<NT, false>(m, 1, ci.slot, s1.get(0, 1), s1.get(1, 1), wsb);
-    for (int i = 0; i < nw; ++i) {
-        s1.template step<true>(st1, i);
+    if constexpr (ST) {
+        s1.template start<true>(st1);
         block_sync<64>();
-        if (i >= n) continue;
+    }
+    auto in1_of = [&](int i) -> LinkIn<T, false> {    // link i's inputs
+        if constexpr (ST) return link_in<NT, false>(m, i, ci.slot, s1.get(0, i), s1.get(1, i), wsb);
+        else return link_in<NT, false>(m, i, ci.slot, at(q, i), at(qd, i), wsb);
+    };
+    LinkIn<T, false> in0, in1;
+    if (n > 0) in0 = in1_of(0);
+    if (n > 1) in1 = in1_of(1);
+    for (int i = 0; i < nw; ++i) {
+        if constexpr (ST) {
+            s1.template step<true>(st1, i);
+            if (i >= n) continue;
+        }
         const LinkIn<T, false> cur = in0;
         in0 = in1;
-        if (i + 2 < n) in1 = link_in<NT, false>(m, i + 2, ci.slot, s1.get(0, i + 2), s1.get(1, i + 2), wsb);
+        if (i + 2 < n) in1 = in1_of(i + 2);
         int32_t code = 0;
         if constexpr (TREE) {
             code = m.template tree_il<NT>(i, ci.slot);
@@ -235,21 +247,32 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, ChainInfo ci, 
     // the state stage runs backward here: position k is link n - 1 - k
     StateStage<T, 3> s2{stg, sbase, slen, lane};
     const T* const st2[3] = {q, qd, tau};
-    block_sync<64>();                                  // sweep 1's reads of the stage are done
-    s2.template start<false>(st2);
-    block_sync<64>();
+    if constexpr (ST) {
+        block_sync<64>();                              // sweep 1's reads of the stage are done
+        s2.template start<false>(st2);
+        block_sync<64>();
+    }
+    auto in2_of = [&](int k) -> LinkIn<T, false> {    // inputs of the link at position k
+        if constexpr (ST) return link_in<NT, false>(m, n - 1 - k, ci.slot, s2.get(0, k), s2.get(1, k), wsb);
+        else return link_in<NT, false>(m, n - 1 - k, ci.slot, at(q, n - 1 - k), at(qd, n - 1 - k), wsb);
+    };
+    auto tau_of = [&](int k) -> T {
+        if constexpr (ST) return s2.get(2, k);
+        else return at(tau, n - 1 - k);
+    };
     Inertia<T> jn;
     LinkIn<T, false> pn;
     T taun = T(0);
     if (n > 0) {
         jn = m.template inertia_il<NT>(n - 1, ci.slot);
-        pn = link_in<NT, false>(m, n - 1, ci.slot, s2.get(0, 0), s2.get(1, 0), wsb);
-        taun = s2.get(2, 0);
+        pn = in2_of(0);
+        taun = tau_of(0);
     }
     for (int k = 0; k < nw; ++k) {
-        s2.template step<false>(st2, k);
-        block_sync<64>();
-        if (k >= n) continue;
+        if constexpr (ST) {
+            s2.template step<false>(st2, k);
+            if (k >= n) continue;
+        }
         const int i = n - 1 - k;
         T f[6], fp[6], pp[6], jh[36];
         const Inertia<T> ji = jn;
@@ -257,8 +280,8 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, ChainInfo ci, 
         const T taui = taun;
         if (i > 0) {
             jn = m.template inertia_il<NT>(i - 1, ci.slot);
-            pn = link_in<NT, false>(m, i - 1, ci.slot, s2.get(0, k + 1), s2.get(1, k + 1), wsb);
-            taun = s2.get(2, k + 1);
+            pn = in2_of(k + 1);
+            taun = tau_of(k + 1);
         }
         if constexpr (TREE) {
 #pragma unroll
@@ -397,19 +420,24 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, ChainInfo ci, 
     const T* const st3[1] = {q};
     OutTile<T, 1> o3{stg + 2 * ST_L * ST_W, sbase, slen, lane};   // qdd of the current tile
     T* const out3[1] = {qdd};
-    block_sync<64>();                                  // sweep 2's reads of the stage are done
-    s3.template start<true>(st3);
-    block_sync<64>();
-    LinkIn<T, true> wn0, wn1;
-    if (n > 0) wn0 = link_in<NT, true>(m, 0, ci.slot, s3.get(0, 0), T(0), wsp(0, 0));
-    if (n > 1) wn1 = link_in<NT, true>(m, 1, ci.slot, s3.get(0, 1), T(0), wsp(1, 0));
-    for (int i = 0; i < nw; ++i) {
-        s3.template step<true>(st3, i);
+    if constexpr (ST) {
+        block_sync<64>();                              // sweep 2's reads of the stage are done
+        s3.template start<true>(st3);
         block_sync<64>();
+    }
+    auto in3_of = [&](int i) -> LinkIn<T, true> {
+        if constexpr (ST) return link_in<NT, true>(m, i, ci.slot, s3.get(0, i), T(0), wsp(i, 0));
+        else return link_in<NT, true>(m, i, ci.slot, at(q, i), T(0), wsp(i, 0));
+    };
+    LinkIn<T, true> wn0, wn1;
+    if (n > 0) wn0 = in3_of(0);
+    if (n > 1) wn1 = in3_of(1);
+    for (int i = 0; i < nw; ++i) {
+        if constexpr (ST) s3.template step<true>(st3, i);
         if (i < n) {
         const LinkIn<T, true> cur = wn0;
         wn0 = wn1;
-        if (i + 2 < n) wn1 = link_in<NT, true>(m, i + 2, ci.slot, s3.get(0, i + 2), T(0), wsp(i + 2, 0));
+        if (i + 2 < n) wn1 = in3_of(i + 2);
         int32_t code = 0;
         if constexpr (TREE) {
             code = m.template tree_il<NT>(i, ci.slot);
@@ -431,8 +459,12 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, ChainInfo ci, 
         t[2] = s;
 #pragma unroll
         for (int c = 0; c < 6; ++c) acc[c] = t[c];
-        o3.put(0, i, x);
-        o.put_aux(b, i, x);                            // qdd may be null when the reverse mode takes it in aux
+        if constexpr (ST) {
+            o3.put(0, i, x);
+            o.put_aux(b, i, x);                        // qdd may be null when the reverse mode takes it in aux
+        } else {
+            o.put(qdd, ci.state0 + i, b, i, x);
+        }
         if constexpr (TREE) {
             if (code & TREE_BRANCH) {
 #pragma unroll
@@ -440,7 +472,7 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, ChainInfo ci, 
             }
         }
         }
-        o3.template flush<true>(out3, i, nw, o.accumulate);
+        if constexpr (ST) o3.template flush<true>(out3, i, nw, o.accumulate);
     }
 }
 
@@ -448,9 +480,9 @@ template <typename T, bool NT, bool TREE>
 __global__ __launch_bounds__(64) void k_abia(ModelView<T> m, ChainMap cm, int nmax, const T* __restrict__ q,
                                              const T* __restrict__ qd, const T* __restrict__ tau,
                                              T* __restrict__ qdd, T* __restrict__ ws, FdOut<T> o) {
-    __shared__ T stg[ABIA_STAGE];
-    __shared__ int64_t sbase[64];
-    __shared__ int slen[64];
+    __shared__ T stg[TREE ? 1 : ABIA_STAGE];           // serial chains only: the state stage
+    __shared__ int64_t sbase[TREE ? 1 : 64];
+    __shared__ int slen[TREE ? 1 : 64];
     const int lane = threadIdx.x;
     const int b = blockIdx.x * 64 + lane;
     ChainInfo ci{0, 0, 0, 0, 0};                      // lanes past the batch take part with no chain
@@ -473,9 +505,9 @@ __global__ __launch_bounds__(64) void k_abia_persistent(ModelView<T> m, ChainMap
                                                         const T* __restrict__ qd, const T* __restrict__ tau,
                                                         T* __restrict__ qdd, T* __restrict__ ws) {
     __shared__ int tile_s;
-    __shared__ T stg[ABIA_STAGE];
-    __shared__ int64_t sbase[64];
-    __shared__ int slen[64];
+    __shared__ T stg[TREE ? 1 : ABIA_STAGE];           // serial chains only: the state stage
+    __shared__ int64_t sbase[TREE ? 1 : 64];
+    __shared__ int slen[TREE ? 1 : 64];
     const int lane = threadIdx.x;
     T* wsb = ws + (size_t)blockIdx.x * nmax * abia_fields<TREE>() * 64 + lane;
     for (;;) {

@@ -351,22 +351,37 @@ template <typename T, int NA> struct StateStage {
     __device__ __forceinline__ T get(int v, int pos) const {
         return s[(((pos / ST_L) & 1) * NA + v) * ST_L * ST_W + (pos % ST_L) * ST_W + lane];
     }
-    // Before the loop: tiles 0 and 1 committed, tile 2 in flight. (The caller
-    // separates the commits from the first reads with block_sync<64>.)
+    // Before the loop: tiles 0 and 1 committed, tile 2 in flight; the three
+    // tiles' loads are issued together. The caller separates the commits from
+    // the first reads (and earlier readers of the LDS from the commits) with
+    // block_sync<64>.
     template <bool FWD> __device__ __forceinline__ void start(const T* const (&a)[NA]) {
+        T r0[NA][ST_L];
         load<FWD>(a, 0);
-        commit(0);
+        for (int v = 0; v < NA; ++v)
+            for (int k = 0; k < ST_L; ++k) r0[v][k] = reg[v][k];
         load<FWD>(a, 1);
+        T* d = s;
+#pragma unroll
+        for (int k = 0; k < ST_L; ++k) {
+            const int c = (k * 64 + lane) / ST_L, j = lane % ST_L;
+#pragma unroll
+            for (int v = 0; v < NA; ++v) d[(v * ST_L + j) * ST_W + c] = r0[v][k];
+        }
         commit(1);
         load<FWD>(a, 2);
     }
     // At position k of the loop (every lane, every k): at the first position of
     // tile t >= 1 the registers (tile t + 1) go to LDS over tile t - 1, whose
     // last entry was read two positions earlier, and tile t + 2 is loaded.
+    // The LDS hand-off is fenced here (block_sync<64>), so the steps in between
+    // carry no fence.
     template <bool FWD> __device__ __forceinline__ void step(const T* const (&a)[NA], int k) {
         if (k > 0 && k % ST_L == 0) {
             const int t = k / ST_L;
+            block_sync<64>();
             commit(t + 1);
+            block_sync<64>();
             load<FWD>(a, t + 2);
         }
     }
