@@ -60,6 +60,11 @@ constexpr int VJP_FIELDS = 25;
 constexpr int VJP_WB = VJP_FIELDS;
 constexpr int VJP_TREE_FIELDS = VJP_FIELDS + 27;
 template <bool TREE> constexpr int vjp_fields() { return TREE ? VJP_TREE_FIELDS : VJP_FIELDS; }
+// LDS of the state stage (launches of serial chains past the last-level
+// cache): sweep B's three inputs (2 slots) and its output tile are the largest
+// (sweep A: two inputs; sweep CE: two inputs, two outputs).
+constexpr int VJP_STAGE = (2 * 3 + 1) * ST_L * ST_W;
+static_assert((2 * 2 + 2) * ST_L * ST_W <= VJP_STAGE, "sweep CE fits");
 
 size_t vjp_workspace_elems(int batch, int nmax, bool tree) {
     size_t blocks = (size_t)(batch + 63) / 64;
@@ -104,18 +109,33 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
                                                const T* __restrict__ gqdd, T* __restrict__ gq,
                                                T* __restrict__ gqd, T* __restrict__ gtau, int accumulate,
                                                int lam_in, T* __restrict__ ws) {
+    // Large launches of serial chains (NT: past the last-level cache) move the
+    // joint state and its adjoints through LDS tiles (StateStage, OutTile),
+    // loaded and stored by all 64 lanes, so lanes past the batch and unsolved
+    // chains take part with no links. Smaller launches, and trees, read and
+    // write them lane by lane: at a few hundred wavefronts the tiles' latency
+    // costs more than their coalescing gains (measured on a 16384 x 32 rollout).
+    constexpr bool ST = NT && !TREE;
+    __shared__ T stg[ST ? VJP_STAGE : 1];
+    __shared__ int64_t sbase[ST ? 64 : 1];
+    __shared__ int slen[ST ? 64 : 1];
     const int lane = threadIdx.x;
     const int b = blockIdx.x * 64 + lane;
-    if (b >= cm.batch) return;
-    const ChainInfo ci = chain_info(m, cm, b);
+    if (!ST && b >= cm.batch) return;
+    ChainInfo ci{0, 0, 0, 0, 0};
+    if (b < cm.batch) ci = chain_info(m, cm, b);
     if (ci.unsolved) {                                 // longer than the workspace is sized for
         fill_unsolved(gq, ci.state0, ci.unsolved, 0, 1);
         fill_unsolved(gqd, ci.state0, ci.unsolved, 0, 1);
         fill_unsolved(gtau, ci.state0, ci.unsolved, 0, 1);
-        return;
+        if (!ST) return;
+        ci.n = 0;
     }
     const int n = ci.n;
     const int sl = ci.slot;
+    int nw = n;                                        // loop bound: each lane's own length, or with the
+    if constexpr (ST) nw = stage_chains(sbase, slen, ci.state0, n, lane);   // stage the longest in the wavefront
+    auto at = [&](const T* a, int i) -> T { return a[ci.state0 + i]; };
     T* wsb = ws + (size_t)blockIdx.x * nmax * vjp_fields<TREE>() * 64 + lane;
     auto w = [&](int i, int f) -> T& { return wsb[((size_t)i * vjp_fields<TREE>() + f) * 64]; };
     // per-link fields stream (NT) when the launch outgrows the last-level cache,
@@ -127,14 +147,24 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
 
     // A: articulated-body inertias and the p recursion with tau_delta := g
     if (!lam_in) {
+        StateStage<T, 2> sa{stg, sbase, slen, lane};     // backward: position k is link n - 1 - k
+        const T* const ina[2] = {gqdd, q};
+        if constexpr (ST) {
+            sa.template start<false>(ina);
+            block_sync<64>();
+        }
         T pc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
         T pi[36];
 #pragma unroll
         for (int c = 0; c < 36; ++c) pi[c] = T(0);
         Pose<T> tn = pose_identity<T>();
         bool carry = false;                            // trees: registers hold link i+1's terms for link i
-        for (int i = n - 1; i >= 0; --i) {
-            const int64_t st = ci.state0 + i;
+        for (int k = 0; k < nw; ++k) {
+            if constexpr (ST) {
+                sa.template step<false>(ina, k);
+                if (k >= n) continue;
+            }
+            const int i = n - 1 - k;
             const int32_t code = code_of(i);
             T jh[36], pp[6];
             inertia_to_mat6(m.template inertia_il<NT>(i, sl), jh);
@@ -169,7 +199,7 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
                 }
             }
             const T dinv = rcp_refined(jh[14]);
-            const T u = gqdd[st] - pp[2];
+            const T u = (ST ? sa.get(0, k) : at(gqdd, i)) - pp[2];
             T h[6];
 #pragma unroll
             for (int c = 0; c < 6; ++c) h[c] = jh[6 * c + 2];
@@ -182,7 +212,7 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
                 for (int c = 0; c < 6; ++c) pi[6 * rr + c] = jh[6 * rr + c] - h[rr] * h[c] * dinv;
 #pragma unroll
             for (int c = 0; c < 6; ++c) pc[c] = pp[c] + h[c] * u * dinv;
-            tn = pose_il<NT>(m, i, sl, q[st]);
+            tn = pose_il<NT>(m, i, sl, ST ? sa.get(1, k) : at(q, i));
             if constexpr (TREE) {
                 // into the parent's frame on every lane; only the record update diverges
                 T x[6], y[36];
@@ -210,6 +240,15 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
     // B (forward): lambda, the force adjoint Fb_i = lambda_i S + A_i Fb_p(i), and
     // the inverse dynamics recursions at the given qdd
     {
+        StateStage<T, 3> sb{stg, sbase, slen, lane};     // forward: position k is link k
+        const T* const inb[3] = {q, qd, qdd ? qdd : q};  // without qdd the third array is not used
+        OutTile<T, 1> ob{stg + 2 * 3 * ST_L * ST_W, sbase, slen, lane};
+        T* const outb[1] = {lam_in ? nullptr : gtau};
+        if constexpr (ST) {
+            block_sync<64>();                          // sweep A's reads of the stage are done
+            sb.template start<true>(inb);
+            block_sync<64>();
+        }
         T acc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
         T fb[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
         T v[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
@@ -223,14 +262,13 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
         };
         auto load = [&](int i) {
             In r;
-            const int64_t st = ci.state0 + i;
 #pragma unroll
             for (int k = 0; k < 4; ++k) r.qt[k] = m.template at_il<NT>(IL_QUAT + k, i, sl);
 #pragma unroll
             for (int k = 0; k < 3; ++k) r.p[k] = m.template at_il<NT>(IL_POS + k, i, sl);
-            r.q = q[st];
-            r.qd = qd[st];
-            r.qdd = qdd ? qdd[st] : ldw(i, VJP_A);   // read before this sweep overwrites it
+            r.q = ST ? sb.get(0, i) : at(q, i);
+            r.qd = ST ? sb.get(1, i) : at(qd, i);
+            r.qdd = qdd ? (ST ? sb.get(2, i) : at(qdd, i)) : ldw(i, VJP_A);   // read before this sweep overwrites it
             r.lam = ldw(i, VJP_UD);
 #pragma unroll
             for (int c = 0; c < 6; ++c) r.hd[c] = lam_in ? T(0) : ldw(i, VJP_HD + c);
@@ -241,8 +279,9 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
         // extra registers cost more than the overlap gains)
         In nx;
         if (!TREE && n > 0) nx = load(0);
-        for (int i = 0; i < n; ++i) {
-            const int64_t st = ci.state0 + i;
+        for (int i = 0; i < nw; ++i) {
+            if constexpr (ST) sb.template step<true>(inb, i);
+            if (i < n) {
             const int32_t code = code_of(i);
             const In cur = TREE ? load(i) : nx;
             if (!TREE && i + 1 < n) nx = load(i + 1);
@@ -271,7 +310,8 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
                 t[2] += lam;
 #pragma unroll
                 for (int c = 0; c < 6; ++c) acc[c] = t[c];
-                gtau[st] = accumulate ? gtau[st] + lam : lam;
+                if constexpr (ST) ob.put(0, i, lam);
+                else gtau[ci.state0 + i] = accumulate ? gtau[ci.state0 + i] + lam : lam;
             }
             ad_inv_apply(tl, fb, t);
             t[2] += lam;
@@ -306,12 +346,23 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
                 stw(i, VJP_A + c, a[c]);
                 stw(i, VJP_F + c, f[c]);
             }
+            }
+            if constexpr (ST) ob.template flush<true>(outb, i, nw, accumulate);
         }
     }
     // CE (backward): the force recursion F_i = f_i + sum over children c of A_c^T F_c,
     // the force term of q_bar, and the adjoints of the velocity and acceleration
     // recursions, all in one sweep
     {
+        StateStage<T, 2> sc{stg, sbase, slen, lane};     // backward: position k is link n - 1 - k
+        const T* const inc[2] = {q, qd};
+        OutTile<T, 2> oc{stg + 2 * 2 * ST_L * ST_W, sbase, slen, lane};
+        T* const outc[2] = {gq, gqd};
+        if constexpr (ST) {
+            block_sync<64>();                          // sweep B's reads of the stage are done
+            sc.template start<false>(inc);
+            block_sync<64>();
+        }
         T fc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};   // link i+1's F, ab, Vb for link i
         T ab[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
         T vb[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
@@ -325,7 +376,6 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
         };
         auto load = [&](int i) {
             In r;
-            const int64_t st = ci.state0 + i;
             r.j = m.template inertia_il<NT>(i, sl);
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
@@ -338,14 +388,16 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
             for (int k = 0; k < 4; ++k) r.qt[k] = m.template at_il<NT>(IL_QUAT + k, i, sl);
 #pragma unroll
             for (int k = 0; k < 3; ++k) r.p[k] = m.template at_il<NT>(IL_POS + k, i, sl);
-            r.q = q[st];
-            r.qd = qd[st];
+            r.q = ST ? sc.get(0, n - 1 - i) : at(q, i);
+            r.qd = ST ? sc.get(1, n - 1 - i) : at(qd, i);
             return r;
         };
         In nx;
         if (!TREE && n > 0) nx = load(n - 1);
-        for (int i = n - 1; i >= 0; --i) {
-            const int64_t st = ci.state0 + i;
+        for (int k = 0; k < nw; ++k) {
+            if constexpr (ST) sc.template step<false>(inc, k);
+            if (k < n) {
+            const int i = n - 1 - k;
             const int32_t code = code_of(i);
             const In cur = TREE ? load(i) : nx;
             if (!TREE && i > 0) nx = load(i - 1);
@@ -429,8 +481,14 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
             ad_z(am, za);
 #pragma unroll
             for (int c = 0; c < 6; ++c) gq_id -= vb[c] * zv[c] + ab[c] * za[c];
-            gq[st] = accumulate ? gq[st] - gq_id : -gq_id;
-            gqd[st] = accumulate ? gqd[st] - gqd_id : -gqd_id;
+            if constexpr (ST) {
+                oc.put(0, k, -gq_id);                // added as -gq_id when accumulating
+                oc.put(1, k, -gqd_id);
+            } else {
+                const int64_t st = ci.state0 + i;
+                gq[st] = accumulate ? gq[st] - gq_id : -gq_id;
+                gqd[st] = accumulate ? gqd[st] - gqd_id : -gqd_id;
+            }
 #pragma unroll
             for (int c = 0; c < 6; ++c) fc[c] = f[c];
             if constexpr (TREE) {
@@ -456,6 +514,8 @@ __global__ __launch_bounds__(64) void k_fd_vjp(ModelView<T> m, ChainMap cm, int 
                     }
                 }
             }
+            }
+            if constexpr (ST) oc.template flush<false>(outc, k, nw, accumulate);
         }
     }
 }

@@ -210,6 +210,42 @@ def test_vjp_full_size_streaming_sampled(fdm, dev):
     assert np.all(np.abs(lhs - rhs) <= CAP["f64"] * scale), (np.abs(lhs - rhs) / scale).max()
 
 
+def test_vjp_large_launch_matches_smaller_launches_every_chain(fdm, dev):
+    """A launch of 65536 chains of 64 links outgrows the last-level cache and moves
+    the joint state and its adjoints through LDS tiles; launches of 16384 of the
+    same chains (by robot id) do not. Every entry of both agrees, for the plain
+    and the accumulating form, so no chain of a tile is misplaced."""
+    batch, n, part = 65536, 64, 16384
+    lengths = np.full(batch, n, np.int32)
+    rb = synth.make_robots(lengths, cfg=2)
+    q, qd, tau = synth.make_state(lengths, cfg=2)
+    model = fdm.Model(rb, "f64", device=dev)
+    tq, tqd, ttau = _t(q, dev), _t(qd, dev), _t(tau, dev)
+    qdd = model.forward(tq, tqd, ttau, batch=batch, algo="abia")
+    g = _t(np.random.default_rng(23).standard_normal(len(q)), dev)
+    big = [x.cpu().numpy() for x in model.backward(tq, tqd, qdd, g, batch=batch)]
+    base = [_t(np.random.default_rng(24 + k).standard_normal(len(q)), dev) for k in range(3)]
+    acc = [x.clone() for x in base]
+    model.backward(tq, tqd, qdd, g, batch=batch, grad_q=acc[0], grad_qd=acc[1], grad_tau=acc[2], accumulate=True)
+    small = [np.empty(len(q)) for _ in range(3)]
+    small_acc = [x.clone() for x in base]
+    for s0 in range(0, batch, part):
+        sl = slice(s0 * n, (s0 + part) * n)
+        rid = torch.arange(s0, s0 + part, dtype=torch.int32, device=dev)
+        outs = model.backward(tq[sl], tqd[sl], qdd[sl], g[sl], batch=part, robot_id=rid)
+        for k in range(3):
+            small[k][sl] = outs[k].cpu().numpy()
+        model.backward(tq[sl], tqd[sl], qdd[sl], g[sl], batch=part, robot_id=rid, grad_q=small_acc[0][sl],
+                       grad_qd=small_acc[1][sl], grad_tau=small_acc[2][sl], accumulate=True)
+    for k, name in enumerate(("q_bar", "qd_bar", "tau_bar")):
+        a, b = big[k].reshape(batch, n), small[k].reshape(batch, n)
+        scale = 1 + np.abs(b).max(axis=1, keepdims=True)
+        assert np.all(np.abs(a - b) <= 1e-11 * scale), (name, np.abs(a - b).max())
+        a, b = acc[k].cpu().numpy().reshape(batch, n), small_acc[k].cpu().numpy().reshape(batch, n)
+        scale = 1 + np.abs(b).max(axis=1, keepdims=True)
+        assert np.all(np.abs(a - b) <= 1e-11 * scale), (name, "accumulate", np.abs(a - b).max())
+
+
 @pytest.mark.parametrize("tree", [False, True])
 @pytest.mark.parametrize("n", [5, 16, 32])
 def test_vjp_fp32(fdm, dev, n, tree):
