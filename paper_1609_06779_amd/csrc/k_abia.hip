@@ -139,14 +139,25 @@ template <typename T> __device__ __forceinline__ void congruence_to_parent(const
 constexpr int ABIA_STAGE = 2 * 3 * ST_L * ST_W;
 static_assert(2 * 1 * ST_L * ST_W + ST_L * ST_W <= ABIA_STAGE, "sweep 3's stage and output tile fit");
 
+// Launches of serial chains with at least ABIA_STAGE_CHAINS chains, the
+// longest of at least ABIA_STAGE_LINKS links, move the joint state through the
+// LDS stage; smaller launches and trees read and write it lane by lane.
+// Measured on MI355X: the stage takes 65536 x 64 from 0.422 to 0.332 ms, but
+// costs one robot or a few hundred wavefronts a fifth more time, and the
+// divergent tree sweeps a third. Plain and persistent launches of one batch
+// take the same path, so their results stay equal bit for bit.
+constexpr int ABIA_STAGE_CHAINS = 65536, ABIA_STAGE_LINKS = 16;
+inline bool abia_stages(bool tree, int batch, int nmax) {
+    return !tree && batch >= ABIA_STAGE_CHAINS && nmax >= ABIA_STAGE_LINKS;
+}
+
 // One chain (or tree) on one lane; every lane of the wavefront calls it (a
-// lane without a chain with ci.n = 0), since the state stage is loaded by all
-// of them. Serial chains stage the joint state; trees read it lane by lane
-// (measured: the stage costs the divergent tree sweeps a third more time). wsb: this lane's workspace column, field f of link i at
+// lane without a chain with ci.n = 0), since with ST the state stage is
+// loaded by all of them. wsb: this lane's workspace column, field f of link i at
 // wsb[(i * abia_fields<TREE>() + f) * 64]. NT: model and workspace streamed
 // with non-temporal accesses (see ModelView::at_il). stg, sbase, slen: the
 // wavefront's LDS (ABIA_STAGE values, 64 + 64 entries).
-template <bool NT, bool TREE, typename T>
+template <bool NT, bool TREE, bool ST, typename T>
 __device__ __forceinline__ void abia_chain(const ModelView<T>& m, ChainInfo ci, const T* __restrict__ q,
                                            const T* __restrict__ qd, const T* __restrict__ tau,
                                            T* __restrict__ qdd, T* __restrict__ wsb, int b, const FdOut<T>& o,
@@ -158,7 +169,7 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, ChainInfo ci, 
     const int n = ci.n;
     const int lane = threadIdx.x & 63;
     auto wsp = [&](int i, int f) -> T* { return &wsb[((size_t)i * abia_fields<TREE>() + f) * 64]; };
-    constexpr bool ST = !TREE;                         // the state goes through the LDS stage
+    static_assert(!(ST && TREE), "trees read the state lane by lane");
     int nw = n;                                        // loop bound: each lane's own length, or with the
     if constexpr (ST) nw = stage_chains(sbase, slen, ci.state0, n, lane);   // stage the longest in the wavefront
     // state entry of array a at link i, read directly (trees)
@@ -476,20 +487,21 @@ __device__ __forceinline__ void abia_chain(const ModelView<T>& m, ChainInfo ci, 
     }
 }
 
-template <typename T, bool NT, bool TREE>
+template <typename T, bool NT, bool TREE, bool ST>
 __global__ __launch_bounds__(64) void k_abia(ModelView<T> m, ChainMap cm, int nmax, const T* __restrict__ q,
                                              const T* __restrict__ qd, const T* __restrict__ tau,
                                              T* __restrict__ qdd, T* __restrict__ ws, FdOut<T> o) {
-    __shared__ T stg[TREE ? 1 : ABIA_STAGE];           // serial chains only: the state stage
-    __shared__ int64_t sbase[TREE ? 1 : 64];
-    __shared__ int slen[TREE ? 1 : 64];
+    __shared__ T stg[ST ? ABIA_STAGE : 1];             // the state stage
+    __shared__ int64_t sbase[ST ? 64 : 1];
+    __shared__ int slen[ST ? 64 : 1];
     const int lane = threadIdx.x;
     const int b = blockIdx.x * 64 + lane;
     ChainInfo ci{0, 0, 0, 0, 0};                      // lanes past the batch take part with no chain
     if (b < cm.batch) ci = chain_info(m, cm, b);
     // workspace: [block][link][field][lane]
-    abia_chain<NT, TREE>(m, ci, q, qd, tau, qdd, ws + (size_t)blockIdx.x * nmax * abia_fields<TREE>() * 64 + lane,
-                         b, o, stg, sbase, slen);
+    abia_chain<NT, TREE, ST>(m, ci, q, qd, tau, qdd,
+                             ws + (size_t)blockIdx.x * nmax * abia_fields<TREE>() * 64 + lane, b, o, stg, sbase,
+                             slen);
 }
 
 // Persistent form for ragged batches: each wavefront takes 64-entry tiles of
@@ -498,16 +510,16 @@ __global__ __launch_bounds__(64) void k_abia(ModelView<T> m, ChainMap cm, int nm
 // lengths and the longest tiles go first. Entries at or past the batch are
 // skipped. Every wavefront leaves once a tile index runs past the list, so
 // the grid always drains.
-template <typename T, bool NT, bool TREE>
+template <typename T, bool NT, bool TREE, bool ST>
 __global__ __launch_bounds__(64) void k_abia_persistent(ModelView<T> m, ChainMap cm, int nmax,
                                                         const int32_t* __restrict__ order, int32_t count,
                                                         int32_t* counter, const T* __restrict__ q,
                                                         const T* __restrict__ qd, const T* __restrict__ tau,
                                                         T* __restrict__ qdd, T* __restrict__ ws) {
     __shared__ int tile_s;
-    __shared__ T stg[TREE ? 1 : ABIA_STAGE];           // serial chains only: the state stage
-    __shared__ int64_t sbase[TREE ? 1 : 64];
-    __shared__ int slen[TREE ? 1 : 64];
+    __shared__ T stg[ST ? ABIA_STAGE : 1];             // the state stage
+    __shared__ int64_t sbase[ST ? 64 : 1];
+    __shared__ int slen[ST ? 64 : 1];
     const int lane = threadIdx.x;
     T* wsb = ws + (size_t)blockIdx.x * nmax * abia_fields<TREE>() * 64 + lane;
     for (;;) {
@@ -520,7 +532,7 @@ __global__ __launch_bounds__(64) void k_abia_persistent(ModelView<T> m, ChainMap
         const int b = k < count ? (order ? order[k] : k) : cm.batch;
         ChainInfo ci{0, 0, 0, 0, 0};                  // entries past the batch: no chain, but the lane takes part
         if (b < cm.batch) ci = chain_info(m, cm, b);
-        abia_chain<NT, TREE>(m, ci, q, qd, tau, qdd, wsb, b, FdOut<T>{}, stg, sbase, slen);
+        abia_chain<NT, TREE, ST>(m, ci, q, qd, tau, qdd, wsb, b, FdOut<T>{}, stg, sbase, slen);
     }
 }
 
@@ -602,15 +614,18 @@ hipError_t launch_abia_persistent(const ModelView<T>& m, const ChainMap& cm, int
         tiles = slot_robot;
         count = m.num_robots;
     }
-#define FDK_ABIA_PERSISTENT(NT, TREE)                                                                   \
-    hipLaunchKernelGGL((k_abia_persistent<T, NT, TREE>), dim3(grid), dim3(64), 0, st, m, cm, nmax, tiles, count, \
-                       counter, q, qd, tau, qdd, ws)
+#define FDK_ABIA_PERSISTENT(NT, TREE, ST)                                                                   \
+    hipLaunchKernelGGL((k_abia_persistent<T, NT, TREE, ST>), dim3(grid), dim3(64), 0, st, m, cm, nmax, tiles, \
+                       count, counter, q, qd, tau, qdd, ws)
     if (m.tree) {
-        if (stream_model) FDK_ABIA_PERSISTENT(true, true);
-        else FDK_ABIA_PERSISTENT(false, true);
+        if (stream_model) FDK_ABIA_PERSISTENT(true, true, false);
+        else FDK_ABIA_PERSISTENT(false, true, false);
+    } else if (abia_stages(false, cm.batch, nmax)) {
+        if (stream_model) FDK_ABIA_PERSISTENT(true, false, true);
+        else FDK_ABIA_PERSISTENT(false, false, true);
     } else {
-        if (stream_model) FDK_ABIA_PERSISTENT(true, false);
-        else FDK_ABIA_PERSISTENT(false, false);
+        if (stream_model) FDK_ABIA_PERSISTENT(true, false, false);
+        else FDK_ABIA_PERSISTENT(false, false, false);
     }
 #undef FDK_ABIA_PERSISTENT
     return hipGetLastError();
@@ -621,14 +636,17 @@ hipError_t launch_abia(const ModelView<T>& m, const ChainMap& cm, int nmax, cons
                        T* qdd, T* ws, bool stream_model, const FdOut<T>& o, hipStream_t st) {
     if (cm.batch <= 0) return hipSuccess;
     const dim3 grid((cm.batch + 63) / 64);
-#define FDK_ABIA(NT, TREE) \
-    hipLaunchKernelGGL((k_abia<T, NT, TREE>), grid, dim3(64), 0, st, m, cm, nmax, q, qd, tau, qdd, ws, o)
+#define FDK_ABIA(NT, TREE, ST) \
+    hipLaunchKernelGGL((k_abia<T, NT, TREE, ST>), grid, dim3(64), 0, st, m, cm, nmax, q, qd, tau, qdd, ws, o)
     if (m.tree) {
-        if (stream_model) FDK_ABIA(true, true);
-        else FDK_ABIA(false, true);
+        if (stream_model) FDK_ABIA(true, true, false);
+        else FDK_ABIA(false, true, false);
+    } else if (abia_stages(false, cm.batch, nmax)) {
+        if (stream_model) FDK_ABIA(true, false, true);
+        else FDK_ABIA(false, false, true);
     } else {
-        if (stream_model) FDK_ABIA(true, false);
-        else FDK_ABIA(false, false);
+        if (stream_model) FDK_ABIA(true, false, false);
+        else FDK_ABIA(false, false, false);
     }
 #undef FDK_ABIA
     return hipGetLastError();
