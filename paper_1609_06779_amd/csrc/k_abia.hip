@@ -140,15 +140,17 @@ constexpr int ABIA_STAGE = 2 * 3 * ST_L * ST_W;
 static_assert(2 * 1 * ST_L * ST_W + ST_L * ST_W <= ABIA_STAGE, "sweep 3's stage and output tile fit");
 
 // Launches of serial chains with at least ABIA_STAGE_CHAINS chains, the
-// longest of at least ABIA_STAGE_LINKS links, move the joint state through the
-// LDS stage; smaller launches and trees read and write it lane by lane.
-// Measured on MI355X: the stage takes 65536 x 64 from 0.422 to 0.332 ms, but
-// costs one robot or a few hundred wavefronts a fifth more time, and the
-// divergent tree sweeps a third. Plain and persistent launches of one batch
-// take the same path, so their results stay equal bit for bit.
-constexpr int ABIA_STAGE_CHAINS = 65536, ABIA_STAGE_LINKS = 16;
-inline bool abia_stages(bool tree, int batch, int nmax) {
-    return !tree && batch >= ABIA_STAGE_CHAINS && nmax >= ABIA_STAGE_LINKS;
+// longest of at least 16 (FP64) or 32 (FP32) links, move the joint state
+// through the LDS stage; smaller launches and trees read and write it lane by
+// lane. Measured on MI355X: the stage takes 65536 x 64 FP64 from 0.422 to
+// 0.332 ms and 65536 x 16 from 0.091 to 0.074 ms, but costs one robot or a few
+// hundred wavefronts a fifth more time, the divergent tree sweeps a third,
+// and FP32 chains of 16 links a tenth (32 links break even). Plain and
+// persistent launches of one batch take the same path, so their results stay
+// equal bit for bit.
+constexpr int ABIA_STAGE_CHAINS = 65536;
+template <typename T> bool abia_stages(bool tree, int batch, int nmax) {
+    return !tree && batch >= ABIA_STAGE_CHAINS && nmax >= (sizeof(T) == 8 ? 16 : 32);
 }
 
 // One chain (or tree) on one lane; every lane of the wavefront calls it (a
@@ -620,7 +622,7 @@ hipError_t launch_abia_persistent(const ModelView<T>& m, const ChainMap& cm, int
     if (m.tree) {
         if (stream_model) FDK_ABIA_PERSISTENT(true, true, false);
         else FDK_ABIA_PERSISTENT(false, true, false);
-    } else if (abia_stages(false, cm.batch, nmax)) {
+    } else if (abia_stages<T>(false, cm.batch, nmax)) {
         if (stream_model) FDK_ABIA_PERSISTENT(true, false, true);
         else FDK_ABIA_PERSISTENT(false, false, true);
     } else {
@@ -641,7 +643,7 @@ hipError_t launch_abia(const ModelView<T>& m, const ChainMap& cm, int nmax, cons
     if (m.tree) {
         if (stream_model) FDK_ABIA(true, true, false);
         else FDK_ABIA(false, true, false);
-    } else if (abia_stages(false, cm.batch, nmax)) {
+    } else if (abia_stages<T>(false, cm.batch, nmax)) {
         if (stream_model) FDK_ABIA(true, false, true);
         else FDK_ABIA(false, false, true);
     } else {
