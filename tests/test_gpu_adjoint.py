@@ -210,11 +210,13 @@ def test_vjp_full_size_streaming_sampled(fdm, dev):
     assert np.all(np.abs(lhs - rhs) <= CAP["f64"] * scale), (np.abs(lhs - rhs) / scale).max()
 
 
-def test_vjp_large_launch_matches_smaller_launches_every_chain(fdm, dev):
+@pytest.mark.parametrize("algo", ["abia", "jsiia"])
+def test_vjp_large_launch_matches_smaller_launches_every_chain(fdm, dev, algo):
     """A launch of 65536 chains of 64 links outgrows the last-level cache and moves
     the joint state and its adjoints through LDS tiles; launches of 16384 of the
     same chains (by robot id) do not. Every entry of both agrees, for the plain
-    and the accumulating form, so no chain of a tile is misplaced."""
+    and the accumulating form, so no chain of a tile is misplaced. With JSIIA's
+    lambda the reverse-mode kernel skips its own M^-1 sweep."""
     batch, n, part = 65536, 64, 16384
     lengths = np.full(batch, n, np.int32)
     rb = synth.make_robots(lengths, cfg=2)
@@ -223,19 +225,20 @@ def test_vjp_large_launch_matches_smaller_launches_every_chain(fdm, dev):
     tq, tqd, ttau = _t(q, dev), _t(qd, dev), _t(tau, dev)
     qdd = model.forward(tq, tqd, ttau, batch=batch, algo="abia")
     g = _t(np.random.default_rng(23).standard_normal(len(q)), dev)
-    big = [x.cpu().numpy() for x in model.backward(tq, tqd, qdd, g, batch=batch)]
+    big = [x.cpu().numpy() for x in model.backward(tq, tqd, qdd, g, batch=batch, algo=algo)]
     base = [_t(np.random.default_rng(24 + k).standard_normal(len(q)), dev) for k in range(3)]
     acc = [x.clone() for x in base]
-    model.backward(tq, tqd, qdd, g, batch=batch, grad_q=acc[0], grad_qd=acc[1], grad_tau=acc[2], accumulate=True)
+    model.backward(tq, tqd, qdd, g, batch=batch, algo=algo, grad_q=acc[0], grad_qd=acc[1], grad_tau=acc[2],
+                   accumulate=True)
     small = [np.empty(len(q)) for _ in range(3)]
     small_acc = [x.clone() for x in base]
     for s0 in range(0, batch, part):
         sl = slice(s0 * n, (s0 + part) * n)
         rid = torch.arange(s0, s0 + part, dtype=torch.int32, device=dev)
-        outs = model.backward(tq[sl], tqd[sl], qdd[sl], g[sl], batch=part, robot_id=rid)
+        outs = model.backward(tq[sl], tqd[sl], qdd[sl], g[sl], batch=part, algo=algo, robot_id=rid)
         for k in range(3):
             small[k][sl] = outs[k].cpu().numpy()
-        model.backward(tq[sl], tqd[sl], qdd[sl], g[sl], batch=part, robot_id=rid, grad_q=small_acc[0][sl],
+        model.backward(tq[sl], tqd[sl], qdd[sl], g[sl], batch=part, algo=algo, robot_id=rid, grad_q=small_acc[0][sl],
                        grad_qd=small_acc[1][sl], grad_tau=small_acc[2][sl], accumulate=True)
     for k, name in enumerate(("q_bar", "qd_bar", "tau_bar")):
         a, b = big[k].reshape(batch, n), small[k].reshape(batch, n)
